@@ -17,10 +17,14 @@ polynomial method, a reading recorded with the build's design notes:
   theta = arccos t, t = (omega - c)/d  (the integral of the damped Chebyshev series).
 
 Shift placement (reading of eq. cdos_root, whose printed form mixes a spectral
-point with a count): roots omega_j of Phi(omega) = j K, K = n_e / n_s,
-j = 0..n_s over [a, b]; sigma_j = (omega_{j-1} + omega_j) / 2 (the paper's
-"midpoint", printed as (u_j - l_j)/2).  The top boundary of the wanted window is
-omega_top = root of Phi = n_e + top_margin * K.  Roots by bisection.
+point with a count): the region to slice is [a, omega_top] with
+omega_top = root of Phi = n_e + top_margin * n_e / n_s (the lowest n_e plus a
+margin, because the estimate is only accurate to the kernel resolution); its
+equal-count points omega_j solve Phi(omega) = j K', K' = Phi(omega_top) / n_s,
+j = 0..n_s, and sigma_j = (omega_{j-1} + omega_j) / 2 is the midpoint of the
+j-th interval (the paper's "midpoint", printed as (u_j - l_j)/2).  The top slice
+[sigma_ns, omega_top) is then half an interval wide, like the bottom one.
+Roots by bisection.
 """
 from __future__ import annotations
 
@@ -136,17 +140,19 @@ def cdos_root(target, mu, g, a, b, n, rtol=1e-12):
     return 0.5 * (lo + hi)
 
 
-def place_shifts(mu, a, b, n, n_e, n_s, top_margin=1.0):
+def place_shifts(mu, a, b, n, n_e, n_s, top_margin=2.0):
     """Equal-count roots and interval midpoints; returns (sigmas, omegas, omega_top)."""
     g = jackson(mu.size)
     K = n_e / n_s
-    omegas = [a] + [cdos_root(j * K, mu, g, a, b, n) for j in range(1, n_s + 1)]
+    top_count = n_e + top_margin * K
+    top = cdos_root(top_count, mu, g, a, b, n)
+    Kp = top_count / n_s
+    omegas = [a] + [cdos_root(j * Kp, mu, g, a, b, n) for j in range(1, n_s + 1)]
     sig = np.array([0.5 * (omegas[j - 1] + omegas[j]) for j in range(1, n_s + 1)])
-    top = cdos_root(n_e + top_margin * K, mu, g, a, b, n)
     return sig, np.array(omegas), top
 
 
-def plan(A, B, n_e, n_s, M=64, nv=20, seed=0, top_margin=1.0):
+def plan(A, B, n_e, n_s, M=64, nv=20, seed=0, top_margin=2.0):
     """Full KPM planner: bounds, moments, roots, midpoints."""
     op = Operator(A, B)
     a, b = lanczos_bounds(op, seed)

@@ -96,8 +96,10 @@ def test_place_shifts_equal_counts_and_midpoints():
     pl = kpm.plan(P.A, P.B, 60, 6, M=64, nv=10, seed=0)
     g = kpm.jackson(64)
     om = pl["omegas"]
+    top_count = 60 + 2.0 * 10.0
+    assert kpm.cdos(pl["omega_top"], pl["mu"], g, pl["a"], pl["b"], 300) == pytest.approx(top_count, abs=1e-6)
     for j in range(1, 7):
-        assert kpm.cdos(om[j], pl["mu"], g, pl["a"], pl["b"], 300) == pytest.approx(10.0 * j, abs=1e-6)
+        assert kpm.cdos(om[j], pl["mu"], g, pl["a"], pl["b"], 300) == pytest.approx(top_count * j / 6, abs=1e-6)
+    assert om[-1] == pytest.approx(pl["omega_top"], abs=1e-9)
     assert np.allclose(pl["sigmas"], 0.5 * (om[:-1] + om[1:]), rtol=0, atol=1e-15)
     assert np.all(np.diff(pl["sigmas"]) > 0)
-    assert pl["omega_top"] > om[-1]
