@@ -6,8 +6,9 @@ members, repeat.  The initial centroids are the previous shifts; after a DOS
 placement the paper seeds with k-means++ (first centre uniform, later centres
 drawn with probability proportional to the squared distance to the nearest
 chosen centre).  Readings: assignment ties go to the lower centroid, an empty
-cluster keeps its centroid, iteration stops when no assignment changes or after
-300 sweeps; the draws come from SplitMix64 (uniform u in [0,1) per draw, stream
+cluster keeps its centroid, a centroid is the left-to-right sum of its members in
+index order divided by their number, iteration stops when no assignment changes
+or after 300 sweeps; the draws come from SplitMix64 (uniform u in [0,1) per draw, stream
 index = draw number) so that every process seeding with the same value agrees.
 """
 from __future__ import annotations
@@ -33,9 +34,12 @@ def lloyd(x, c0, max_iter=300):
             break
         lab = new
         for j in range(c.size):
-            m = lab == j
-            if m.any():
-                c[j] = np.sum(x[m]) / m.sum()
+            members = x[lab == j]
+            if members.size:
+                total = 0.0
+                for v in members:          # left-to-right sum in index order
+                    total += float(v)
+                c[j] = total / members.size
     return c, lab
 
 
@@ -49,7 +53,9 @@ def kmeanspp_init(x, k, seed):
     centres = [x[min(int(u * n), n - 1)]]
     d2 = (x - centres[0]) ** 2
     while len(centres) < k:
-        total = float(np.sum(d2))
+        total = 0.0
+        for v in d2:                       # left-to-right sum in index order
+            total += float(v)
         u = prng.uniform(s, draw, 1)[0]
         draw += 1
         if total == 0.0:
