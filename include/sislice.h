@@ -1,0 +1,210 @@
+/*
+ * sislice.h -- C ABI of an MI355X (gfx950) shift-invert spectrum-slicing
+ * eigensolver for symmetric-definite pencils (A, B), after
+ * "SISLICE: shift-invert spectrum slicing for the SCF eigenvalue problem"
+ * (arXiv:1908.06043).
+ *
+ * Problem (Section 1, eq. seq_gep): A X = B X Lambda with A symmetric and B
+ * symmetric positive definite; the n_e wanted eigenpairs are the lowest ones.
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are FP64, column-major, leading dimension >= n.  Symmetric inputs
+ *     (A, B) are read from their LOWER triangle only and are never written.
+ *   - "device" pointers are HIP device memory on the handle's device; "host"
+ *     pointers are ordinary CPU memory.  The caller owns every buffer it passes;
+ *     the library never frees caller memory.  Workspace belongs to the handle.
+ *   - Work is ordered on the handle's stream.  Entry points that return host
+ *     results (inertia, reports, planned shifts) synchronise that stream;
+ *     sislice_ldlt_solve is asynchronous.
+ *   - All arithmetic is FP64; the inertia is an exact integer count.
+ *   - Errors: negative status = usage/runtime error, positive = numerical
+ *     outcome.  No exception crosses the ABI.  Calls on one handle must not
+ *     overlap (a handle is not thread-safe); separate handles are independent.
+ */
+#ifndef SISLICE_H
+#define SISLICE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SISLICE_OK = 0,
+  SISLICE_ERR_ARG = -1,        /* invalid argument (size, pointer, option)              */
+  SISLICE_ERR_HIP = -2,        /* a HIP runtime call failed                             */
+  SISLICE_ERR_ALLOC = -3,      /* device or host allocation failed                      */
+  SISLICE_ERR_NO_DEVICE = -4,  /* no usable gfx950 device                               */
+  SISLICE_SINGULAR_SHIFT = 1,  /* exact zero pivot: a shift is an eigenvalue (Sec. 2.1
+                                  assumes this never happens)                          */
+  SISLICE_NOT_CONVERGED = 2,   /* residual tolerance not met within the iteration cap   */
+  SISLICE_MISSING_EIGS = 3     /* a slice holds more eigenvalues than validated
+                                  candidates (Sec. 2.2, second case), or fewer than n_e
+                                  eigenvalues lie below the top boundary               */
+} sislice_status;
+
+typedef struct sislice_handle sislice_handle;
+
+/* Options of the full solve and of the planner.  Fill with sislice_default_opts. */
+typedef struct {
+  int32_t block;         /* Lanczos block size b (8)                                   */
+  int32_t max_basis;     /* active Lanczos basis cap, multiple of block, <= 112 (112)   */
+  int32_t max_cycles;    /* restart cycles per probe before NOT_CONVERGED (40)           */
+  int32_t kpm_moments;   /* Chebyshev moments of the DOS estimate (64)                   */
+  int32_t kpm_vectors;   /* Rademacher probe vectors (20)                                */
+  int32_t bounds_steps;  /* Lanczos steps of the spectral-bounds estimate (30)           */
+  int32_t nb;            /* factorization panel width (0 = library default)             */
+  int32_t reserved_i;    /* must be 0                                                    */
+  double tol;            /* residual ||Ax - lambda Bx|| / (||A||_2 ||x||) target (1e-10) */
+  double top_margin;     /* top boundary at the CDOS root of n_e + top_margin*n_e/n_s (2) */
+  uint64_t seed;         /* SplitMix64 seed of every random draw (0)                     */
+} sislice_opts;
+
+/* Per-solve report, host memory owned by the caller.  Array members are optional
+ * caller arrays (may be NULL) of the stated length. */
+typedef struct {
+  int64_t n_shifts;        /* shifts used (n_s)                                        */
+  int64_t n_validated;     /* validated eigenpairs below the top boundary              */
+  int64_t n_converged;     /* of the returned n_e, how many meet tol                   */
+  int64_t nu_top;          /* inertia count at the top boundary                        */
+  double omega_top;        /* top boundary used                                        */
+  double anorm;            /* ||A||_2 estimate used to normalise residuals             */
+  int32_t cycles_max;      /* largest number of Lanczos restart cycles of any probe    */
+  int32_t block_steps;     /* block Lanczos steps summed over probes                   */
+  double t_factor_ms;      /* shift-form + LDL^T + inertia of every shift and boundary */
+  double t_lanczos_ms;     /* block Lanczos incl. restarts                             */
+  double t_rr_ms;          /* explicit Rayleigh-Ritz and residuals                     */
+  double t_host_ms;        /* host validation                                          */
+  double t_total_ms;
+  double flops_factor;     /* n^3/3 per factorization, summed                          */
+  int64_t *nu;             /* [n_shifts] inertia nu(sigma_j) = #{lambda < sigma_j}      */
+  int32_t *slice_case;     /* [n_shifts+1] 0 equal counts, 1 missing, 2 trimmed        */
+  int32_t *slice_exact;    /* [n_shifts+1] exact counts from inertia                   */
+  int32_t *slice_cand;     /* [n_shifts+1] validation candidates                       */
+} sislice_report;
+
+void sislice_default_opts(sislice_opts *opts);
+const char *sislice_status_string(sislice_status s);
+
+/* Create a handle on HIP device `device`, ordering work on `stream` (a
+ * hipStream_t; NULL = the null stream).  Fails with SISLICE_ERR_NO_DEVICE when
+ * the device is absent or is not gfx950. */
+sislice_status sislice_create(sislice_handle **h, int device, void *stream);
+sislice_status sislice_destroy(sislice_handle *h);
+sislice_status sislice_set_stream(sislice_handle *h, void *stream);
+
+/* Bunch-Kaufman LDL^T of C = A - sigma B (Sec. 2.1: the probe's major cost) and
+ * the Sylvester inertia of D (Sec. 2.2).
+ *   A, B   device, n x n, lower triangle read (lda, ldb >= n).
+ *   LD     device, n x n, ldld >= n, written: D on the diagonal and, for a 2x2
+ *          pivot block at (k, k+1), D[k+1,k] at LD[k+1,k]; the strictly lower
+ *          remainder holds unit-lower L (L[k+1,k] = 0 inside a 2x2 block).
+ *   ipiv   device int32[n], written: P C P^T = L D L^T where row i of P C P^T is
+ *          row p(i) of C; ipiv[i] = p(i) for a 1x1 pivot row and -(p(i)+1) for
+ *          both rows of a 2x2 pivot block.
+ *   inertia host int64[3]: (negative, zero, positive) eigenvalue counts of D;
+ *          inertia[0] = #{lambda(A,B) < sigma}.
+ * Returns SISLICE_SINGULAR_SHIFT (with the factors written) when a pivot is an
+ * exact zero.  Synchronises the stream. */
+sislice_status sislice_ldlt_factor(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                                   const double *B, int64_t ldb, double sigma, double *LD,
+                                   int64_t ldld, int32_t *ipiv, int64_t inertia[3]);
+
+/* The same for n_shifts shifts (host array `sigmas`), factored together (the
+ * GPU's share of the probes of Sec. 4.1).  LD and ipiv are HOST arrays of
+ * n_shifts DEVICE pointers; inertia is host int64[3*n_shifts]. */
+sislice_status sislice_ldlt_factor_multi(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                                         const double *B, int64_t ldb, int64_t n_shifts,
+                                         const double *sigmas, double *const *LD, int64_t ldld,
+                                         int32_t *const *ipiv, int64_t *inertia);
+
+/* X <- C^{-1} X with the factors of sislice_ldlt_factor (Algorithm 2, third step:
+ * L^{-T} D^{-1} L^{-1} applied through P).  X device n x nrhs (ldx >= n),
+ * 1 <= nrhs <= 64.  Asynchronous. */
+sislice_status sislice_ldlt_solve(sislice_handle *h, int64_t n, const double *LD, int64_t ldld,
+                                  const int32_t *ipiv, int64_t nrhs, double *X, int64_t ldx);
+
+/* Shift placement from a stochastic Chebyshev DOS estimate (Sec. 3.1 with the
+ * kernel polynomial method in place of the Lanczos DOS): spectral bounds by a
+ * Lanczos run on L_B^{-1} A L_B^{-T}, opts->kpm_moments Jackson-damped moments
+ * from opts->kpm_vectors Rademacher vectors, the closed-form CDOS, its roots at
+ * equal counts over [a, omega_top] with omega_top the root at
+ * n_e + top_margin*n_e/n_s, and one shift at each interval midpoint.
+ *   sigmas     host double[n_s] out, ascending.
+ *   omega_top  host double out.
+ *   moments    host double[kpm_moments] out (may be NULL).
+ *   bounds     host double[2] out (a, b) (may be NULL).
+ * Synchronises. */
+sislice_status sislice_plan_shifts_kpm(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                                       const double *B, int64_t ldb, int64_t n_e, int64_t n_s,
+                                       const sislice_opts *opts, double *sigmas, double *omega_top,
+                                       double *moments, double *bounds);
+
+/* The plain per-pencil path (Algorithm 1, one pass on a fixed pencil): factor
+ * every shift and the top boundary, read the inertias, run block shift-invert
+ * Lanczos in the B inner product per shift (b = opts->block, thick restart with
+ * locking), explicit Rayleigh-Ritz with A and B, residuals, slice validation
+ * (Sec. 2.2), and return the lowest n_e validated eigenpairs.
+ *   sigmas     host double[n_s], ascending, or NULL: then the shifts and the top
+ *              boundary are planned with sislice_plan_shifts_kpm.
+ *   omega_top  host double in/out: the top boundary when sigmas != NULL (must
+ *              exceed every shift); the boundary used on return.
+ *   evals      device double[n_e] out, ascending.
+ *   evecs      device n x n_e (ldx >= n) out, B-orthonormal columns.
+ *   resid      device double[n_e] out, ||A x - lambda B x|| / (||A||_2 ||x||).
+ *   report     host, may be NULL.
+ * Synchronises. */
+sislice_status sislice_solve(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, int64_t n_e, int64_t n_s,
+                             const double *sigmas, double *omega_top, const sislice_opts *opts,
+                             double *evals, double *evecs, int64_t ldx, double *resid,
+                             sislice_report *report);
+
+/* Shift migration by k-means (Sec. 3.2), host only: Lloyd iterations on the 1-D
+ * set `ritz` (host double[n]) from the initial centroids `prev_shifts` (host
+ * double[n_s]) or, if use_kmeanspp, from k-means++ seeding drawn from the
+ * SplitMix64 stream of `seed`.  Ties go to the lower centroid; an empty cluster
+ * keeps its centroid; at most 300 sweeps.  new_shifts: host double[n_s] out,
+ * ascending.  labels: host int32[n] out (may be NULL). */
+sislice_status sislice_kmeans_shifts(const double *ritz, int64_t n, const double *prev_shifts,
+                                     int64_t n_s, int32_t use_kmeanspp, uint64_t seed,
+                                     double *new_shifts, int32_t *labels);
+
+/* Slice validation (Sec. 2.2), host only.  Probe j (shift sigmas[j]) reports
+ * counts[j] Ritz values and residual norms stored contiguously from
+ * offsets[j] in `thetas` / `resids`.  Slices: (-inf, s_1), [s_j, s_{j+1}) split
+ * at their midpoint tau (a value at tau belongs to the lower probe),
+ * [s_ns, omega_top).  Outputs: slice_case/slice_exact/slice_cand int32[n_s+1];
+ * chosen int32[total] flags (1 = validated) aligned with `thetas`.
+ * Returns the number of validated values, or a negative status. */
+int64_t sislice_validate(int64_t n_s, const double *sigmas, const int64_t *nu, double omega_top,
+                         int64_t nu_top, const int64_t *offsets, const int64_t *counts,
+                         const double *thetas, const double *resids, int32_t *slice_case,
+                         int32_t *slice_exact, int32_t *slice_cand, int32_t *chosen);
+
+/* Host helpers of the planner (Sec. 3.1), exposed for testing:
+ * CDOS Phi(omega) of Jackson-damped moments mu[0..M) on [a, b] for order n, and
+ * the equal-count placement described at sislice_plan_shifts_kpm. */
+double sislice_kpm_cdos(const double *mu, int32_t M, double a, double b, int64_t n, double omega);
+sislice_status sislice_kpm_place(const double *mu, int32_t M, double a, double b, int64_t n,
+                                 int64_t n_e, int64_t n_s, double top_margin, double *sigmas,
+                                 double *omega_top);
+
+/* SplitMix64 output i of `seed` (counter form): the generator behind every
+ * random draw of the library. */
+uint64_t sislice_splitmix64(uint64_t seed, uint64_t i);
+
+/* Small dense symmetric eigensolver used for the projected problems of
+ * Rayleigh-Ritz (Sec. 2.1): `batch` matrices of order m <= 112, device,
+ * column-major with leading dimension lda, lower triangle read.  W device
+ * double[batch*m] eigenvalues ascending; V device batch*(m x m) eigenvectors
+ * (leading dimension m).  Asynchronous. */
+sislice_status sislice_sym_eig(sislice_handle *h, int32_t m, int32_t batch, const double *A,
+                               int64_t lda, double *W, double *V);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SISLICE_H */

@@ -1,0 +1,98 @@
+"""ctypes declarations of the C ABI in ``include/sislice.h`` (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libsislice.so")
+
+c_double_p = C.POINTER(C.c_double)
+c_int64_p = C.POINTER(C.c_int64)
+c_int32_p = C.POINTER(C.c_int32)
+c_void_pp = C.POINTER(C.c_void_p)
+
+STATUS = {
+    0: "ok", -1: "invalid argument", -2: "HIP runtime error", -3: "allocation failed",
+    -4: "no gfx950 device", 1: "singular shift", 2: "not converged", 3: "missing eigenvalues",
+}
+
+
+class Opts(C.Structure):
+    _fields_ = [("block", C.c_int32), ("max_basis", C.c_int32), ("max_cycles", C.c_int32),
+                ("kpm_moments", C.c_int32), ("kpm_vectors", C.c_int32),
+                ("bounds_steps", C.c_int32), ("nb", C.c_int32), ("reserved_i", C.c_int32),
+                ("tol", C.c_double), ("top_margin", C.c_double), ("seed", C.c_uint64)]
+
+
+class Report(C.Structure):
+    _fields_ = [("n_shifts", C.c_int64), ("n_validated", C.c_int64), ("n_converged", C.c_int64),
+                ("nu_top", C.c_int64), ("omega_top", C.c_double), ("anorm", C.c_double),
+                ("cycles_max", C.c_int32), ("block_steps", C.c_int32),
+                ("t_factor_ms", C.c_double), ("t_lanczos_ms", C.c_double),
+                ("t_rr_ms", C.c_double), ("t_host_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("flops_factor", C.c_double), ("nu", c_int64_p), ("slice_case", c_int32_p),
+                ("slice_exact", c_int32_p), ("slice_cand", c_int32_p)]
+
+
+_SIGS = {
+    "sislice_default_opts": (None, [C.POINTER(Opts)]),
+    "sislice_status_string": (C.c_char_p, [C.c_int]),
+    "sislice_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
+    "sislice_destroy": (C.c_int, [C.c_void_p]),
+    "sislice_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sislice_ldlt_factor": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                      C.c_int64, C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
+                                      c_int64_p]),
+    "sislice_ldlt_factor_multi": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                            C.c_void_p, C.c_int64, C.c_int64, c_double_p,
+                                            c_void_pp, C.c_int64, c_void_pp, c_int64_p]),
+    "sislice_ldlt_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                     C.c_int64, C.c_void_p, C.c_int64]),
+    "sislice_plan_shifts_kpm": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                          C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                          C.POINTER(Opts), c_double_p, c_double_p, c_double_p,
+                                          c_double_p]),
+    "sislice_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                C.c_int64, C.c_int64, C.c_int64, c_double_p, c_double_p,
+                                C.POINTER(Opts), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
+                                C.POINTER(Report)]),
+    "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
+                                        C.c_uint64, c_double_p, c_int32_p]),
+    "sislice_validate": (C.c_int64, [C.c_int64, c_double_p, c_int64_p, C.c_double, C.c_int64,
+                                     c_int64_p, c_int64_p, c_double_p, c_double_p, c_int32_p,
+                                     c_int32_p, c_int32_p, c_int32_p]),
+    "sislice_kpm_cdos": (C.c_double, [c_double_p, C.c_int32, C.c_double, C.c_double, C.c_int64,
+                                      C.c_double]),
+    "sislice_kpm_place": (C.c_int, [c_double_p, C.c_int32, C.c_double, C.c_double, C.c_int64,
+                                    C.c_int64, C.c_int64, C.c_double, c_double_p, c_double_p]),
+    "sislice_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+    "sislice_sym_eig": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                  C.c_void_p, C.c_void_p]),
+}
+
+EXPORTED = tuple(_SIGS)
+
+_lib = None
+
+
+def load():
+    """Load the built library; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python -m paper_1908_06043_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class SisliceError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: status {code} ({STATUS.get(code, 'unknown')})")

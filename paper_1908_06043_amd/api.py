@@ -1,0 +1,250 @@
+"""Thin torch-facing binding of the HIP library (argument marshalling only).
+
+Every computation happens in the library's gfx950 kernels; torch provides device
+memory and the current HIP stream.  Matrices are passed as square float64 CUDA
+tensors; the library reads them as column-major, i.e. it sees the transpose of
+a row-major torch tensor, which for the symmetric A and B is the same matrix.
+Column-major outputs are returned as views with mathematical indexing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Opts, Report, SisliceError
+
+_handles = {}
+
+
+def _require_gpu():
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1908_06043_amd needs a ROCm GPU (gfx950); none is visible")
+
+
+def handle(device=None):
+    """Library handle for `device`, bound to torch's current stream on each call."""
+    _require_gpu()
+    lib = _lib.load()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = _handles.get(dev)
+    if h is None:
+        hp = C.c_void_p()
+        with torch.cuda.device(dev):
+            st = lib.sislice_create(C.byref(hp), dev, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if st != 0:
+            raise SisliceError(st, "sislice_create")
+        h = hp.value
+        _handles[dev] = h
+    st = lib.sislice_set_stream(C.c_void_p(h), C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    if st != 0:
+        raise SisliceError(st, "sislice_set_stream")
+    return C.c_void_p(h)
+
+
+def _mat(M, name):
+    if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float64 and M.dim() == 2
+            and M.shape[0] == M.shape[1] and M.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous square float64 CUDA tensor")
+    return M
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    _lib.load().sislice_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _check(st, where, ok=(0,)):
+    if st not in ok:
+        raise SisliceError(st, where)
+    return st
+
+
+@dataclass
+class Factor:
+    LDt: torch.Tensor      # (n, n): LDt[j, i] = LD(i, j) (column-major storage)
+    ipiv: torch.Tensor     # int32 (n,)
+    inertia: tuple
+    status: int
+
+    @property
+    def LD(self):
+        return self.LDt.t()
+
+
+def ldlt_factor(A, B, sigma) -> Factor:
+    """Bunch-Kaufman LDL^T of A - sigma B with the inertia of D."""
+    return ldlt_factor_multi(A, B, [sigma])[0]
+
+
+def ldlt_factor_multi(A, B, sigmas):
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n = A.shape[0]
+    sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64).ravel())
+    S = sig.size
+    LDts = [torch.empty((n, n), dtype=torch.float64, device=A.device) for _ in range(S)]
+    ipivs = [torch.empty(n, dtype=torch.int32, device=A.device) for _ in range(S)]
+    ld_ptrs = (C.c_void_p * S)(*[t.data_ptr() for t in LDts])
+    ip_ptrs = (C.c_void_p * S)(*[t.data_ptr() for t in ipivs])
+    inert = np.zeros(3 * S, dtype=np.int64)
+    lib = _lib.load()
+    st = lib.sislice_ldlt_factor_multi(handle(A.device.index), n, A.data_ptr(), n, B.data_ptr(), n, S,
+                                       sig.ctypes.data_as(_lib.c_double_p), ld_ptrs, n, ip_ptrs,
+                                       inert.ctypes.data_as(_lib.c_int64_p))
+    _check(st, "sislice_ldlt_factor_multi", ok=(0, 1))
+    return [Factor(LDts[s], ipivs[s], tuple(int(x) for x in inert[3 * s:3 * s + 3]), st) for s in range(S)]
+
+
+def ldlt_solve(f: Factor, X):
+    """Returns C^{-1} X for X of shape (n, nrhs) (or (n,)) using the factors."""
+    vec = X.dim() == 1
+    Xc = (X[:, None] if vec else X).t().contiguous()   # (nrhs, n) = column-major n x nrhs
+    n = f.LDt.shape[0]
+    nrhs = Xc.shape[0]
+    lib = _lib.load()
+    st = lib.sislice_ldlt_solve(handle(X.device.index), n, f.LDt.data_ptr(), n, f.ipiv.data_ptr(),
+                                nrhs, Xc.data_ptr(), n)
+    _check(st, "sislice_ldlt_solve")
+    out = Xc.t()
+    return out[:, 0] if vec else out
+
+
+def sym_eig(M):
+    """Eigen-decomposition of a batch of small symmetric matrices (m <= 112)."""
+    Mb = M if M.dim() == 3 else M[None]
+    batch, m, _ = Mb.shape
+    Ac = Mb.transpose(1, 2).contiguous()
+    W = torch.empty((batch, m), dtype=torch.float64, device=M.device)
+    V = torch.empty((batch, m, m), dtype=torch.float64, device=M.device)   # V[b, j, i] = vec j, comp i
+    lib = _lib.load()
+    st = lib.sislice_sym_eig(handle(M.device.index), m, batch, Ac.data_ptr(), m, W.data_ptr(), V.data_ptr())
+    _check(st, "sislice_sym_eig")
+    Vm = V.transpose(1, 2)
+    return (W[0], Vm[0]) if M.dim() == 2 else (W, Vm)
+
+
+def plan_shifts_kpm(A, B, n_e, n_s, opts=None):
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n = A.shape[0]
+    o = opts or default_opts()
+    sig = np.zeros(n_s)
+    top = C.c_double()
+    mom = np.zeros(o.kpm_moments)
+    bnd = np.zeros(2)
+    lib = _lib.load()
+    st = lib.sislice_plan_shifts_kpm(handle(A.device.index), n, A.data_ptr(), n, B.data_ptr(), n,
+                                     n_e, n_s, C.byref(o), sig.ctypes.data_as(_lib.c_double_p),
+                                     C.byref(top), mom.ctypes.data_as(_lib.c_double_p),
+                                     bnd.ctypes.data_as(_lib.c_double_p))
+    _check(st, "sislice_plan_shifts_kpm")
+    return dict(sigmas=sig, omega_top=top.value, mu=mom, a=bnd[0], b=bnd[1])
+
+
+def solve(A, B, n_e, n_s, sigmas=None, omega_top=None, opts=None, check=True):
+    """Lowest n_e eigenpairs of (A, B).  Returns dict with evals, evecs (n x n_e view),
+    resid, status and the report."""
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n = A.shape[0]
+    o = opts or default_opts()
+    ev = torch.empty(n_e, dtype=torch.float64, device=A.device)
+    Xt = torch.empty((n_e, n), dtype=torch.float64, device=A.device)
+    rs = torch.empty(n_e, dtype=torch.float64, device=A.device)
+    rep = Report()
+    nu = np.zeros(n_s, dtype=np.int64)
+    sc = np.zeros(n_s + 1, dtype=np.int32)
+    se = np.zeros(n_s + 1, dtype=np.int32)
+    sd = np.zeros(n_s + 1, dtype=np.int32)
+    rep.nu = nu.ctypes.data_as(_lib.c_int64_p)
+    rep.slice_case = sc.ctypes.data_as(_lib.c_int32_p)
+    rep.slice_exact = se.ctypes.data_as(_lib.c_int32_p)
+    rep.slice_cand = sd.ctypes.data_as(_lib.c_int32_p)
+    top = C.c_double(float(omega_top) if omega_top is not None else 0.0)
+    if sigmas is not None:
+        sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+        if sig.size != n_s:
+            raise ValueError("len(sigmas) != n_s")
+        sp = sig.ctypes.data_as(_lib.c_double_p)
+        if omega_top is None:
+            raise ValueError("omega_top is required with explicit shifts")
+    else:
+        sig = None
+        sp = None
+    lib = _lib.load()
+    st = lib.sislice_solve(handle(A.device.index), n, A.data_ptr(), n, B.data_ptr(), n, n_e, n_s, sp,
+                           C.byref(top), C.byref(o), ev.data_ptr(), Xt.data_ptr(), n, rs.data_ptr(),
+                           C.byref(rep))
+    if check:
+        _check(st, "sislice_solve")
+    report = {f: getattr(rep, f) for f, _ in Report._fields_ if f not in ("nu", "slice_case", "slice_exact", "slice_cand")}
+    report.update(nu=nu, slice_case=sc, slice_exact=se, slice_cand=sd)
+    return dict(evals=ev, evecs=Xt.t(), resid=rs, status=st, omega_top=top.value, report=report)
+
+
+# ----------------------------------------------------------- host-only helpers
+
+def kmeans_shifts(ritz, prev_shifts=None, n_s=None, use_kmeanspp=False, seed=0):
+    x = np.ascontiguousarray(np.asarray(ritz, dtype=np.float64))
+    k = len(prev_shifts) if prev_shifts is not None else int(n_s)
+    prev = np.ascontiguousarray(np.asarray(prev_shifts if prev_shifts is not None else np.zeros(k), dtype=np.float64))
+    out = np.zeros(k)
+    lab = np.zeros(x.size, dtype=np.int32)
+    st = _lib.load().sislice_kmeans_shifts(x.ctypes.data_as(_lib.c_double_p), x.size,
+                                          prev.ctypes.data_as(_lib.c_double_p), k, int(use_kmeanspp),
+                                          seed, out.ctypes.data_as(_lib.c_double_p),
+                                          lab.ctypes.data_as(_lib.c_int32_p))
+    _check(st, "sislice_kmeans_shifts")
+    return out, lab
+
+
+def validate(sigmas, nus, thetas, resids, omega_top, nu_top):
+    sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+    ns = sig.size
+    nu = np.ascontiguousarray(np.asarray(nus, dtype=np.int64))
+    counts = np.array([len(t) for t in thetas], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    th = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in thetas]) if counts.sum() else np.zeros(1))
+    rs = np.ascontiguousarray(np.concatenate([np.asarray(r, dtype=np.float64) for r in resids]) if counts.sum() else np.zeros(1))
+    sc = np.zeros(ns + 1, dtype=np.int32)
+    se = np.zeros(ns + 1, dtype=np.int32)
+    sd = np.zeros(ns + 1, dtype=np.int32)
+    ch = np.zeros(max(int(counts.sum()), 1), dtype=np.int32)
+    nv = _lib.load().sislice_validate(ns, sig.ctypes.data_as(_lib.c_double_p), nu.ctypes.data_as(_lib.c_int64_p),
+                                      float(omega_top), int(nu_top), offs.ctypes.data_as(_lib.c_int64_p),
+                                      counts.ctypes.data_as(_lib.c_int64_p), th.ctypes.data_as(_lib.c_double_p),
+                                      rs.ctypes.data_as(_lib.c_double_p), sc.ctypes.data_as(_lib.c_int32_p),
+                                      se.ctypes.data_as(_lib.c_int32_p), sd.ctypes.data_as(_lib.c_int32_p),
+                                      ch.ctypes.data_as(_lib.c_int32_p))
+    if nv < 0:
+        raise SisliceError(int(nv), "sislice_validate")
+    return dict(n_validated=int(nv), slice_case=sc, slice_exact=se, slice_cand=sd,
+                chosen=ch[: int(counts.sum())], offsets=offs, counts=counts)
+
+
+def kpm_cdos(mu, a, b, n, omega):
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    return _lib.load().sislice_kpm_cdos(mu.ctypes.data_as(_lib.c_double_p), mu.size, a, b, n, omega)
+
+
+def kpm_place(mu, a, b, n, n_e, n_s, top_margin=2.0):
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64))
+    sig = np.zeros(n_s)
+    top = C.c_double()
+    st = _lib.load().sislice_kpm_place(mu.ctypes.data_as(_lib.c_double_p), mu.size, a, b, n, n_e, n_s,
+                                       top_margin, sig.ctypes.data_as(_lib.c_double_p), C.byref(top))
+    _check(st, "sislice_kpm_place")
+    return sig, top.value
+
+
+def splitmix64(seed, i):
+    return int(_lib.load().sislice_splitmix64(seed, i))

@@ -1,0 +1,281 @@
+// Dense FP64 building blocks of the Lanczos / Rayleigh-Ritz / KPM phases:
+// batched MFMA GEMM with optional transposes and deterministic split-K,
+// symmetrisation of a lower-stored matrix, column dot products / norms, and the
+// counter-based Gaussian start blocks.
+//
+// GEMM design (gfx950): 64x64 output tile per 256-thread workgroup, four
+// wavefronts each owning 32x32 as 2x2 v_mfma_f64_16x16x4 blocks; K staged
+// through LDS in chunks of 16 (sA[k][i], sB[k][j]).  The MFMA A operand carries
+// op(B)^T and the B operand op(A)^T so that accumulator register r of lane l
+// holds C(i0 + l%16, j0 + l/16 + 4r): sixteen consecutive rows of one column,
+// i.e. coalesced column-major stores.  Transposed operands only change the
+// global->LDS load pattern (always along the contiguous dimension).
+#include "blas.hpp"
+#include "common.hpp"
+
+namespace sislice {
+
+constexpr int GT = 64;   // tile rows/cols
+constexpr int GK = 16;   // K chunk
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ double sA[GK][GT + 2];
+  __shared__ double sB[GK][GT + 2];
+  const int zb = blockIdx.z;
+  const int b = zb / g.splits, sp = zb % g.splits;
+  const int m = g.m ? g.m[b] : g.m0;
+  const int n = g.n ? g.n[b] : g.n0;
+  const int K = g.k ? g.k[b] : g.k0;
+  const int i0 = blockIdx.x * GT, j0 = blockIdx.y * GT;
+  if (i0 >= m || j0 >= n) return;
+  const double* A = g.A[b];
+  const double* B = g.B[b];
+  int kc = (K + g.splits - 1) / g.splits;
+  kc = (kc + GK - 1) / GK * GK;
+  const int kb = sp * kc, ke = min(K, kb + kc);
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+  const int lr = l & 15, lk = l >> 4;
+  d4 acc[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < GK * GT / 256; ++q) {
+      const int e = tid + 256 * q;
+      int ii, kk;
+      if (!TA) {
+        ii = e & 63;
+        kk = e >> 6;
+      } else {
+        kk = e & 15;
+        ii = e >> 4;
+      }
+      const int gi = i0 + ii, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < ke) v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
+      sA[kk][ii] = v;
+      int jj, kk2;
+      if (!TB) {
+        kk2 = e & 15;
+        jj = e >> 4;
+      } else {
+        jj = e & 63;
+        kk2 = e >> 6;
+      }
+      const int gj = j0 + jj, gk2 = k0 + kk2;
+      double u = 0.0;
+      if (gj < n && gk2 < ke) u = TB ? B[gj + (long)gk2 * g.ldb] : B[gk2 + (long)gj * g.ldb];
+      sB[kk2][jj] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const double bA0 = sA[kk + lk][wi + lr], bA1 = sA[kk + lk][wi + 16 + lr];
+      const double aB0 = sB[kk + lk][wj + lr], aB1 = sB[kk + lk][wj + 16 + lr];
+      acc[0][0] = mfma16x16x4(aB0, bA0, acc[0][0]);
+      acc[0][1] = mfma16x16x4(aB1, bA0, acc[0][1]);
+      acc[1][0] = mfma16x16x4(aB0, bA1, acc[1][0]);
+      acc[1][1] = mfma16x16x4(aB1, bA1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  if (g.splits > 1) {
+    double* P = g.partial + ((long)b * g.splits + sp) * g.pstride;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + wi + 16 * x + lr, j = j0 + wj + 16 * y + lk + 4 * r;
+          if (i < m && j < n) P[i + (long)j * g.pld] = acc[x][y][r];
+        }
+    return;
+  }
+  double* C = g.C[b];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + 16 * x + lr, j = j0 + wj + 16 * y + lk + 4 * r;
+        if (i < m && j < n) {
+          double* c = C + i + (long)j * g.ldc;
+          const double v = g.alpha * acc[x][y][r];
+          *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+        }
+      }
+}
+
+// C = alpha * sum_sp partial[sp] + beta * C, summed in split order (deterministic).
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
+  const int b = blockIdx.y;
+  const int m = g.m ? g.m[b] : g.m0;
+  const int n = g.n ? g.n[b] : g.n0;
+  double* C = g.C[b];
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)m * n; e += (long)gridDim.x * 256) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    double s = 0.0;
+    for (int sp = 0; sp < g.splits; ++sp)
+      s += g.partial[((long)b * g.splits + sp) * g.pstride + i + (long)j * g.pld];
+    double* c = C + i + (long)j * g.ldc;
+    const double v = g.alpha * s;
+    *c = (g.beta == 0.0) ? v : v + g.beta * *c;
+  }
+}
+
+void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hipStream_t st) {
+  if (batch <= 0 || mmax <= 0 || nmax <= 0) return;
+  if (g.splits < 1) g.splits = 1;
+  if (g.splits > 1) {
+    SL_CHECK_ARG(g.partial != nullptr, "split-K GEMM needs a partial buffer");
+    g.pld = mmax;
+    g.pstride = (long)mmax * nmax;
+  }
+  dim3 grid((unsigned)ceil_div(mmax, GT), (unsigned)ceil_div(nmax, GT), (unsigned)(batch * g.splits));
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
+  if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, g);
+  if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, g);
+  if (ta && tb) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, g);
+  SL_LAUNCH_CHECK();
+  if (g.splits > 1) {
+    const long tot = (long)mmax * nmax;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096), batch),
+                       dim3(256), 0, st, g);
+    SL_LAUNCH_CHECK();
+  }
+}
+
+// F (n x n, ldf) = symmetric completion of the lower triangle of S (lds), tiled
+// through LDS so both the read and the mirrored write are coalesced.
+__global__ __launch_bounds__(256) void k_sym_full(int n, const double* __restrict__ S, long lds,
+                                                  double* __restrict__ F, long ldf) {
+  __shared__ double t[32][33];
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = bi * 32 + tx, j = bj * 32 + yy;
+    double v = 0.0;
+    if (i < n && j < n) {
+      v = (i >= j) ? S[i + (long)j * lds] : S[j + (long)i * lds];
+      F[i + (long)j * ldf] = v;
+    }
+    t[yy][tx] = v;
+  }
+  __syncthreads();
+  if (bi == bj) return;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = bj * 32 + tx, j = bi * 32 + yy;  // mirrored tile
+    if (i < n && j < n) F[i + (long)j * ldf] = t[tx][yy];
+  }
+}
+
+void sym_full_launch(int n, const double* S, long lds, double* F, long ldf, hipStream_t st) {
+  const unsigned T = (unsigned)ceil_div(n, 32);
+  hipLaunchKernelGGL(k_sym_full, dim3(T, T), dim3(256), 0, st, n, S, lds, F, ldf);
+  SL_LAUNCH_CHECK();
+}
+
+// Column dots: out[b][c] = sum_i X[i,c] * Y[i,c] (or ||X[:,c] - w_c Y[:,c]||^2 when
+// mode == 1), per batch, two-level deterministic reduction.
+__global__ __launch_bounds__(256) void k_coldot_partial(ColDotArgs a) {
+  const int b = blockIdx.z, c = blockIdx.y, chunk = blockIdx.x;
+  const int nc = a.ncol ? a.ncol[b] : a.ncol0;
+  if (c >= nc) return;
+  const double* X = a.X[b] + (long)c * a.ldx;
+  const double* Y = a.Y[b] + (long)c * a.ldy;
+  const double w = (a.mode == 1) ? a.w[b][c] : 0.0;
+  const int r0 = chunk * kDotChunk, r1 = min(a.n, r0 + kDotChunk);
+  double s = 0.0;
+  for (int i = r0 + threadIdx.x; i < r1; i += 256) {
+    if (a.mode == 0) {
+      s += X[i] * Y[i];
+    } else {
+      const double d = X[i] - w * Y[i];
+      s += d * d;
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[((long)b * a.maxcol + c) * a.nchunk + chunk] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_coldot_reduce(ColDotArgs a) {
+  const int b = blockIdx.x;
+  const int nc = a.ncol ? a.ncol[b] : a.ncol0;
+  for (int c = threadIdx.x; c < nc; c += 256) {
+    double s = 0.0;
+    for (int q = 0; q < a.nchunk; ++q) s += a.partial[((long)b * a.maxcol + c) * a.nchunk + q];
+    a.out[b][c] = (a.mode == 1) ? sqrt(s) : s;
+  }
+}
+
+void coldot_launch(ColDotArgs a, int batch, int maxcol, hipStream_t st) {
+  a.maxcol = maxcol;
+  a.nchunk = (int)ceil_div(a.n, kDotChunk);
+  hipLaunchKernelGGL(k_coldot_partial, dim3(a.nchunk, maxcol, batch), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_coldot_reduce, dim3(batch), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+}
+
+// Gaussian block from the SplitMix64 stream: entry (i, c) uses stream index
+// c * n + i, Box-Muller on outputs 2k and 2k+1 (the library's shared definition).
+__device__ __forceinline__ unsigned long long smix(unsigned long long seed, unsigned long long i) {
+  unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_gauss_block(int n, int ncol, const unsigned long long* seeds,
+                                                     double* const* X, long ldx) {
+  const int b = blockIdx.y;
+  const unsigned long long sd = seeds[b];
+  double* x = X[b];
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)n * ncol; e += (long)gridDim.x * 256) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    const unsigned long long k = (unsigned long long)c * n + i;
+    const double u1 = (double)(smix(sd, 2 * k) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(smix(sd, 2 * k + 1) >> 11) * 0x1.0p-53;
+    x[i + (long)c * ldx] = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rademacher_block(int n, int ncol, unsigned long long seed,
+                                                          double* X, long ldx) {
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)n * ncol; e += (long)gridDim.x * 256) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    const unsigned long long v = smix(seed, (unsigned long long)c * n + i);
+    X[i + (long)c * ldx] = (v >> 63) ? -1.0 : 1.0;
+  }
+}
+
+void gauss_launch(int n, int ncol, int batch, const unsigned long long* d_seeds, double* const* X,
+                  long ldx, hipStream_t st) {
+  const long tot = (long)n * ncol;
+  hipLaunchKernelGGL(k_gauss_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048), batch),
+                     dim3(256), 0, st, n, ncol, d_seeds, X, ldx);
+  SL_LAUNCH_CHECK();
+}
+
+void rademacher_launch(int n, int ncol, unsigned long long seed, double* X, long ldx,
+                       hipStream_t st) {
+  const long tot = (long)n * ncol;
+  hipLaunchKernelGGL(k_rademacher_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048)),
+                     dim3(256), 0, st, n, ncol, seed, X, ldx);
+  SL_LAUNCH_CHECK();
+}
+
+}  // namespace sislice

@@ -1,0 +1,61 @@
+// Dense FP64 building blocks (launch interface).
+#pragma once
+
+#include "common.hpp"
+
+namespace sislice {
+
+// C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch; op(A) is m x k, op(B) k x n.
+// Per-batch sizes come from the device arrays m/n/k when non-null, else from
+// m0/n0/k0.  beta == 0 never reads C.  splits > 1 reduces K in `splits` ordered
+// partial products (deterministic), which needs `partial` with room for
+// batch * splits * mmax * nmax doubles.
+struct GemmArgs {
+  const int* m = nullptr;
+  const int* n = nullptr;
+  const int* k = nullptr;
+  int m0 = 0, n0 = 0, k0 = 0;
+  const double* const* A = nullptr;
+  long lda = 0;
+  const double* const* B = nullptr;
+  long ldb = 0;
+  double* const* C = nullptr;
+  long ldc = 0;
+  double alpha = 1.0, beta = 0.0;
+  int splits = 1;
+  double* partial = nullptr;
+  long pld = 0, pstride = 0;
+};
+
+void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hipStream_t st);
+void sym_full_launch(int n, const double* S, long lds, double* F, long ldf, hipStream_t st);
+
+constexpr int kDotChunk = 2048;
+
+// mode 0: out[b][c] = X[:,c] . Y[:,c];  mode 1: out[b][c] = ||X[:,c] - w[b][c] Y[:,c]||_2
+struct ColDotArgs {
+  int n = 0;
+  const int* ncol = nullptr;
+  int ncol0 = 0;
+  const double* const* X = nullptr;
+  long ldx = 0;
+  const double* const* Y = nullptr;
+  long ldy = 0;
+  const double* const* w = nullptr;
+  double* const* out = nullptr;
+  int mode = 0;
+  double* partial = nullptr;  // batch * maxcol * ceil(n / kDotChunk)
+  int maxcol = 0, nchunk = 0;
+};
+
+void coldot_launch(ColDotArgs a, int batch, int maxcol, hipStream_t st);
+inline size_t coldot_partial_size(int n, int batch, int maxcol) {
+  return (size_t)batch * maxcol * ceil_div(n, kDotChunk);
+}
+
+void gauss_launch(int n, int ncol, int batch, const unsigned long long* d_seeds, double* const* X,
+                  long ldx, hipStream_t st);
+void rademacher_launch(int n, int ncol, unsigned long long seed, double* X, long ldx,
+                       hipStream_t st);
+
+}  // namespace sislice

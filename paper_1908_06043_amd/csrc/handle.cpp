@@ -1,0 +1,273 @@
+// Handle lifecycle, workspaces, status strings and the factorization entry points.
+#include "handle.hpp"
+
+#include <cstring>
+#include <string>
+
+#include "factor_api.hpp"
+#include "kernels.hpp"
+
+namespace sislice {
+
+void check_handle(sislice_handle* h) {
+  SL_CHECK_ARG(h != nullptr, "null handle");
+  SL_HIP(hipSetDevice(h->device));
+}
+
+void* ws_get(sislice_handle* h, int id, size_t bytes) {
+  auto& b = h->bufs[id];
+  if (bytes == 0) bytes = 256;
+  if (b.cap < bytes) {
+    if (b.ptr) {
+      SL_HIP(hipStreamSynchronize(h->stream));
+      SL_HIP(hipFree(b.ptr));
+      b.ptr = nullptr;
+      b.cap = 0;
+    }
+    size_t cap = bytes + bytes / 8;
+    if (hipMalloc(&b.ptr, cap) != hipSuccess) {
+      b.ptr = nullptr;
+      throw Error(SISLICE_ERR_ALLOC, "device workspace allocation failed");
+    }
+    b.cap = cap;
+  }
+  return b.ptr;
+}
+
+void* host_stage(sislice_handle* h, size_t bytes) {
+  if (h->host_cap < bytes) {
+    if (h->host_stage) {
+      SL_HIP(hipStreamSynchronize(h->stream));
+      SL_HIP(hipHostFree(h->host_stage));
+      h->host_stage = nullptr;
+      h->host_cap = 0;
+    }
+    size_t cap = bytes + bytes / 4 + 4096;
+    if (hipHostMalloc(&h->host_stage, cap, hipHostMallocDefault) != hipSuccess) {
+      h->host_stage = nullptr;
+      throw Error(SISLICE_ERR_ALLOC, "pinned host allocation failed");
+    }
+    h->host_cap = cap;
+  }
+  return h->host_stage;
+}
+
+unsigned* sync_words(sislice_handle* h, size_t words) {
+  if (h->sync_cap < words) {
+    if (h->sync) {
+      SL_HIP(hipStreamSynchronize(h->stream));
+      SL_HIP(hipFree(h->sync));
+      h->sync = nullptr;
+      h->sync_cap = 0;
+    }
+    const size_t cap = words + 4096;
+    if (hipMalloc(&h->sync, cap * sizeof(unsigned)) != hipSuccess) {
+      h->sync = nullptr;
+      throw Error(SISLICE_ERR_ALLOC, "sync area allocation failed");
+    }
+    SL_HIP(hipMemsetAsync(h->sync, 0, cap * sizeof(unsigned), h->stream));
+    h->sync_cap = cap;
+  }
+  return h->sync;
+}
+
+int default_nb(int n) { return n >= 2048 ? 64 : 32; }
+
+FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, long lda,
+                        const double* B, long ldb, int S, const double* sigmas_host,
+                        double* const* LD_host, long ldld, int32_t* const* ipiv_host, int nb,
+                        bool pivot) {
+  const int npmax = factor_npanel_max(n, nb);
+  const long ldw = n;
+  Sizer z;
+  z.take<double>(S);                          // sigmas
+  z.take<double>((size_t)S * ldw * (nb + 2));  // W
+  for (int q = 0; q < 4; ++q) z.take<int>((size_t)S * n);
+  z.take<int>((size_t)S * npmax);
+  z.take<int>((size_t)S * npmax * n);
+  z.take<FactorState>(S);
+  z.take<int64_t>(3 * (size_t)S);
+  z.take<void*>(9 * (size_t)S);
+  Carver c(ws_get(h, bufid, z.off));
+  FactorPlan fp;
+  fp.n = n;
+  fp.nshift = S;
+  fp.nb = nb;
+  fp.pivot = pivot;
+  fp.A = A;
+  fp.B = B;
+  fp.lda = lda;
+  fp.ldb = ldb;
+  fp.ldld = ldld;
+  fp.ldw = ldw;
+  double* d_sig = c.take<double>(S);
+  double* W = c.take<double>((size_t)S * ldw * (nb + 2));
+  int* perm = c.take<int>((size_t)S * n);
+  int* sw = c.take<int>((size_t)S * n);
+  int* blk = c.take<int>((size_t)S * n);
+  int* cp = c.take<int>((size_t)S * n);
+  int* ps = c.take<int>((size_t)S * npmax);
+  int* snap = c.take<int>((size_t)S * npmax * n);
+  fp.d_state = c.take<FactorState>(S);
+  fp.d_inertia = c.take<int64_t>(3 * (size_t)S);
+  void** tab = c.take<void*>(9 * (size_t)S);
+  // host staging: sigmas then the nine pointer tables
+  size_t hbytes = sizeof(double) * S + sizeof(void*) * 9 * S;
+  char* hs = static_cast<char*>(host_stage(h, hbytes));
+  std::memcpy(hs, sigmas_host, sizeof(double) * S);
+  void** ht = reinterpret_cast<void**>(hs + sizeof(double) * S);
+  for (int s = 0; s < S; ++s) {
+    ht[0 * S + s] = LD_host[s];
+    ht[1 * S + s] = W + (size_t)s * ldw * (nb + 2);
+    ht[2 * S + s] = perm + (size_t)s * n;
+    ht[3 * S + s] = sw + (size_t)s * n;
+    ht[4 * S + s] = blk + (size_t)s * n;
+    ht[5 * S + s] = cp + (size_t)s * n;
+    ht[6 * S + s] = ps + (size_t)s * npmax;
+    ht[7 * S + s] = snap + (size_t)s * npmax * n;
+    ht[8 * S + s] = ipiv_host[s];
+  }
+  SL_HIP(hipMemcpyAsync(d_sig, hs, sizeof(double) * S, hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(tab, ht, sizeof(void*) * 9 * S, hipMemcpyHostToDevice, h->stream));
+  fp.d_sigmas = d_sig;
+  fp.d_LD = reinterpret_cast<double* const*>(tab + 0 * S);
+  fp.d_W = reinterpret_cast<double* const*>(tab + 1 * S);
+  fp.d_perm = reinterpret_cast<int* const*>(tab + 2 * S);
+  fp.d_sw = reinterpret_cast<int* const*>(tab + 3 * S);
+  fp.d_blk = reinterpret_cast<int* const*>(tab + 4 * S);
+  fp.d_colpanel = reinterpret_cast<int* const*>(tab + 5 * S);
+  fp.d_pstart = reinterpret_cast<int* const*>(tab + 6 * S);
+  fp.d_snap = reinterpret_cast<int* const*>(tab + 7 * S);
+  fp.d_ipiv = reinterpret_cast<int* const*>(tab + 8 * S);
+  return fp;
+}
+
+}  // namespace sislice
+
+using namespace sislice;
+
+#define SL_API_BEGIN try {
+#define SL_API_END                                          \
+  }                                                         \
+  catch (const sislice::Error& e) {                         \
+    std::fprintf(stderr, "sislice: %s\n", e.what());        \
+    return e.status;                                        \
+  }                                                         \
+  catch (const std::exception& e) {                         \
+    std::fprintf(stderr, "sislice: %s\n", e.what());        \
+    return SISLICE_ERR_HIP;                                 \
+  }
+
+extern "C" {
+
+void sislice_default_opts(sislice_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->block = 8;
+  o->max_basis = 112;
+  o->max_cycles = 40;
+  o->kpm_moments = 64;
+  o->kpm_vectors = 20;
+  o->bounds_steps = 30;
+  o->nb = 0;
+  o->tol = 1e-10;
+  o->top_margin = 2.0;
+  o->seed = 0;
+}
+
+const char* sislice_status_string(sislice_status s) {
+  switch (s) {
+    case SISLICE_OK: return "ok";
+    case SISLICE_ERR_ARG: return "invalid argument";
+    case SISLICE_ERR_HIP: return "HIP runtime error";
+    case SISLICE_ERR_ALLOC: return "allocation failed";
+    case SISLICE_ERR_NO_DEVICE: return "no gfx950 device";
+    case SISLICE_SINGULAR_SHIFT: return "a shift is an eigenvalue (exact zero pivot)";
+    case SISLICE_NOT_CONVERGED: return "residual tolerance not reached";
+    case SISLICE_MISSING_EIGS: return "eigenvalues missing from a slice or below the top boundary";
+  }
+  return "unknown status";
+}
+
+sislice_status sislice_create(sislice_handle** out, int device, void* stream) {
+  SL_API_BEGIN
+  SL_CHECK_ARG(out != nullptr, "null output pointer");
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return SISLICE_ERR_NO_DEVICE;
+  hipDeviceProp_t prop;
+  SL_HIP(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SISLICE_ERR_NO_DEVICE;
+  SL_HIP(hipSetDevice(device));
+  auto* h = new sislice_handle();
+  h->device = device;
+  h->stream = static_cast<hipStream_t>(stream);
+  for (auto& e : h->ev) SL_HIP(hipEventCreate(&e));
+  *out = h;
+  return SISLICE_OK;
+  SL_API_END
+}
+
+sislice_status sislice_destroy(sislice_handle* h) {
+  if (!h) return SISLICE_OK;
+  hipSetDevice(h->device);
+  hipStreamSynchronize(h->stream);
+  for (auto& b : h->bufs)
+    if (b.ptr) hipFree(b.ptr);
+  if (h->host_stage) hipHostFree(h->host_stage);
+  if (h->sync) hipFree(h->sync);
+  for (auto& e : h->ev)
+    if (e) hipEventDestroy(e);
+  delete h;
+  return SISLICE_OK;
+}
+
+sislice_status sislice_set_stream(sislice_handle* h, void* stream) {
+  SL_API_BEGIN
+  check_handle(h);
+  h->stream = static_cast<hipStream_t>(stream);
+  return SISLICE_OK;
+  SL_API_END
+}
+
+sislice_status sislice_ldlt_factor_multi(sislice_handle* h, int64_t n, const double* A, int64_t lda,
+                                         const double* B, int64_t ldb, int64_t n_shifts,
+                                         const double* sigmas, double* const* LD, int64_t ldld,
+                                         int32_t* const* ipiv, int64_t* inertia) {
+  SL_API_BEGIN
+  check_handle(h);
+  SL_CHECK_ARG(n >= 0 && n <= (int64_t)1 << 20, "n out of range");
+  SL_CHECK_ARG(n_shifts >= 1 && n_shifts <= 4096, "n_shifts out of range");
+  SL_CHECK_ARG(inertia && sigmas && LD && ipiv, "null pointer argument");
+  if (n == 0) {
+    for (int64_t s = 0; s < 3 * n_shifts; ++s) inertia[s] = 0;
+    return SISLICE_OK;
+  }
+  SL_CHECK_ARG(A && B && lda >= n && ldb >= n && ldld >= n, "bad matrix argument");
+  for (int64_t s = 0; s < n_shifts; ++s) SL_CHECK_ARG(LD[s] && ipiv[s], "null LD/ipiv pointer");
+  SL_CHECK_ARG(n <= 20000, "n too large for the factorization kernels (LDS-resident column)");
+  const int nb = default_nb((int)n);
+  FactorPlan fp = build_factor(h, kBufFactor, (int)n, A, lda, B, ldb, (int)n_shifts, sigmas, LD,
+                               ldld, ipiv, nb, true);
+  factor_launch(fp, h->stream);
+  auto* hi = static_cast<int64_t*>(host_stage(h, sizeof(int64_t) * 3 * n_shifts));
+  SL_HIP(hipMemcpyAsync(hi, fp.d_inertia, sizeof(int64_t) * 3 * n_shifts, hipMemcpyDeviceToHost,
+                        h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));
+  bool singular = false;
+  for (int64_t s = 0; s < 3 * n_shifts; ++s) inertia[s] = hi[s];
+  for (int64_t s = 0; s < n_shifts; ++s) singular |= inertia[3 * s + 1] > 0;
+  return singular ? SISLICE_SINGULAR_SHIFT : SISLICE_OK;
+  SL_API_END
+}
+
+sislice_status sislice_ldlt_factor(sislice_handle* h, int64_t n, const double* A, int64_t lda,
+                                   const double* B, int64_t ldb, double sigma, double* LD,
+                                   int64_t ldld, int32_t* ipiv, int64_t inertia[3]) {
+  double* lds[1] = {LD};
+  int32_t* ips[1] = {ipiv};
+  return sislice_ldlt_factor_multi(h, n, A, lda, B, ldb, 1, &sigma, lds, ldld, ips, inertia);
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// Library handle: device, stream and growable device workspaces.
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+struct sislice_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[8] = {};
+  struct Buf {
+    void* ptr = nullptr;
+    size_t cap = 0;
+  };
+  Buf bufs[8];
+  void* host_stage = nullptr;  // pinned staging for small host<->device records
+  size_t host_cap = 0;
+  unsigned* sync = nullptr;  // epoch flags and ticket counters of the persistent solves
+  size_t sync_cap = 0;       // in unsigned words
+  unsigned epoch = 0;
+};
+
+namespace sislice {
+
+enum BufId { kBufFactor = 0, kBufSolve = 1, kBufDriver = 2, kBufKpm = 3, kBufEig = 4, kBufMisc = 5 };
+
+// Returns a device buffer of at least `bytes`, reallocating (contents lost) if needed.
+void* ws_get(sislice_handle* h, int id, size_t bytes);
+void* host_stage(sislice_handle* h, size_t bytes);
+
+// Bump allocator over one workspace block.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* r = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return r;
+  }
+  static size_t round(size_t b) { return (b + 255) & ~size_t(255); }
+};
+
+// Counting pass with the same layout rules as Carver.
+struct Sizer {
+  size_t off = 0;
+  template <class T>
+  void take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    off += count * sizeof(T);
+  }
+};
+
+void check_handle(sislice_handle* h);
+
+// Zero-initialised flag/counter words for persistent launches; grows (and
+// re-zeroes) on demand.  Returns the base pointer.
+unsigned* sync_words(sislice_handle* h, size_t words);
+inline unsigned next_epoch(sislice_handle* h) { return ++h->epoch; }
+
+}  // namespace sislice

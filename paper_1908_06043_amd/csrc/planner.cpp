@@ -1,0 +1,274 @@
+// Host-side planning: slice validation (Section 2.2), the KPM cumulative DOS and
+// equal-count shift placement (Section 3.1), k-means shift migration (Section
+// 3.2) and the SplitMix64 counter generator used for every random draw.
+#include "planner.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+namespace sislice {
+
+// SplitMix64 (Steele, Lea & Flood 2014), counter form: output i of seed s is the
+// finaliser applied to s + (i + 1) * golden-ratio increment.
+uint64_t splitmix64(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+double rng_uniform(uint64_t seed, uint64_t i) { return (double)(splitmix64(seed, i) >> 11) * 0x1.0p-53; }
+
+uint64_t rng_derive(uint64_t seed, uint64_t tag) { return splitmix64(seed ^ tag, 0); }
+
+// ------------------------------------------------------------------ KPM
+
+void jackson(int M, double* g) {
+  const double q = M_PI / (M + 1);
+  const double cotq = std::cos(q) / std::sin(q);
+  for (int k = 0; k < M; ++k)
+    g[k] = ((M - k + 1) * std::cos(q * k) + std::sin(q * k) * cotq) / (M + 1);
+}
+
+// Phi(omega) = N [g0 mu0 (1 - th/pi) - (2/pi) sum_{k>=1} g_k mu_k sin(k th)/k],
+// th = arccos((omega - c)/d): the integral of the Jackson-damped Chebyshev
+// density from the bottom of [a, b] up to omega.
+double kpm_cdos(const double* mu, const double* g, int M, double a, double b, int64_t n,
+                double omega) {
+  const double c = 0.5 * (a + b), d = 0.5 * (b - a);
+  double t = (omega - c) / d;
+  t = std::min(1.0, std::max(-1.0, t));
+  const double th = std::acos(t);
+  double acc = g[0] * mu[0] * (1.0 - th / M_PI);
+  for (int k = 1; k < M; ++k) acc -= (2.0 / M_PI) * g[k] * mu[k] * std::sin(k * th) / k;
+  return (double)n * acc;
+}
+
+double kpm_root(double target, const double* mu, const double* g, int M, double a, double b,
+                int64_t n) {
+  double lo = a, hi = b;
+  const double tol = 1e-12 * (b - a);
+  while (hi - lo > tol) {
+    const double mid = 0.5 * (lo + hi);
+    if (kpm_cdos(mu, g, M, a, b, n, mid) < target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+void kpm_place(const double* mu, int M, double a, double b, int64_t n, int64_t n_e, int64_t n_s,
+               double top_margin, double* sigmas, double* omega_top) {
+  std::vector<double> g(M);
+  jackson(M, g.data());
+  const double K = (double)n_e / (double)n_s;
+  const double top_count = (double)n_e + top_margin * K;
+  *omega_top = kpm_root(top_count, mu, g.data(), M, a, b, n);
+  const double Kp = top_count / (double)n_s;
+  double prev = a;
+  for (int64_t j = 1; j <= n_s; ++j) {
+    const double w = kpm_root(j * Kp, mu, g.data(), M, a, b, n);
+    sigmas[j - 1] = 0.5 * (prev + w);
+    prev = w;
+  }
+}
+
+// ------------------------------------------------------------------ k-means
+
+static int nearest(const double* c, int k, double x) {
+  int best = 0;
+  double bd = std::fabs(x - c[0]);
+  for (int j = 1; j < k; ++j) {
+    const double d = std::fabs(x - c[j]);
+    if (d < bd) {  // strict: ties stay with the lower centroid
+      bd = d;
+      best = j;
+    }
+  }
+  return best;
+}
+
+void kmeanspp(const double* x, int64_t n, int k, uint64_t seed, double* out) {
+  const uint64_t s = rng_derive(seed, kTagKmeansPP);
+  uint64_t draw = 0;
+  double u = rng_uniform(s, draw++);
+  int64_t first = std::min<int64_t>((int64_t)(u * (double)n), n - 1);
+  out[0] = x[first];
+  std::vector<double> d2(n);
+  for (int64_t i = 0; i < n; ++i) d2[i] = (x[i] - out[0]) * (x[i] - out[0]);
+  for (int c = 1; c < k; ++c) {
+    double total = 0.0;
+    for (int64_t i = 0; i < n; ++i) total += d2[i];
+    u = rng_uniform(s, draw++);
+    if (total == 0.0) {
+      out[c] = out[c - 1];
+      continue;
+    }
+    const double target = u * total;
+    double cum = 0.0;
+    int64_t pick = n - 1;
+    for (int64_t i = 0; i < n; ++i) {
+      cum += d2[i];
+      if (cum > target) {
+        pick = i;
+        break;
+      }
+    }
+    out[c] = x[pick];
+    for (int64_t i = 0; i < n; ++i) {
+      const double e = (x[i] - x[pick]) * (x[i] - x[pick]);
+      if (e < d2[i]) d2[i] = e;
+    }
+  }
+}
+
+void lloyd(const double* x, int64_t n, int k, double* c, int32_t* lab_out, int max_iter) {
+  std::vector<int32_t> lab(n, -1), nl(n);
+  for (int it = 0; it < max_iter; ++it) {
+    for (int64_t i = 0; i < n; ++i) nl[i] = nearest(c, k, x[i]);
+    if (it > 0 && nl == lab) break;
+    lab = nl;
+    for (int j = 0; j < k; ++j) {
+      double sum = 0.0;
+      int64_t cnt = 0;
+      for (int64_t i = 0; i < n; ++i)
+        if (lab[i] == j) {
+          sum += x[i];
+          ++cnt;
+        }
+      if (cnt > 0) c[j] = sum / (double)cnt;
+    }
+  }
+  if (lab_out)
+    for (int64_t i = 0; i < n; ++i) lab_out[i] = lab[i];
+}
+
+// ------------------------------------------------------------------ validation
+
+int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
+                 const int64_t* off, const int64_t* cnt, const double* th, const double* rs,
+                 int32_t* scase, int32_t* sexact, int32_t* scand, int32_t* chosen) {
+  int64_t total = 0;
+  for (int64_t j = 0; j < ns; ++j) total = std::max(total, off[j] + cnt[j]);
+  for (int64_t t = 0; t < total; ++t) chosen[t] = 0;
+  int64_t nval = 0;
+  struct Cand {
+    double v, r, dist;
+    int64_t idx;
+  };
+  std::vector<Cand> cs;
+  for (int64_t s = 0; s <= ns; ++s) {
+    const double lo = (s == 0) ? -std::numeric_limits<double>::infinity() : sig[s - 1];
+    const double hi = (s == ns) ? omega_top : sig[s];
+    const int64_t nlo = (s == 0) ? 0 : nu[s - 1];
+    const int64_t nhi = (s == ns) ? nu_top : nu[s];
+    const int64_t n_exact = nhi - nlo;
+    cs.clear();
+    auto add = [&](int64_t p, double a, double b, bool lo_closed, bool hi_closed) {
+      for (int64_t q = 0; q < cnt[p]; ++q) {
+        const int64_t t = off[p] + q;
+        const double v = th[t];
+        const bool in_lo = lo_closed ? (v >= a) : (v > a);
+        const bool in_hi = hi_closed ? (v <= b) : (v < b);
+        if (in_lo && in_hi) cs.push_back({v, rs[t], std::fabs(v - sig[p]), t});
+      }
+    };
+    if (s == 0) {
+      add(0, lo, hi, false, false);
+    } else if (s == ns) {
+      add(ns - 1, lo, hi, true, false);
+    } else {
+      const double tau = 0.5 * (lo + hi);
+      add(s - 1, lo, tau, true, true);  // a value at tau belongs to the lower probe
+      add(s, tau, hi, false, false);
+    }
+    const int64_t n_cand = (int64_t)cs.size();
+    int32_t cse = 0;
+    if (n_exact > n_cand) cse = 1;
+    if (n_exact < n_cand) {
+      cse = 2;
+      std::sort(cs.begin(), cs.end(), [](const Cand& a, const Cand& b) {
+        if (a.r != b.r) return a.r < b.r;
+        if (a.dist != b.dist) return a.dist < b.dist;
+        return a.v < b.v;
+      });
+      cs.resize(std::max<int64_t>(n_exact, 0));
+    }
+    for (const auto& c : cs) {
+      chosen[c.idx] = 1;
+      ++nval;
+    }
+    if (scase) scase[s] = cse;
+    if (sexact) sexact[s] = (int32_t)n_exact;
+    if (scand) scand[s] = (int32_t)n_cand;
+  }
+  return nval;
+}
+
+}  // namespace sislice
+
+using namespace sislice;
+
+extern "C" {
+
+uint64_t sislice_splitmix64(uint64_t seed, uint64_t i) { return splitmix64(seed, i); }
+
+double sislice_kpm_cdos(const double* mu, int32_t M, double a, double b, int64_t n, double omega) {
+  if (!mu || M <= 0 || !(b > a)) return std::numeric_limits<double>::quiet_NaN();
+  std::vector<double> g(M);
+  jackson(M, g.data());
+  return kpm_cdos(mu, g.data(), M, a, b, n, omega);
+}
+
+sislice_status sislice_kpm_place(const double* mu, int32_t M, double a, double b, int64_t n,
+                                 int64_t n_e, int64_t n_s, double top_margin, double* sigmas,
+                                 double* omega_top) {
+  if (!mu || !sigmas || !omega_top || M <= 0 || !(b > a) || n_s <= 0 || n_e <= 0 || n_e > n)
+    return SISLICE_ERR_ARG;
+  kpm_place(mu, M, a, b, n, n_e, n_s, top_margin, sigmas, omega_top);
+  return SISLICE_OK;
+}
+
+sislice_status sislice_kmeans_shifts(const double* ritz, int64_t n, const double* prev_shifts,
+                                     int64_t n_s, int32_t use_kmeanspp, uint64_t seed,
+                                     double* new_shifts, int32_t* labels) {
+  if (!ritz || !new_shifts || n <= 0 || n_s <= 0 || n_s > n) return SISLICE_ERR_ARG;
+  if (!use_kmeanspp && !prev_shifts) return SISLICE_ERR_ARG;
+  std::vector<double> c(n_s);
+  if (use_kmeanspp)
+    kmeanspp(ritz, n, (int)n_s, seed, c.data());
+  else
+    for (int64_t j = 0; j < n_s; ++j) c[j] = prev_shifts[j];
+  std::sort(c.begin(), c.end());
+  lloyd(ritz, n, (int)n_s, c.data(), labels, 300);
+  // labels refer to the sorted initial order; the final centroids keep that order
+  // unless two crossed, so report them sorted together with relabelled members
+  std::vector<int> order(n_s);
+  for (int64_t j = 0; j < n_s; ++j) order[j] = (int)j;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c[a] < c[b]; });
+  std::vector<int> rank(n_s);
+  for (int64_t j = 0; j < n_s; ++j) {
+    new_shifts[j] = c[order[j]];
+    rank[order[j]] = (int)j;
+  }
+  if (labels)
+    for (int64_t i = 0; i < n; ++i) labels[i] = rank[labels[i]];
+  return SISLICE_OK;
+}
+
+int64_t sislice_validate(int64_t n_s, const double* sigmas, const int64_t* nu, double omega_top,
+                         int64_t nu_top, const int64_t* offsets, const int64_t* counts,
+                         const double* thetas, const double* resids, int32_t* slice_case,
+                         int32_t* slice_exact, int32_t* slice_cand, int32_t* chosen) {
+  if (n_s <= 0 || !sigmas || !nu || !offsets || !counts || !chosen) return SISLICE_ERR_ARG;
+  for (int64_t j = 0; j < n_s; ++j)
+    if (counts[j] > 0 && (!thetas || !resids)) return SISLICE_ERR_ARG;
+  return validate(n_s, sigmas, nu, omega_top, nu_top, offsets, counts, thetas, resids, slice_case,
+                  slice_exact, slice_cand, chosen);
+}
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// Host-side planning helpers (validation, KPM CDOS, k-means, SplitMix64).
+#pragma once
+
+#include <cstdint>
+
+#include "sislice.h"
+
+namespace sislice {
+
+// Sub-stream tags of the SplitMix64 draws (seed of a stream = output 0 of seed ^ tag).
+constexpr uint64_t kTagKpm = 0x4B504Dull;        // Rademacher probe vectors
+constexpr uint64_t kTagBounds = 0x424E44ull;     // spectral-bounds Lanczos start
+constexpr uint64_t kTagLanczos = 0x4C4E43ull;    // probe start blocks (^ shift index << 32)
+constexpr uint64_t kTagKmeansPP = 0x4B4D50ull;   // k-means++ seeding
+
+uint64_t splitmix64(uint64_t seed, uint64_t i);
+double rng_uniform(uint64_t seed, uint64_t i);
+uint64_t rng_derive(uint64_t seed, uint64_t tag);
+
+void jackson(int M, double* g);
+double kpm_cdos(const double* mu, const double* g, int M, double a, double b, int64_t n,
+                double omega);
+void kpm_place(const double* mu, int M, double a, double b, int64_t n, int64_t n_e, int64_t n_s,
+               double top_margin, double* sigmas, double* omega_top);
+void kmeanspp(const double* x, int64_t n, int k, uint64_t seed, double* out);
+void lloyd(const double* x, int64_t n, int k, double* c, int32_t* lab, int max_iter);
+int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
+                 const int64_t* off, const int64_t* cnt, const double* th, const double* rs,
+                 int32_t* scase, int32_t* sexact, int32_t* scand, int32_t* chosen);
+
+}  // namespace sislice

@@ -1,0 +1,298 @@
+// Shift-invert application X = C^{-1} Y = P^T L^{-T} D^{-1} L^{-1} P Y through the
+// factors of the Bunch-Kaufman LDL^T (Algorithm 2, third step), for several
+// shifts at once.
+//
+// Design (gfx950): the triangular solves are dependency chains over row blocks
+// of 64.  Each solve is one persistent launch per direction: workgroups take
+// row blocks in dependency order from a per-shift ticket counter (so a block
+// only ever waits for blocks already owned by running workgroups), accumulate
+// the off-diagonal contributions of finished blocks as their epoch flags appear
+// (agent-scope release/acquire), and finish their block with a precomputed
+// inverse of the 64x64 unit-lower diagonal block, so the critical path per
+// block is one flag hand-off plus a 64x64 GEMV.  L is read once per direction.
+// The block-diagonal D^{-1} (1x1 and 2x2 pivots) is applied at the start of the
+// backward sweep.
+#include "common.hpp"
+#include "solve.hpp"
+
+namespace sislice {
+
+constexpr int SB = kSolveBlock;  // 64 rows per block
+
+// perm p(i) and pivot-block flags (1: 1x1, 2: first row of 2x2, 0: second row)
+// from the documented ipiv format.
+__global__ __launch_bounds__(256) void k_solve_prep(int n, const int* const* ipivs,
+                                                    int* const* perms, int* const* blks) {
+  const int s = blockIdx.y;
+  const int* ipiv = ipivs[s];
+  int* perm = perms[s];
+  int* blk = blks[s];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int v = ipiv[i];
+    perm[i] = v >= 0 ? v : -v - 1;
+    if (v >= 0) {
+      blk[i] = 1;
+    } else {
+      int run = 0;  // consecutive 2x2 rows before i
+      for (int q = i - 1; q >= 0 && ipiv[q] < 0; --q) ++run;
+      blk[i] = (run & 1) ? 0 : 2;
+    }
+  }
+}
+
+__device__ __forceinline__ double lval(const double* LD, long ldld, const int* blk, int row,
+                                       int col) {
+  // strictly lower L entry (row > col); inside a 2x2 pivot block the slot holds
+  // D's off-diagonal and L's entry is a structural zero
+  if (row == col + 1 && blk[col] == 2) return 0.0;
+  return LD[row + (long)col * ldld];
+}
+
+// Inverse of each 64x64 unit-lower diagonal block of L (rows past n: identity).
+// Linv layout per shift: block b at b*SB*SB, column-major 64x64.
+__global__ __launch_bounds__(64) void k_diag_inv_blk(int n, const double* const* LDs, long ldld,
+                                                     const int* const* blks, double* const* Linvs) {
+  __shared__ double sL[SB][SB + 1];
+  __shared__ double sX[SB][SB + 1];  // sX[c][i] = X(i, c)
+  const int b = blockIdx.x, s = blockIdx.y, t = threadIdx.x;
+  const double* LD = LDs[s];
+  const int* blk = blks[s];
+  const int r0 = b * SB;
+  for (int k = 0; k < SB; ++k) {
+    const int col = r0 + k, row = r0 + t;
+    double v = 0.0;
+    if (t > k && row < n) v = lval(LD, ldld, blk, row, col);
+    sL[t][k] = v;
+  }
+  __syncthreads();
+  const int c = t;
+  for (int i = 0; i < SB; ++i) {
+    double acc = (i == c) ? 1.0 : 0.0;
+    for (int k = 0; k < i; ++k) acc -= sL[i][k] * sX[c][k];
+    sX[c][i] = (i >= c) ? acc : 0.0;
+  }
+  __syncthreads();
+  double* Linv = Linvs[s] + (long)b * SB * SB;
+  for (int k = 0; k < SB; ++k) Linv[t + k * SB] = sX[k][t];
+}
+
+__device__ __forceinline__ unsigned ticket(unsigned* ctr, unsigned nblk) {
+  __shared__ unsigned t;
+  if (threadIdx.x == 0) {
+    t = atomicAdd(ctr, 1u);
+    if (t == nblk - 1) atomicExch(ctr, 0u);  // last taker resets for the next launch
+  }
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ void wait_flag(const unsigned* flag, unsigned epoch) {
+  if (threadIdx.x == 0) {
+    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+      __builtin_amdgcn_s_sleep(1);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void post_flag(unsigned* flag, unsigned epoch) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Forward sweep: Z = L^{-1} P Y.  256 threads; thread (i = tid % 64, q = tid / 64)
+// owns rows i of columns q, q+4, ... of the block.
+__global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
+  __shared__ double sM[SB][SB + 1];   // an L block or the diagonal inverse
+  __shared__ double sZ[kSolveMaxRhs][SB];
+  const int s = blockIdx.y, tid = threadIdx.x;
+  const int i = tid & 63, q0 = tid >> 6;
+  const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
+  const unsigned b = ticket(a.ctr + s, nblk);
+  const double* LD = a.LD[s];
+  const int* blk = a.blk[s];
+  const int* perm = a.perm[s];
+  const double* Y = a.Y[s];
+  double* Z = a.Z[s];
+  unsigned* flags = a.flags + (long)s * a.flag_stride;
+  const int r0 = b * SB;
+  double acc[kSolveMaxRhs / 4];
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    acc[m] = (c < nrhs && r0 + i < n) ? Y[perm[r0 + i] + (long)c * a.ldy] : 0.0;
+  }
+  for (int cb = 0; cb < (int)b; ++cb) {
+    wait_flag(flags + cb, a.epoch);
+    const int c0 = cb * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int rr = e & 63, kk = e >> 6;  // rows contiguous
+      const int row = r0 + rr, col = c0 + kk;
+      sM[rr][kk] = (row < n) ? lval(LD, a.ldld, blk, row, col) : 0.0;
+    }
+    for (int e = tid; e < nrhs * SB; e += 256) {
+      const int rr = e & 63, c = e >> 6;
+      sZ[c][rr] = Z[c0 + rr + (long)c * a.ldz];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double t = acc[m];
+        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
+        acc[m] = t;
+      }
+    }
+    __syncthreads();
+  }
+  // diagonal block: Z_b = Linv_b * acc
+  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int rr = e & 63, kk = e >> 6;
+    sM[rr][kk] = Linv[rr + kk * SB];
+  }
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    if (c < nrhs) sZ[c][i] = acc[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    if (c < nrhs && r0 + i < n) {
+      double t = 0.0;
+      for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
+      Z[r0 + i + (long)c * a.ldz] = t;
+    }
+  }
+  post_flag(flags + b, a.epoch);
+}
+
+// Backward sweep: X = P^T L^{-T} D^{-1} Z.
+__global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
+  __shared__ double sM[SB][SB + 1];
+  __shared__ double sV[kSolveMaxRhs][SB];
+  const int s = blockIdx.y, tid = threadIdx.x;
+  const int i = tid & 63, q0 = tid >> 6;
+  const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
+  const unsigned t = ticket(a.ctr + s, nblk);
+  const int b = nblk - 1 - (int)t;
+  const double* LD = a.LD[s];
+  const int* blk = a.blk[s];
+  const int* perm = a.perm[s];
+  const double* Z = a.Z[s];
+  double* V = a.V[s];
+  double* X = a.X[s];
+  unsigned* flags = a.flags + (long)s * a.flag_stride + nblk;
+  const int r0 = b * SB;
+  const int row = r0 + i;
+  double acc[kSolveMaxRhs / 4];
+  // D^{-1} on this block's rows
+  double d11 = 1.0, d21 = 0.0, d22 = 1.0;
+  int bt = 1, partner = row;
+  if (row < n) {
+    bt = blk[row];
+    if (bt == 2) partner = row + 1;
+    if (bt == 0) partner = row - 1;
+    if (bt == 1) {
+      d11 = LD[row + (long)row * a.ldld];
+    } else {
+      const int k = bt == 2 ? row : row - 1;
+      d11 = LD[k + (long)k * a.ldld];
+      d21 = LD[k + 1 + (long)k * a.ldld];
+      d22 = LD[k + 1 + (long)(k + 1) * a.ldld];
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    double v = 0.0;
+    if (c < nrhs && row < n) {
+      const double z = Z[row + (long)c * a.ldz];
+      if (bt == 1) {
+        v = (d11 != 0.0) ? z / d11 : 0.0;
+      } else {
+        const double zp = Z[partner + (long)c * a.ldz];
+        // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
+        const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
+        const double aa = d11 / d21, gg = d22 / d21;
+        const double tt = 1.0 / (d21 * (aa * gg - 1.0));
+        v = bt == 2 ? tt * (gg * z1 - z2) : tt * (aa * z2 - z1);
+      }
+    }
+    acc[m] = v;
+  }
+  for (int cb = nblk - 1; cb > b; --cb) {
+    wait_flag(flags + cb, a.epoch);
+    const int c0 = cb * SB;
+    // sM[kk][rr] = L(c0 + kk, r0 + rr): columns of this block, rows of block cb
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int kk = e & 63, rr = e >> 6;
+      const int lrow = c0 + kk, lcol = r0 + rr;
+      sM[kk][rr] = (lrow < n) ? lval(LD, a.ldld, blk, lrow, lcol) : 0.0;
+    }
+    for (int e = tid; e < nrhs * SB; e += 256) {
+      const int kk = e & 63, c = e >> 6;
+      sV[c][kk] = (c0 + kk < n) ? V[c0 + kk + (long)c * a.ldz] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double tt = acc[m];
+        for (int k = 0; k < SB; ++k) tt -= sM[k][i] * sV[c][k];
+        acc[m] = tt;
+      }
+    }
+    __syncthreads();
+  }
+  // V_b = Linv_b^T * acc
+  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+  for (int e = tid; e < SB * SB; e += 256) {
+    const int rr = e & 63, kk = e >> 6;
+    sM[rr][kk] = Linv[rr + kk * SB];
+  }
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    if (c < nrhs) sV[c][i] = acc[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    const int c = q0 + 4 * m;
+    if (c < nrhs && row < n) {
+      double tt = 0.0;
+      for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
+      V[row + (long)c * a.ldz] = tt;
+      X[perm[row] + (long)c * a.ldx] = tt;
+    }
+  }
+  post_flag(flags + b, a.epoch);
+}
+
+void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_perm,
+                       int* const* d_blk, const double* const* d_LD, long ldld,
+                       double* const* d_Linv, hipStream_t st) {
+  hipLaunchKernelGGL(k_solve_prep, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n, d_ipiv,
+                     d_perm, d_blk);
+  SL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_diag_inv_blk, dim3((unsigned)ceil_div(n, SB), S), dim3(64), 0, st, n, d_LD,
+                     ldld, (const int* const*)d_blk, d_Linv);
+  SL_LAUNCH_CHECK();
+}
+
+void solve_launch(SolveArgs a, hipStream_t st) {
+  const int nblk = (int)ceil_div(a.n, SB);
+  hipLaunchKernelGGL(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+}
+
+}  // namespace sislice

@@ -1,0 +1,38 @@
+// Multi-shift LDL^T solve kernels (launch interface).
+#pragma once
+
+#include "common.hpp"
+
+namespace sislice {
+
+constexpr int kSolveBlock = 64;    // rows per dependency block
+constexpr int kSolveMaxRhs = 32;   // right-hand sides per launch
+
+struct SolveArgs {
+  int n = 0, nshift = 0, nrhs = 0;
+  unsigned epoch = 0;            // strictly increasing per launch pair
+  const double* const* LD = nullptr;
+  long ldld = 0;
+  const int* const* perm = nullptr;
+  const int* const* blk = nullptr;
+  const double* const* Linv = nullptr;  // nblk * 64 * 64 per shift
+  const double* const* Y = nullptr;     // input  n x nrhs (ldy)
+  long ldy = 0;
+  double* const* X = nullptr;           // output n x nrhs (ldx); may alias Y
+  long ldx = 0;
+  double* const* Z = nullptr;           // scratch n x nrhs (ldz)
+  double* const* V = nullptr;           // scratch n x nrhs (ldz)
+  long ldz = 0;
+  unsigned* flags = nullptr;            // nshift * flag_stride (>= 2 * nblk), zero-initialised once
+  long flag_stride = 0;
+  unsigned* ctr = nullptr;              // nshift ticket counters, zero-initialised once
+};
+
+void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_perm,
+                       int* const* d_blk, const double* const* d_LD, long ldld,
+                       double* const* d_Linv, hipStream_t st);
+void solve_launch(SolveArgs a, hipStream_t st);
+
+inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
+
+}  // namespace sislice

@@ -1,0 +1,102 @@
+"""GPU parity of the Bunch-Kaufman LDL^T + inertia kernels against the oracle.
+
+Inertia must be bit-exact: equal to the oracle's own factorization, to the exact
+count #{lambda < sigma} of the constructed pencils and to brute-force eigenvalue
+counts.  The factors are checked through the backward error and the documented
+layout (the pivot sequence itself may differ from the oracle's on near-ties).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bk
+from paper_1908_06043_amd import inputs
+from tests.gpu_helpers import backward_error, decode_factor, inertia_of
+
+pytestmark = pytest.mark.gpu
+U = np.finfo(np.float64).eps / 2
+
+
+def dev(M):
+    return torch.from_numpy(np.ascontiguousarray(M)).cuda()
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (7, 2), (31, 3), (32, 4), (33, 5), (64, 6),
+                                    (65, 7), (200, 8), (333, 9), (517, 10)])
+def test_random_symmetric_inertia_and_backward_error(gpu_lib, n, seed):
+    C = inputs.random_symmetric(n, seed)
+    I = np.eye(n)
+    f = gpu_lib.ldlt_factor(dev(C), dev(I), 0.0)
+    w = np.linalg.eigvalsh(C)
+    exact = (int(np.sum(w < 0)), 0, int(np.sum(w > 0)))
+    assert f.inertia == exact
+    assert f.inertia == bk.inertia(bk.bk_ldlt(C))
+    LD = f.LD.cpu().numpy()
+    ip = f.ipiv.cpu().numpy()
+    assert backward_error(C, LD, ip) <= 100 * n * U
+    L, D, perm, blocks = decode_factor(LD, ip)
+    assert inertia_of(D) == f.inertia
+
+
+def test_pencil_n200_inertia_matches_construction_and_oracle(gpu_lib):
+    P = inputs.pencil_clusters4(200, 0)
+    sig = inputs.safe_shifts(P.lam, np.linspace(-2.1, 2.1, 15))
+    facs = gpu_lib.ldlt_factor_multi(dev(P.A), dev(P.B), sig)
+    for s, f in zip(sig, facs):
+        assert f.inertia[0] == int(np.sum(P.lam < s))
+        assert f.inertia == bk.inertia(bk.bk_ldlt(bk.shifted(P.A, P.B, s)))
+        C = bk.shifted(P.A, P.B, s)
+        assert backward_error(C, f.LD.cpu().numpy(), f.ipiv.cpu().numpy()) <= 100 * 200 * U
+
+
+def test_multi_shift_scf_pencil_n1000(gpu_lib):
+    P = inputs.pencil_scf(1000, 100, seed=4)
+    sig = inputs.safe_shifts(P.lam, np.linspace(P.lam[0] - 0.1, P.lam[150], 9))
+    facs = gpu_lib.ldlt_factor_multi(dev(P.A), dev(P.B), sig)
+    assert [f.inertia[0] for f in facs] == [int(np.sum(P.lam < s)) for s in sig]
+    for s, f in zip(sig[::4], facs[::4]):
+        C = bk.shifted(P.A, P.B, s)
+        assert backward_error(C, f.LD.cpu().numpy(), f.ipiv.cpu().numpy()) <= 100 * 1000 * U
+
+
+def test_diagonal_pencil_exact(gpu_lib):
+    a = np.array([3.0, -1.0, 0.75, -2.5, 7.0, 0.25, -0.5, 4.0])
+    P = inputs.pencil_diag(a)
+    f = gpu_lib.ldlt_factor(dev(P.A), dev(P.B), 0.5)
+    LD = f.LD.cpu().numpy()
+    assert np.array_equal(np.diag(LD), a - 0.5)           # bit-exact D
+    assert np.array_equal(f.ipiv.cpu().numpy(), np.arange(8))
+    assert np.all(np.tril(LD, -1) == 0.0)
+    d = a - 0.5
+    assert f.inertia == (int(np.sum(d < 0)), int(np.sum(d == 0)), int(np.sum(d > 0)))
+
+
+def test_singular_shift_reports_zero_pivot(gpu_lib):
+    P = inputs.pencil_diag(np.array([1.0, 2.0, 3.0, 4.0]))
+    f = gpu_lib.ldlt_factor(dev(P.A), dev(P.B), 2.0)
+    assert f.status == 1 and f.inertia == (1, 1, 2)
+
+
+def test_definite_extremes(gpu_lib):
+    P = inputs.pencil_clusters4(120, 5)
+    lo, hi = gpu_lib.ldlt_factor_multi(dev(P.A), dev(P.B), [P.lam[0] - 1.0, P.lam[-1] + 1.0])
+    assert lo.inertia == (0, 0, 120) and hi.inertia == (120, 0, 0)
+
+
+def test_full_size_n4096_seventeen_shifts(gpu_lib):
+    """The benchmark's launch configuration: 16 shifts + boundary at N=4096."""
+    P = inputs.pencil_scf(4096, 400, seed=0)
+    sig = inputs.safe_shifts(P.lam, np.linspace(P.lam[0] - 0.05, P.lam[430], 17))
+    A, B = dev(P.A), dev(P.B)
+    facs = gpu_lib.ldlt_factor_multi(A, B, sig)
+    assert [f.inertia[0] for f in facs] == [int(np.sum(P.lam < s)) for s in sig]
+    assert all(f.inertia[1] == 0 and sum(f.inertia) == 4096 for f in facs)
+    # sampled backward error through matrix-vector products on the CPU
+    rng = np.random.default_rng(0)
+    for s, f in zip(sig[::8], facs[::8]):
+        L, D, perm, _ = decode_factor(f.LD.cpu().numpy(), f.ipiv.cpu().numpy())
+        C = bk.shifted(P.A, P.B, s)
+        x = rng.standard_normal(4096)
+        lhs = C[np.ix_(perm, perm)] @ x
+        rhs = L @ (D @ (L.T @ x))
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(C, 1) * np.linalg.norm(x)

@@ -1,0 +1,100 @@
+"""CPU checks of the C ABI: the library loads and exports every declared entry point,
+and the host-only planner functions agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import kmeans, kpm, prng, validate as oval
+from paper_1908_06043_amd import _lib, api
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HEADER = os.path.join(os.path.dirname(HERE), "include", "sislice.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sislice_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib.EXPORTED)
+
+
+def test_status_strings_and_defaults():
+    lib = _lib.load()
+    for code in (0, -1, -2, -3, -4, 1, 2, 3):
+        assert lib.sislice_status_string(code)
+    o = api.default_opts()
+    assert (o.block, o.max_basis, o.kpm_moments, o.kpm_vectors, o.tol) == (8, 112, 64, 20, 1e-10)
+
+
+def test_splitmix64_matches_oracle():
+    for seed in (0, 1, 12345, 2**63 + 7):
+        for i in (0, 1, 2, 1000):
+            assert api.splitmix64(seed, i) == prng.splitmix64(seed, i)
+
+
+def test_kpm_cdos_and_placement_match_oracle():
+    rng = np.random.default_rng(0)
+    mu = np.concatenate([[1.0], rng.normal(0, 0.05, 63) / (1 + np.arange(63))])
+    a, b, n = -5.2, 5.3, 4096
+    g = kpm.jackson(64)
+    for w in np.linspace(a, b, 17):
+        assert api.kpm_cdos(mu, a, b, n, w) == pytest.approx(kpm.cdos(w, mu, g, a, b, n), abs=1e-9)
+    sig, top = api.kpm_place(mu, a, b, n, 400, 16, 2.0)
+    osig, _, otop = kpm.place_shifts(mu, a, b, n, 400, 16, 2.0)
+    assert np.allclose(sig, osig, rtol=0, atol=1e-10) and top == pytest.approx(otop, abs=1e-10)
+
+
+def test_kmeans_matches_oracle_bit_for_bit():
+    rng = np.random.default_rng(1)
+    x = np.sort(np.concatenate([rng.normal(c, 0.07, 40) for c in (-3, -1.2, 0.4, 2.5)]))
+    prev = np.array([-3.5, -1.0, 0.0, 3.0])
+    c, lab = api.kmeans_shifts(x, prev)
+    oc, olab = kmeans.migrate(x, prev)
+    assert np.array_equal(c, oc) and np.array_equal(lab, olab)
+    c, lab = api.kmeans_shifts(x, n_s=6, use_kmeanspp=True, seed=7)
+    oc, olab = kmeans.migrate(x, np.zeros(6), use_kmeanspp=True, seed=7)
+    assert np.array_equal(c, oc)
+
+
+def test_validation_matches_oracle():
+    rng = np.random.default_rng(2)
+    lam = np.sort(rng.uniform(-3, 3, 60))
+    sig = np.array([-2.0, -0.7, 0.5, 1.9])
+    top = 2.6
+    nus = [int(np.sum(lam < s)) for s in sig]
+    nut = int(np.sum(lam < top))
+    th, rs = [], []
+    for j, s in enumerate(sig):
+        lo = sig[j - 1] if j else -np.inf
+        hi = sig[j + 1] if j + 1 < len(sig) else top
+        t = lam[(lam > lo) & (lam < hi)].copy()
+        if j == 1:
+            t = np.concatenate([t[:-2], [t[0] + 1e-3]])          # a missing value and a spurious one
+        r = rng.uniform(0, 1e-12, t.size)
+        th.append(t)
+        rs.append(r)
+    out = api.validate(sig, nus, th, rs, top, nut)
+    ref = oval.validate(sig, nus, th, rs, top, nut)
+    assert list(out["slice_case"]) == [s["case"] for s in ref["slices"]]
+    assert list(out["slice_exact"]) == [s["n_exact"] for s in ref["slices"]]
+    assert list(out["slice_cand"]) == [s["n_cand"] for s in ref["slices"]]
+    flat = np.concatenate(th)
+    got = np.sort(flat[out["chosen"] == 1])
+    assert np.array_equal(got, np.array([v[0] for v in ref["validated"]]))
+
+
+def test_gpu_entry_points_refuse_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        api.handle()
