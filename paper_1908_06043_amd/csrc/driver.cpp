@@ -1,0 +1,1237 @@
+// The plain per-pencil path (Algorithm 1, one pass on a fixed pencil) and the
+// KPM shift planner (Section 3.1), orchestrating the device kernels.
+//
+//  1. Factor A - sigma_j B for every shift and the top boundary together and read
+//     the inertias (Section 2.2) -- all counts are known before any iteration.
+//  2. Per shift, block shift-invert Lanczos in the B inner product (block 8):
+//     W = (A - sigma B)^{-1} U_last, full B-reorthogonalisation against the
+//     locked and active bases (twice), Z = B W for all shifts in one GEMM,
+//     CholeskyQR2, projected matrix T from the projections.  Probes advance in
+//     lock step; when the active basis is full, eig(T) gives Ritz pairs and
+//     residual estimates; converged pairs inside the probe's window
+//     (sigma_{j-1}, sigma_{j+1}) are locked, the best unconverged ones are kept
+//     (thick restart).  A probe stops once both of its slices hold as many
+//     locked values as their exact counts.
+//  3. Explicit Rayleigh-Ritz with A on the locked vectors (Section 2.1),
+//     residuals, slice validation (Section 2.2), lowest n_e out.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <vector>
+
+#include "blas.hpp"
+#include "eig.hpp"
+#include "factor_api.hpp"
+#include "handle.hpp"
+#include "lanczos.hpp"
+#include "planner.hpp"
+#include "solve.hpp"
+
+namespace sislice {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// Pinned host ring + device ring for the small per-launch tables.
+class Ring {
+ public:
+  explicit Ring(sislice_handle* h, size_t cap = 16u << 20) : h_(h), cap_(cap) {
+    if (h->ring_cap < cap) {
+      if (h->ring_host) {
+        SL_HIP(hipStreamSynchronize(h->stream));
+        SL_HIP(hipHostFree(h->ring_host));
+        h->ring_host = nullptr;
+        h->ring_cap = 0;
+      }
+      SL_HIP(hipHostMalloc(&h->ring_host, cap, hipHostMallocDefault));
+      h->ring_cap = cap;
+    }
+    host_ = static_cast<char*>(h->ring_host);
+    dev_ = static_cast<char*>(ws_get(h, kBufRing, cap));
+  }
+  void* put(const void* src, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    const size_t b = (bytes + 255) & ~size_t(255);
+    SL_CHECK_ARG(b <= cap_, "table too large for the upload ring");
+    if (off_ + b > cap_) {
+      SL_HIP(hipStreamSynchronize(h_->stream));
+      off_ = 0;
+    }
+    if (src)
+      std::memcpy(host_ + off_, src, bytes);
+    else
+      std::memset(host_ + off_, 0, bytes);
+    SL_HIP(hipMemcpyAsync(dev_ + off_, host_ + off_, bytes, hipMemcpyHostToDevice, h_->stream));
+    void* r = dev_ + off_;
+    off_ += b;
+    return r;
+  }
+  template <class T>
+  T* vec(const std::vector<T>& v) {
+    return static_cast<T*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T)));
+  }
+  template <class T>
+  T* const* ptrs(const std::vector<T*>& v) {
+    return reinterpret_cast<T* const*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
+  }
+  template <class T>
+  const T* const* cptrs(const std::vector<T*>& v) {
+    return reinterpret_cast<const T* const*>(
+        put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
+  }
+  void synced() { off_ = 0; }
+
+ private:
+  sislice_handle* h_;
+  size_t cap_;
+  char* host_;
+  char* dev_;
+  size_t off_ = 0;
+};
+
+struct Ctx {
+  sislice_handle* h;
+  hipStream_t st;
+  Ring* ring;
+};
+
+// Batched GEMM helper: per-batch sizes, pointer tables through the ring,
+// split-K (ordered partials) when the reduction is long and the output small.
+void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std::vector<int>& nn,
+          const std::vector<int>& k, const std::vector<const double*>& A, long lda,
+          const std::vector<const double*>& B, long ldb, const std::vector<double*>& C, long ldc,
+          double alpha, double beta) {
+  const int batch = (int)m.size();
+  if (batch == 0) return;
+  int mmax = 0, nmax = 0, kmax = 0;
+  for (int b = 0; b < batch; ++b) {
+    mmax = std::max(mmax, m[b]);
+    nmax = std::max(nmax, nn[b]);
+    kmax = std::max(kmax, k[b]);
+  }
+  if (mmax == 0 || nmax == 0) return;
+  GemmArgs g;
+  g.m = c.ring->vec(m);
+  g.n = c.ring->vec(nn);
+  g.k = c.ring->vec(k);
+  g.A = c.ring->cptrs(A);
+  g.lda = lda;
+  g.B = c.ring->cptrs(B);
+  g.ldb = ldb;
+  g.C = c.ring->ptrs(C);
+  g.ldc = ldc;
+  g.alpha = alpha;
+  g.beta = beta;
+  int splits = 1;
+  const long tiles = ceil_div(mmax, 64) * ceil_div(nmax, 64) * (long)batch;
+  if (kmax >= 1024 && tiles < 512) {
+    splits = (int)std::min<long>(std::max<long>(1, 1024 / tiles), kmax / 256);
+    splits = std::max(1, std::min(splits, 64));
+  }
+  g.splits = splits;
+  if (splits > 1)
+    g.partial = static_cast<double*>(
+        ws_get(c.h, kBufMisc, sizeof(double) * (size_t)batch * splits * mmax * nmax));
+  gemm_launch(g, batch, mmax, nmax, ta, tb, c.st);
+}
+
+struct ProbeHost {
+  double sigma = 0, lo = 0, hi = 0;
+  int64_t need = 0;
+  int mq = 0;        // active basis columns incl. the newest block
+  int nl = 0;        // locked columns
+  bool active = true;
+  bool broke = false;
+  int cycles = 0;
+  int steps = 0;
+  std::vector<double> lock_lam;
+};
+
+void check_opts(const sislice_opts& o) {
+  SL_CHECK_ARG(o.block == kLanczosBlock, "only block size 8 is built");
+  SL_CHECK_ARG(o.max_basis >= 32 && o.max_basis <= kEigMax && o.max_basis % kLanczosBlock == 0,
+               "max_basis must be a multiple of 8 in [32, 112]");
+  SL_CHECK_ARG(o.max_cycles >= 1, "max_cycles must be positive");
+  SL_CHECK_ARG(o.kpm_moments >= 4 && o.kpm_moments <= 4096, "kpm_moments out of range");
+  SL_CHECK_ARG(o.kpm_vectors >= 1 && o.kpm_vectors <= kSolveMaxRhs, "kpm_vectors in [1, 32]");
+  SL_CHECK_ARG(o.bounds_steps >= 2 && o.bounds_steps <= 100, "bounds_steps in [2, 100]");
+  SL_CHECK_ARG(o.tol > 0 && o.tol < 1, "tol in (0, 1)");
+}
+
+// ||M||_2 of a symmetric full matrix by block power iteration with a final
+// Rayleigh-Ritz on 8 vectors (a lower bound that converges quickly; only a
+// tolerance scale is needed).
+double sym_norm2(Ctx& c, int n, const double* M, double* X, double* Y, double* G, double* R,
+                 double* H, double* Wv, double* Vv, int* flag, int* active1, uint64_t seed) {
+  const int b = kLanczosBlock;
+  std::vector<unsigned long long> sd{rng_derive(seed, 0x4E524Dull)};
+  gauss_launch(n, b, 1, c.ring->vec(sd), c.ring->ptrs(std::vector<double*>{X}), n, c.st);
+  for (int it = 0; it < 12; ++it) {
+    gemm(c, false, false, {n}, {b}, {n}, {M}, n, {X}, n, {Y}, n, 1.0, 0.0);
+    gemm(c, true, false, {b}, {b}, {n}, {Y}, n, {Y}, n, {G}, b, 1.0, 0.0);
+    CholQrArgs q;
+    q.n = n;
+    q.active = active1;
+    q.G = c.ring->cptrs(std::vector<double*>{G});
+    q.Vin = c.ring->cptrs(std::vector<double*>{Y});
+    q.Uin = q.Vin;
+    q.ldin = n;
+    q.Vout = c.ring->ptrs(std::vector<double*>{X});
+    q.Uout = c.ring->ptrs(std::vector<double*>{Y});
+    q.ldout = n;
+    q.R = c.ring->ptrs(std::vector<double*>{R});
+    q.flag = flag;
+    cholqr_launch(q, 1, c.st);
+  }
+  gemm(c, false, false, {n}, {b}, {n}, {M}, n, {X}, n, {Y}, n, 1.0, 0.0);
+  gemm(c, true, false, {b}, {b}, {n}, {X}, n, {Y}, n, {H}, b, 1.0, 0.0);
+  EigArgs e;
+  e.m = c.ring->vec(std::vector<int>{b});
+  e.A = c.ring->cptrs(std::vector<double*>{H});
+  e.lda = b;
+  e.W = c.ring->ptrs(std::vector<double*>{Wv});
+  e.V = c.ring->ptrs(std::vector<double*>{Vv});
+  e.ldv = b;
+  eig_launch(e, 1, b, c.st);
+  double w[kLanczosBlock];
+  SL_HIP(hipMemcpyAsync(w, Wv, sizeof(w), hipMemcpyDeviceToHost, c.st));
+  SL_HIP(hipStreamSynchronize(c.st));
+  c.ring->synced();
+  double mx = 0.0;
+  for (double v : w) mx = std::max(mx, std::fabs(v));
+  return mx;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- planner
+
+sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                         const sislice_opts& o, double* sig, double* top, double* mom_out,
+                         double* bounds_out) {
+  const int n = (int)n64;
+  const int nv = o.kpm_vectors, M = o.kpm_moments, bs = o.bounds_steps;
+  hipStream_t st = h->stream;
+  Ring ring(h);
+  Ctx c{h, st, &ring};
+  const long nblk = solve_nblk(n);
+  // workspace
+  Sizer z;
+  z.take<double>((size_t)n * n);      // Af
+  z.take<double>((size_t)n * n);      // LD of B
+  z.take<int32_t>(n);                 // ipiv
+  z.take<int>(n);                     // perm
+  z.take<int>(n);                     // blk
+  z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  z.take<double>(n);                  // D^{-1/2}
+  for (int q = 0; q < 7; ++q) z.take<double>((size_t)n * nv);  // t_prev, t_cur, t_next, tmp1..3, V0
+  z.take<double>((size_t)n * (bs + 1));  // Lanczos basis
+  z.take<double>((size_t)n * 4);         // w, misc
+  z.take<double>(4096);                  // small scalars
+  z.take<double>((size_t)(bs + 1) * (bs + 1) * 2);
+  z.take<int>(64);
+  Carver cv(ws_get(h, kBufKpm, z.off));
+  double* Af = cv.take<double>((size_t)n * n);
+  double* LDB = cv.take<double>((size_t)n * n);
+  int32_t* ipB = cv.take<int32_t>(n);
+  int* permB = cv.take<int>(n);
+  int* blkB = cv.take<int>(n);
+  double* LinvB = cv.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  double* dsc = cv.take<double>(n);
+  double* T0 = cv.take<double>((size_t)n * nv);
+  double* T1 = cv.take<double>((size_t)n * nv);
+  double* T2 = cv.take<double>((size_t)n * nv);
+  double* X1 = cv.take<double>((size_t)n * nv);
+  double* X2 = cv.take<double>((size_t)n * nv);
+  double* X3 = cv.take<double>((size_t)n * nv);
+  double* V0 = cv.take<double>((size_t)n * nv);
+  double* Vb = cv.take<double>((size_t)n * (bs + 1));
+  double* wv = cv.take<double>((size_t)n * 4);
+  double* small = cv.take<double>(4096);
+  double* Tm = cv.take<double>((size_t)(bs + 1) * (bs + 1) * 2);
+  int* iflag = cv.take<int>(64);
+  SL_HIP(hipMemsetAsync(iflag, 0, 64 * sizeof(int), st));
+  sym_full_launch(n, A, lda, Af, n, st);
+  // B = L D L^T without interchanges (B is SPD), so L_B = L D^{1/2}
+  {
+    double* lds[1] = {LDB};
+    int32_t* ips[1] = {ipB};
+    double zero = 0.0;
+    FactorPlan fp = build_factor(h, kBufFactor, n, B, ldb, B, ldb, 1, &zero, lds, n, ips,
+                                 default_nb(n), false);
+    factor_launch(fp, st);
+    int64_t inert[3];
+    SL_HIP(hipMemcpyAsync(inert, fp.d_inertia, sizeof(inert), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    if (inert[0] != 0 || inert[1] != 0) throw Error(SISLICE_ERR_ARG, "B is not positive definite");
+  }
+  const double* ldtab[1] = {LDB};
+  const int* iptab[1] = {ipB};
+  (void)iptab;
+  {
+    auto tLD = ring.cptrs(std::vector<double*>{LDB});
+    auto tip = ring.cptrs(std::vector<int32_t*>{ipB});
+    auto tperm = ring.ptrs(std::vector<int*>{permB});
+    auto tblk = ring.ptrs(std::vector<int*>{blkB});
+    auto tLinv = ring.ptrs(std::vector<double*>{LinvB});
+    solve_prep_launch(n, 1, reinterpret_cast<const int* const*>(tip), tperm, tblk, tLD, n, tLinv, st);
+  }
+  (void)ldtab;
+  inv_sqrt_diag_launch(n, LDB, n, dsc, iflag, st);
+  unsigned* sync = sync_words(h, 64 + 2 * nblk);
+  // H Y for k columns: D^{-1/2} L^{-1} A L^{-T} D^{-1/2} Y  (result in out)
+  auto apply_H = [&](const double* Yin, double* out, int k) {
+    SL_HIP(hipMemcpyAsync(X1, Yin, sizeof(double) * n * k, hipMemcpyDeviceToDevice, st));
+    row_scale_launch(n, k, dsc, X1, n, st);
+    SolveArgs a;
+    a.n = n;
+    a.nshift = 1;
+    a.nrhs = k;
+    a.LD = ring.cptrs(std::vector<double*>{LDB});
+    a.ldld = n;
+    a.perm = ring.cptrs(std::vector<int*>{permB});
+    a.blk = ring.cptrs(std::vector<int*>{blkB});
+    a.Linv = ring.cptrs(std::vector<double*>{LinvB});
+    a.flags = sync + 64;
+    a.flag_stride = 2 * nblk;
+    a.ctr = sync;
+    a.applyD = 0;
+    a.ldy = a.ldx = a.ldz = n;
+    // backward sweep reads Z = X1, writes X = X2 (V scratch = X3)
+    a.epoch = next_epoch(h);
+    a.Z = ring.ptrs(std::vector<double*>{X1});
+    a.V = ring.ptrs(std::vector<double*>{X3});
+    a.X = ring.ptrs(std::vector<double*>{X2});
+    a.Y = a.Z;
+    solve_launch(a, st, 2);
+    gemm(c, false, false, {n}, {k}, {n}, {Af}, n, {X2}, n, {X3}, n, 1.0, 0.0);
+    // forward sweep reads Y = X3, writes Z = out
+    a.epoch = next_epoch(h);
+    a.Y = ring.cptrs(std::vector<double*>{X3});
+    a.Z = ring.ptrs(std::vector<double*>{out});
+    a.X = a.Z;
+    solve_launch(a, st, 1);
+    row_scale_launch(n, k, dsc, out, n, st);
+  };
+  // ---- spectral bounds: bs-step Lanczos on H with full reorthogonalisation
+  std::vector<unsigned long long> sdb{rng_derive(o.seed, kTagBounds)};
+  gauss_launch(n, 1, 1, ring.vec(sdb), ring.ptrs(std::vector<double*>{Vb}), n, st);
+  ColDotArgs cd;
+  cd.n = n;
+  cd.ncol0 = 1;
+  cd.mode = 0;
+  cd.partial = static_cast<double*>(ws_get(h, kBufEig, sizeof(double) * coldot_partial_size(n, 1, nv)));
+  auto dot1 = [&](const double* x, const double* y, double* out) {
+    ColDotArgs d = cd;
+    d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+    d.ldx = n;
+    d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+    d.ldy = n;
+    d.out = ring.ptrs(std::vector<double*>{out});
+    coldot_launch(d, 1, 1, st);
+  };
+  double nrm2;
+  dot1(Vb, Vb, small);
+  SL_HIP(hipMemcpyAsync(&nrm2, small, sizeof(double), hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  {
+    std::vector<double> sc(n, 1.0 / std::sqrt(nrm2));
+    double* dsc2 = small + 16;
+    (void)dsc2;
+    // scale the start vector by a uniform factor through a one-column GEMM with a 1x1 matrix
+    double s1 = 1.0 / std::sqrt(nrm2);
+    SL_HIP(hipMemcpyAsync(small + 8, &s1, sizeof(double), hipMemcpyHostToDevice, st));
+    gemm(c, false, false, {n}, {1}, {1}, {Vb}, n, {small + 8}, 1, {wv}, n, 1.0, 0.0);
+    SL_HIP(hipMemcpyAsync(Vb, wv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  }
+  std::vector<double> alpha(bs, 0.0), beta(bs, 0.0);
+  int m = bs;
+  for (int j = 0; j < bs; ++j) {
+    double* vj = Vb + (size_t)j * n;
+    apply_H(vj, wv, 1);
+    dot1(vj, wv, small);
+    for (int pass = 0; pass < 2; ++pass) {
+      // coef = V^T w ; w -= V coef
+      gemm(c, true, false, {j + 1}, {1}, {n}, {Vb}, n, {wv}, n, {small + 64}, j + 1, 1.0, 0.0);
+      gemm(c, false, false, {n}, {1}, {j + 1}, {Vb}, n, {small + 64}, j + 1, {wv}, n, -1.0, 1.0);
+    }
+    dot1(wv, wv, small + 1);
+    double ab[2];
+    SL_HIP(hipMemcpyAsync(ab, small, sizeof(ab), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    alpha[j] = ab[0];
+    beta[j] = std::sqrt(std::max(ab[1], 0.0));
+    if (beta[j] == 0.0) {
+      m = j + 1;
+      break;
+    }
+    if (j + 1 < bs + 1) {
+      const double inv = 1.0 / beta[j];
+      SL_HIP(hipMemcpyAsync(small + 8, &inv, sizeof(double), hipMemcpyHostToDevice, st));
+      gemm(c, false, false, {n}, {1}, {1}, {wv}, n, {small + 8}, 1, {Vb + (size_t)(j + 1) * n}, n,
+           1.0, 0.0);
+    }
+  }
+  // Ritz values of the tridiagonal T_m on the device eigensolver
+  std::vector<double> Th((size_t)m * m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    Th[j + (size_t)j * m] = alpha[j];
+    if (j + 1 < m) Th[(j + 1) + (size_t)j * m] = Th[j + (size_t)(j + 1) * m] = beta[j];
+  }
+  SL_HIP(hipMemcpyAsync(Tm, Th.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, st));
+  double* thv = Tm + (size_t)m * m;
+  double* Sv = small + 256;
+  SL_CHECK_ARG((size_t)m * m + 256 <= 4096, "bounds_steps too large");
+  {
+    EigArgs e;
+    e.m = ring.vec(std::vector<int>{m});
+    e.A = ring.cptrs(std::vector<double*>{Tm});
+    e.lda = m;
+    e.W = ring.ptrs(std::vector<double*>{thv});
+    e.V = ring.ptrs(std::vector<double*>{Sv});
+    e.ldv = m;
+    eig_launch(e, 1, m, st);
+  }
+  std::vector<double> th(m), S((size_t)m * m);
+  SL_HIP(hipMemcpyAsync(th.data(), thv, sizeof(double) * m, hipMemcpyDeviceToHost, st));
+  SL_HIP(hipMemcpyAsync(S.data(), Sv, sizeof(double) * m * m, hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  const double rlo = std::fabs(beta[m - 1] * S[(m - 1) + 0 * (size_t)m]);
+  const double rhi = std::fabs(beta[m - 1] * S[(m - 1) + (size_t)(m - 1) * m]);
+  const double pad = 0.01 * (th[m - 1] - th[0]);
+  const double a = th[0] - rlo - pad, bb = th[m - 1] + rhi + pad;
+  // ---- Chebyshev moments: doubling identities mu_{2k} = 2<t_k,t_k> - mu_0,
+  // mu_{2k+1} = 2<t_{k+1},t_k> - mu_1 with t_k = T_k(H~) v
+  const double cc = 0.5 * (a + bb), dd = 0.5 * (bb - a);
+  rademacher_launch(n, nv, rng_derive(o.seed, kTagKpm), V0, n, st);
+  const int K = M / 2 + 1;  // t_0 .. t_K
+  double* dots = small + 1024;  // [2K+2][nv]
+  SL_CHECK_ARG((size_t)(2 * K + 2) * nv + 1024 <= 4096, "too many moments for the scratch area");
+  ColDotArgs cdv = cd;
+  cdv.ncol0 = nv;
+  auto dotv = [&](const double* x, const double* y, double* out) {
+    ColDotArgs d = cdv;
+    d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+    d.ldx = n;
+    d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+    d.ldy = n;
+    d.out = ring.ptrs(std::vector<double*>{out});
+    coldot_launch(d, 1, nv, st);
+  };
+  // H~ X = (H X - c X) / d via GEMM-free combination on the device:
+  // out = (1/d) H X - (c/d) X, prev-combination for the recurrence
+  auto scaled_step = [&](const double* tcur, const double* tprev, double* tnext, bool first) {
+    apply_H(tcur, X2, nv);  // X2 = H tcur (X2 is free again after apply_H)
+    // tnext = f1 * X2 + f2 * tcur + f3 * tprev   (columnwise, via two 1x1-GEMM updates)
+    const double f1 = first ? 1.0 / dd : 2.0 / dd;
+    const double f2 = first ? -cc / dd : -2.0 * cc / dd;
+    double coefs[3] = {f1, f2, -1.0};
+    SL_HIP(hipMemcpyAsync(small + 32, coefs, sizeof(coefs), hipMemcpyHostToDevice, st));
+    // treat the n x nv blocks as (n*nv) x 1 vectors
+    gemm(c, false, false, {n * nv}, {1}, {1}, {X2}, (long)n * nv, {small + 32}, 1, {tnext},
+         (long)n * nv, 1.0, 0.0);
+    gemm(c, false, false, {n * nv}, {1}, {1}, {tcur}, (long)n * nv, {small + 33}, 1, {tnext},
+         (long)n * nv, 1.0, 1.0);
+    if (!first)
+      gemm(c, false, false, {n * nv}, {1}, {1}, {tprev}, (long)n * nv, {small + 34}, 1, {tnext},
+           (long)n * nv, 1.0, 1.0);
+  };
+  double* tp = T0;
+  double* tc = T1;
+  double* tn = T2;
+  SL_HIP(hipMemcpyAsync(tp, V0, sizeof(double) * n * nv, hipMemcpyDeviceToDevice, st));
+  dotv(tp, tp, dots + 0 * nv);            // <t0,t0>
+  scaled_step(tp, nullptr, tc, true);     // t1
+  dotv(tc, tp, dots + 1 * nv);            // <t1,t0>
+  for (int k = 1; k < K; ++k) {
+    dotv(tc, tc, dots + (2 * k) * nv);    // <t_k,t_k>
+    scaled_step(tc, tp, tn, false);       // t_{k+1}
+    dotv(tn, tc, dots + (2 * k + 1) * nv);  // <t_{k+1},t_k>
+    double* t = tp;
+    tp = tc;
+    tc = tn;
+    tn = t;
+  }
+  std::vector<double> hd((size_t)(2 * K) * nv);
+  SL_HIP(hipMemcpyAsync(hd.data(), dots, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, st));
+  int bad = 0;
+  SL_HIP(hipMemcpyAsync(&bad, iflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  if (bad) throw Error(SISLICE_ERR_ARG, "B is not positive definite");
+  auto total = [&](int q) {
+    double s = 0.0;
+    for (int v = 0; v < nv; ++v) s += hd[(size_t)q * nv + v];
+    return s / ((double)n * nv);
+  };
+  std::vector<double> mu(M, 0.0);
+  const double mu0 = total(0), mu1 = total(1);
+  mu[0] = mu0;
+  if (M > 1) mu[1] = mu1;
+  for (int k = 1; 2 * k < M; ++k) {
+    mu[2 * k] = 2.0 * total(2 * k) - mu0;
+    if (2 * k + 1 < M) mu[2 * k + 1] = 2.0 * total(2 * k + 1) - mu1;
+  }
+  kpm_place(mu.data(), M, a, bb, n, n_e, n_s, o.top_margin, sig, top);
+  if (mom_out)
+    for (int k = 0; k < M; ++k) mom_out[k] = mu[k];
+  if (bounds_out) {
+    bounds_out[0] = a;
+    bounds_out[1] = bb;
+  }
+  return SISLICE_OK;
+}
+
+// ---------------------------------------------------------------- solve
+
+sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                          const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
+                          double* evals, double* evecs, int64_t ldx, double* resid_out,
+                          sislice_report* rep) {
+  const auto t_start = Clock::now();
+  const int n = (int)n64;
+  const int P = (int)n_s;
+  const int b = kLanczosBlock;
+  hipStream_t st = h->stream;
+  std::vector<double> sig(P);
+  double top = 0;
+  double t_plan = 0;
+  if (!sigmas_in) {
+    const auto t0 = Clock::now();
+    plan_impl(h, n64, A, lda, B, ldb, n_e, n_s, o, sig.data(), &top, nullptr, nullptr);
+    t_plan = ms_since(t0);
+  } else {
+    for (int j = 0; j < P; ++j) sig[j] = sigmas_in[j];
+    top = *omega_top_io;
+    for (int j = 1; j < P; ++j) SL_CHECK_ARG(sig[j] > sig[j - 1], "shifts must be ascending");
+    SL_CHECK_ARG(top > sig[P - 1], "omega_top must exceed every shift");
+  }
+  Ring ring(h);
+  Ctx c{h, st, &ring};
+  const int S1 = P + 1;  // shifts + top boundary
+  const long nblk = solve_nblk(n);
+  // ---- factor-phase workspace
+  Sizer z;
+  z.take<double>((size_t)n * n);  // Af
+  z.take<double>((size_t)n * n);  // Bf
+  for (int s = 0; s < S1; ++s) z.take<double>((size_t)n * n);
+  for (int s = 0; s < S1; ++s) z.take<int32_t>(n);
+  for (int s = 0; s < P; ++s) {
+    z.take<int>(n);
+    z.take<int>(n);
+    z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  }
+  z.take<double>(64 * 8);  // norm estimation scratch
+  z.take<double>((size_t)n * 8 * 2);
+  z.take<int>(64);
+  Carver cv(ws_get(h, kBufDriver, z.off));
+  double* Af = cv.take<double>((size_t)n * n);
+  double* Bf = cv.take<double>((size_t)n * n);
+  std::vector<double*> LD(S1);
+  std::vector<int32_t*> ipv(S1);
+  for (int s = 0; s < S1; ++s) LD[s] = cv.take<double>((size_t)n * n);
+  for (int s = 0; s < S1; ++s) ipv[s] = cv.take<int32_t>(n);
+  std::vector<int*> perm(P), blk(P);
+  std::vector<double*> Linv(P);
+  for (int s = 0; s < P; ++s) {
+    perm[s] = cv.take<int>(n);
+    blk[s] = cv.take<int>(n);
+    Linv[s] = cv.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  }
+  double* nsmall = cv.take<double>(64 * 8);
+  double* nX = cv.take<double>((size_t)n * 8 * 2);
+  int* nflag = cv.take<int>(64);
+  // ---- 1. factorizations and inertia
+  const auto t_f0 = Clock::now();
+  sym_full_launch(n, A, lda, Af, n, st);
+  sym_full_launch(n, B, ldb, Bf, n, st);
+  std::vector<double> pts(sig);
+  pts.push_back(top);
+  const int nb = o.nb > 0 ? std::min(o.nb, kMaxNb) : default_nb(n);
+  FactorPlan fp =
+      build_factor(h, kBufFactor, n, A, lda, B, ldb, S1, pts.data(), LD.data(), n, ipv.data(), nb, true);
+  factor_launch(fp, st);
+  std::vector<int64_t> inert(3 * S1);
+  SL_HIP(hipMemcpyAsync(inert.data(), fp.d_inertia, sizeof(int64_t) * 3 * S1, hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  const double t_factor = ms_since(t_f0);
+  for (int s = 0; s < S1; ++s)
+    if (inert[3 * s + 1] != 0) {
+      if (rep) {
+        rep->n_shifts = P;
+        rep->t_factor_ms = t_factor;
+      }
+      return SISLICE_SINGULAR_SHIFT;
+    }
+  std::vector<int64_t> nu(P);
+  for (int s = 0; s < P; ++s) nu[s] = inert[3 * s];
+  const int64_t nu_top = inert[3 * P];
+  for (int s = 1; s < P; ++s) SL_CHECK_ARG(nu[s] >= nu[s - 1], "inertia not monotone");
+  if (rep) {
+    rep->n_shifts = P;
+    rep->nu_top = nu_top;
+    rep->omega_top = top;
+    rep->flops_factor = (double)S1 * (double)n * n * n / 3.0;
+    if (rep->nu)
+      for (int s = 0; s < P; ++s) rep->nu[s] = nu[s];
+  }
+  *omega_top_io = top;
+  // solve preparation for the probe shifts
+  solve_prep_launch(n, P, reinterpret_cast<const int* const*>(ring.ptrs(std::vector<int32_t*>(ipv.begin(), ipv.begin() + P))),
+                    ring.ptrs(perm), ring.ptrs(blk),
+                    ring.cptrs(std::vector<double*>(LD.begin(), LD.begin() + P)), n, ring.ptrs(Linv), st);
+  // ||A||_2 and ||B||_2 estimates
+  std::vector<int> one{1};
+  int* active1 = ring.vec(one);
+  const double anorm = sym_norm2(c, n, Af, nX, nX + (size_t)n * 8, nsmall, nsmall + 64, nsmall + 128,
+                                 nsmall + 192, nsmall + 256, nflag, active1, o.seed);
+  active1 = ring.vec(one);
+  const double bnorm = sym_norm2(c, n, Bf, nX, nX + (size_t)n * 8, nsmall, nsmall + 64, nsmall + 128,
+                                 nsmall + 192, nsmall + 256, nflag, active1, o.seed ^ 0x5A5Aull);
+  if (rep) rep->anorm = anorm;
+  // ---- 2. block Lanczos per probe
+  const auto t_l0 = Clock::now();
+  std::vector<ProbeHost> pr(P);
+  int64_t max_need = 0;
+  for (int j = 0; j < P; ++j) {
+    pr[j].sigma = sig[j];
+    pr[j].lo = j > 0 ? sig[j - 1] : -std::numeric_limits<double>::infinity();
+    pr[j].hi = j + 1 < P ? sig[j + 1] : top;
+    const int64_t nlo = j > 0 ? nu[j - 1] : 0;
+    const int64_t nhi = j + 1 < P ? nu[j + 1] : nu_top;
+    pr[j].need = nhi - nlo;
+    max_need = std::max(max_need, pr[j].need);
+  }
+  const int LC = (int)std::min<int64_t>(n, max_need + 16);
+  int MB = o.max_basis;
+  while (MB > 16 && MB + 2 * b + LC > n) MB -= b;
+  const int QC = MB + 2 * b;
+  const int kkeep_max = std::max(b, MB - 6 * b);
+  Sizer zl;
+  zl.take<double>((size_t)n * b * P);  // W_all
+  zl.take<double>((size_t)n * b * P);  // Z_all
+  for (int j = 0; j < P; ++j) {
+    zl.take<double>((size_t)n * QC);  // Q
+    zl.take<double>((size_t)n * QC);  // UQ
+    zl.take<double>((size_t)n * LC);  // L
+    zl.take<double>((size_t)n * LC);  // UL
+    zl.take<double>((size_t)n * MB);  // Xt
+    zl.take<double>((size_t)n * MB);  // Ut
+    zl.take<double>((size_t)n * b);   // solve scratch Z
+    zl.take<double>((size_t)n * b);   // solve scratch V
+    zl.take<double>((size_t)QC * QC);  // T
+    zl.take<double>((size_t)QC * QC);  // S (eigvecs)
+    zl.take<double>((size_t)QC * QC);  // S lock sel
+    zl.take<double>((size_t)QC * QC);  // S keep sel
+    zl.take<double>(QC);               // theta
+    zl.take<double>(QC);               // est
+    zl.take<double>((size_t)QC * b);   // CQ
+    zl.take<double>((size_t)LC * b);   // CL
+    zl.take<double>(4 * b * b);        // G, R1, R2, Rt
+    zl.take<int>(2 * QC);              // idx lock / keep
+  }
+  zl.take<int>(P);  // flags
+  Carver cl(ws_get(h, kBufLanczos, zl.off));
+  double* Wall = cl.take<double>((size_t)n * b * P);
+  double* Zall = cl.take<double>((size_t)n * b * P);
+  struct ProbeDev {
+    double *Q, *UQ, *L, *UL, *Xt, *Ut, *Zs, *Vs, *T, *S, *SL, *SK, *th, *est, *CQ, *CL, *G, *R1, *R2, *Rt;
+    int *il, *ik;
+  };
+  std::vector<ProbeDev> pd(P);
+  for (int j = 0; j < P; ++j) {
+    auto& d = pd[j];
+    d.Q = cl.take<double>((size_t)n * QC);
+    d.UQ = cl.take<double>((size_t)n * QC);
+    d.L = cl.take<double>((size_t)n * LC);
+    d.UL = cl.take<double>((size_t)n * LC);
+    d.Xt = cl.take<double>((size_t)n * MB);
+    d.Ut = cl.take<double>((size_t)n * MB);
+    d.Zs = cl.take<double>((size_t)n * b);
+    d.Vs = cl.take<double>((size_t)n * b);
+    d.T = cl.take<double>((size_t)QC * QC);
+    d.S = cl.take<double>((size_t)QC * QC);
+    d.SL = cl.take<double>((size_t)QC * QC);
+    d.SK = cl.take<double>((size_t)QC * QC);
+    d.th = cl.take<double>(QC);
+    d.est = cl.take<double>(QC);
+    d.CQ = cl.take<double>((size_t)QC * b);
+    d.CL = cl.take<double>((size_t)LC * b);
+    double* g4 = cl.take<double>(4 * b * b);
+    d.G = g4;
+    d.R1 = g4 + b * b;
+    d.R2 = g4 + 2 * b * b;
+    d.Rt = g4 + 3 * b * b;
+    int* ii = cl.take<int>(2 * QC);
+    d.il = ii;
+    d.ik = ii + QC;
+  }
+  int* dflags = cl.take<int>(P);
+  for (int j = 0; j < P; ++j) SL_HIP(hipMemsetAsync(pd[j].T, 0, sizeof(double) * QC * QC, st));
+  unsigned* sync = sync_words(h, 64 + (size_t)P * 2 * nblk + 64);
+  auto Wj = [&](int j) { return Wall + (size_t)j * n * b; };
+  auto Zj = [&](int j) { return Zall + (size_t)j * n * b; };
+  // start blocks: Gaussian from the shared stream, B-orthonormalised (CholeskyQR2)
+  {
+    std::vector<unsigned long long> seeds(P);
+    std::vector<double*> wp(P);
+    for (int j = 0; j < P; ++j) {
+      seeds[j] = rng_derive(o.seed, kTagLanczos ^ ((uint64_t)j << 32));
+      wp[j] = Wj(j);
+    }
+    gauss_launch(n, b, P, ring.vec(seeds), ring.ptrs(wp), n, st);
+  }
+  std::vector<int> all(P);
+  std::iota(all.begin(), all.end(), 0);
+  auto act_vec = [&](const auto& js, auto f) {
+    using T = decltype(f(js[0]));
+    std::vector<T> v;
+    v.reserve(js.size());
+    for (const auto& j : js) v.push_back(f(j));
+    return v;
+  };
+  auto cholqr2 = [&](const std::vector<int>& js, const std::vector<double*>& Vin,
+                     const std::vector<double*>& Uin, long ldin, const std::vector<double*>& Vout,
+                     const std::vector<double*>& Uout, bool coupling) {
+    const int na = (int)js.size();
+    std::vector<int> ones(na, 1), bs(na, b), ns(na, n);
+    std::vector<const double*> cV(Vin.begin(), Vin.end()), cU(Uin.begin(), Uin.end());
+    gemm(c, true, false, bs, bs, ns, cV, ldin, cU, ldin, act_vec(js, [&](int j) { return pd[j].G; }), b, 1.0, 0.0);
+    CholQrArgs q;
+    q.n = n;
+    q.active = ring.vec(ones);
+    q.G = ring.cptrs(act_vec(js, [&](int j) { return pd[j].G; }));
+    q.Vin = ring.cptrs(Vin);
+    q.Uin = ring.cptrs(Uin);
+    q.ldin = ldin;
+    q.Vout = ring.ptrs(Vout);
+    q.Uout = ring.ptrs(Uout);
+    q.ldout = n;
+    q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
+    q.flag = dflags;  // indexed by position; only read when all probes are active
+    cholqr_launch(q, na, st);
+    std::vector<const double*> cVo(Vout.begin(), Vout.end()), cUo(Uout.begin(), Uout.end());
+    gemm(c, true, false, bs, bs, ns, cVo, n, cUo, n, act_vec(js, [&](int j) { return pd[j].G; }), b, 1.0, 0.0);
+    q.Vin = ring.cptrs(Vout);
+    q.Uin = ring.cptrs(Uout);
+    q.ldin = n;
+    q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
+    cholqr_launch(q, na, st);
+    if (coupling) {
+      CouplingArgs ca;
+      ca.active = ring.vec(ones);
+      ca.R1 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
+      ca.R2 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
+      ca.Rt = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Rt; }));
+      ca.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
+      ca.ldt = QC;
+      ca.row0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq; }));
+      coupling_launch(ca, na, st);
+    }
+  };
+  // Z = B W, then B-orthonormalise into Q[:, 0:8]
+  gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
+  cholqr2(all, act_vec(all, Wj), act_vec(all, Zj), n, act_vec(all, [&](int j) { return pd[j].Q; }),
+          act_vec(all, [&](int j) { return pd[j].UQ; }), false);
+  for (int j = 0; j < P; ++j) pr[j].mq = b;
+  // slice bookkeeping
+  std::vector<int64_t> n_exact(P + 1);
+  for (int s = 0; s <= P; ++s) {
+    const int64_t lo = s == 0 ? 0 : nu[s - 1];
+    const int64_t hi = s == P ? nu_top : nu[s];
+    n_exact[s] = hi - lo;
+  }
+  auto slice_done = [&](int s) {
+    int64_t cnt = 0;
+    if (s == 0) {
+      for (double v : pr[0].lock_lam) cnt += v < sig[0];
+    } else if (s == P) {
+      for (double v : pr[P - 1].lock_lam) cnt += v >= sig[P - 1] && v < top;
+    } else {
+      const double lo = sig[s - 1], hi = sig[s], tau = 0.5 * (lo + hi);
+      for (double v : pr[s - 1].lock_lam) cnt += v >= lo && v <= tau;
+      for (double v : pr[s].lock_lam) cnt += v > tau && v < hi;
+    }
+    return cnt >= n_exact[s];
+  };
+  int block_steps = 0, cycles_max = 0;
+  const double lock_tol = o.tol / 100.0;
+  for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
+    std::vector<int> act;
+    for (int j = 0; j < P; ++j)
+      if (pr[j].active) act.push_back(j);
+    if (act.empty()) break;
+    // ---- steps until every active probe's basis is full
+    while (true) {
+      std::vector<int> js;
+      for (int j : act)
+        if (pr[j].mq - b < MB) js.push_back(j);
+      if (js.empty()) break;
+      const int na = (int)js.size();
+      block_steps += na;
+      for (int j : js) pr[j].steps++;
+      // a. W_j = (A - sigma_j B)^{-1} U_j[:, last block]
+      SolveArgs sa;
+      sa.n = n;
+      sa.nshift = na;
+      sa.nrhs = b;
+      sa.epoch = next_epoch(h);
+      sa.LD = ring.cptrs(act_vec(js, [&](int j) { return LD[j]; }));
+      sa.ldld = n;
+      sa.perm = ring.cptrs(act_vec(js, [&](int j) { return perm[j]; }));
+      sa.blk = ring.cptrs(act_vec(js, [&](int j) { return blk[j]; }));
+      sa.Linv = ring.cptrs(act_vec(js, [&](int j) { return Linv[j]; }));
+      sa.Y = ring.cptrs(act_vec(js, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
+      sa.ldy = n;
+      sa.X = ring.ptrs(act_vec(js, Wj));
+      sa.ldx = n;
+      sa.Z = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Zs; }));
+      sa.V = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Vs; }));
+      sa.ldz = n;
+      sa.flags = sync + 64;
+      sa.flag_stride = 2 * nblk;
+      sa.ctr = sync;
+      solve_launch(sa, st, 0);
+      // b. full B-reorthogonalisation, twice; T's new column block from the projections
+      const auto vb = std::vector<int>(na, b);
+      const auto vn = std::vector<int>(na, n);
+      const auto vmq = act_vec(js, [&](int j) { return pr[j].mq; });
+      const auto vnl = act_vec(js, [&](int j) { return pr[j].nl; });
+      const auto pW = act_vec(js, [&](int j) { return (const double*)Wj(j); });
+      const auto pWm = act_vec(js, Wj);
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm(c, true, false, vnl, vb, vn, act_vec(js, [&](int j) { return (const double*)pd[j].UL; }), n,
+             pW, n, act_vec(js, [&](int j) { return pd[j].CL; }), LC, 1.0, 0.0);
+        gemm(c, true, false, vmq, vb, vn, act_vec(js, [&](int j) { return (const double*)pd[j].UQ; }), n,
+             pW, n, act_vec(js, [&](int j) { return pd[j].CQ; }), QC, 1.0, 0.0);
+        gemm(c, false, false, vn, vb, vnl, act_vec(js, [&](int j) { return (const double*)pd[j].L; }), n,
+             act_vec(js, [&](int j) { return (const double*)pd[j].CL; }), LC, pWm, n, -1.0, 1.0);
+        gemm(c, false, false, vn, vb, vmq, act_vec(js, [&](int j) { return (const double*)pd[j].Q; }), n,
+             act_vec(js, [&](int j) { return (const double*)pd[j].CQ; }), QC, pWm, n, -1.0, 1.0);
+        TWriteArgs tw;
+        tw.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
+        tw.ldt = QC;
+        tw.S = ring.cptrs(act_vec(js, [&](int j) { return pd[j].CQ; }));
+        tw.lds = QC;
+        tw.rows = ring.vec(vmq);
+        tw.r0 = ring.vec(std::vector<int>(na, 0));
+        tw.c0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq - b; }));
+        tw.cols = b;
+        tw.add = pass;
+        twrite_launch(tw, na, st);
+      }
+      // c. Z = B W for every probe in one GEMM (inactive blocks are recomputed harmlessly)
+      gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
+      // d. CholeskyQR2 into the next block; coupling block of T
+      cholqr2(js, pWm, act_vec(js, Zj), n, act_vec(js, [&](int j) { return pd[j].Q + (size_t)pr[j].mq * n; }),
+              act_vec(js, [&](int j) { return pd[j].UQ + (size_t)pr[j].mq * n; }), true);
+      for (int j : js) pr[j].mq += b;
+    }
+    // ---- cycle end: Ritz pairs of T, estimates, locking and thick restart
+    const int na = (int)act.size();
+    const auto vmt = act_vec(act, [&](int j) { return pr[j].mq - b; });
+    int mtmax = 0;
+    for (int v : vmt) mtmax = std::max(mtmax, v);
+    EigArgs e;
+    e.m = ring.vec(vmt);
+    e.A = ring.cptrs(act_vec(act, [&](int j) { return pd[j].T; }));
+    e.lda = QC;
+    e.W = ring.ptrs(act_vec(act, [&](int j) { return pd[j].th; }));
+    e.V = ring.ptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+    e.ldv = QC;
+    eig_launch(e, na, mtmax, st);
+    RitzEstArgs re;
+    re.mt = ring.vec(vmt);
+    re.S = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+    re.lds = QC;
+    re.Rt = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Rt; }));
+    re.est = ring.ptrs(act_vec(act, [&](int j) { return pd[j].est; }));
+    ritz_est_launch(re, na, st);
+    std::vector<std::vector<double>> th(na, std::vector<double>(QC)), es(na, std::vector<double>(QC));
+    for (int q = 0; q < na; ++q) {
+      SL_HIP(hipMemcpyAsync(th[q].data(), pd[act[q]].th, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipMemcpyAsync(es[q].data(), pd[act[q]].est, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
+    }
+    std::vector<int> hflags(P, 0);
+    SL_HIP(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    std::vector<std::vector<int>> lk(na), kp(na);
+    std::vector<std::vector<double>> thk(na);
+    for (int q = 0; q < na; ++q) {
+      const int j = act[q];
+      auto& p = pr[j];
+      p.cycles++;
+      const int mt = vmt[q];
+      const double scale = (anorm + std::fabs(p.sigma) * bnorm) / anorm;
+      std::vector<int> rest;
+      for (int i = 0; i < mt; ++i) {
+        const double t = th[q][i];
+        if (t == 0.0 || !std::isfinite(t)) continue;
+        const double lam = p.sigma + 1.0 / t;
+        const double r = es[q][i] / std::fabs(t) * scale;
+        if (lam > p.lo && lam < p.hi && r <= lock_tol && p.nl + (int)lk[q].size() < LC) {
+          lk[q].push_back(i);
+          p.lock_lam.push_back(lam);
+        } else {
+          rest.push_back(i);
+        }
+      }
+      std::stable_sort(rest.begin(), rest.end(),
+                       [&](int x, int y) { return std::fabs(th[q][x]) > std::fabs(th[q][y]); });
+      const int kk = std::min<int>((int)rest.size(), kkeep_max);
+      kp[q].assign(rest.begin(), rest.begin() + kk);
+      for (int i : kp[q]) thk[q].push_back(th[q][i]);
+    }
+    // device: select columns, lock GEMMs, keep GEMMs, move newest block, reset T
+    std::vector<int> nlk(na), nkp(na), rows(na);
+    for (int q = 0; q < na; ++q) {
+      nlk[q] = (int)lk[q].size();
+      nkp[q] = (int)kp[q].size();
+      rows[q] = vmt[q];
+    }
+    std::vector<int*> il_ptr(na), ik_ptr(na);
+    for (int q = 0; q < na; ++q) {
+      il_ptr[q] = ring.vec(lk[q]);
+      ik_ptr[q] = ring.vec(kp[q]);
+    }
+    SelectArgs sl;
+    sl.count = ring.vec(nlk);
+    sl.rows = ring.vec(rows);
+    sl.in = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+    sl.ldi = QC;
+    sl.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SL; }));
+    sl.ldo = QC;
+    sl.idx = ring.cptrs(il_ptr);
+    select_launch(sl, na, (long)QC * QC, st);
+    SelectArgs sk = sl;
+    sk.count = ring.vec(nkp);
+    sk.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SK; }));
+    sk.idx = ring.cptrs(ik_ptr);
+    select_launch(sk, na, (long)QC * QC, st);
+    const auto vn = std::vector<int>(na, n);
+    gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
+         act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
+         act_vec(act, [&](int j) { return pd[j].L + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
+    gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
+         act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
+         act_vec(act, [&](int j) { return pd[j].UL + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
+    gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
+         act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
+         act_vec(act, [&](int j) { return pd[j].Xt; }), n, 1.0, 0.0);
+    gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
+         act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
+         act_vec(act, [&](int j) { return pd[j].Ut; }), n, 1.0, 0.0);
+    CopyArgs cp;
+    cp.n = n;
+    cp.ncol = ring.vec(std::vector<int>(na, b));
+    cp.lds = n;
+    cp.ldd = n;
+    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Q + (size_t)(pr[j].mq - b) * n; }));
+    cp.dst = ring.ptrs([&] {
+      std::vector<double*> v;
+      for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].Q + (size_t)nkp[q] * n);
+      return v;
+    }());
+    copy_launch(cp, na, b, st);
+    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
+    cp.dst = ring.ptrs([&] {
+      std::vector<double*> v;
+      for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].UQ + (size_t)nkp[q] * n);
+      return v;
+    }());
+    copy_launch(cp, na, b, st);
+    cp.ncol = ring.vec(nkp);
+    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Xt; }));
+    cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].Q; }));
+    copy_launch(cp, na, kkeep_max, st);
+    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Ut; }));
+    cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].UQ; }));
+    copy_launch(cp, na, kkeep_max, st);
+    std::vector<double*> thp(na);
+    for (int q = 0; q < na; ++q) thp[q] = ring.vec(thk[q]);
+    TResetArgs tr;
+    tr.active = ring.vec(std::vector<int>(na, 1));
+    tr.T = ring.ptrs(act_vec(act, [&](int j) { return pd[j].T; }));
+    tr.ldt = QC;
+    tr.dim = QC;
+    tr.k = ring.vec(nkp);
+    tr.theta = ring.cptrs(thp);
+    treset_launch(tr, na, st);
+    for (int q = 0; q < na; ++q) {
+      auto& p = pr[act[q]];
+      p.nl += nlk[q];
+      p.mq = nkp[q] + b;
+    }
+    // probe activity from slice completion
+    std::vector<bool> done(P + 1);
+    for (int s = 0; s <= P; ++s) done[s] = slice_done(s);
+    for (int j = 0; j < P; ++j) {
+      pr[j].active = !(done[j] && done[j + 1]) && pr[j].nl < LC;
+      cycles_max = std::max(cycles_max, pr[j].cycles);
+    }
+  }
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  const double t_lanczos = ms_since(t_l0);
+  // ---- 3. explicit Rayleigh-Ritz with A on the locked vectors, residuals
+  const auto t_r0 = Clock::now();
+  struct Chunk {
+    int probe, off, cnt;
+    std::vector<int> cols;
+  };
+  std::vector<Chunk> chunks;
+  int NL = 0;
+  for (int j = 0; j < P; ++j) {
+    std::vector<int> ord(pr[j].nl);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return pr[j].lock_lam[x] < pr[j].lock_lam[y]; });
+    for (int s0 = 0; s0 < (int)ord.size(); s0 += kEigMax) {
+      Chunk ch;
+      ch.probe = j;
+      ch.off = NL;
+      ch.cnt = std::min<int>(kEigMax, (int)ord.size() - s0);
+      ch.cols.assign(ord.begin() + s0, ord.begin() + s0 + ch.cnt);
+      NL += ch.cnt;
+      chunks.push_back(std::move(ch));
+    }
+  }
+  const int NC = (int)chunks.size();
+  std::vector<double> vals(NL), ress(NL);
+  double *Xa = nullptr, *AXa = nullptr, *BXa = nullptr, *Xf = nullptr, *AXf = nullptr, *BXf = nullptr,
+         *Hm = nullptr, *Om = nullptr, *Ym = nullptr, *rr = nullptr, *xn = nullptr;
+  if (NL > 0) {
+    Sizer zr;
+    for (int q = 0; q < 6; ++q) zr.take<double>((size_t)n * NL);
+    zr.take<double>((size_t)NC * kEigMax * kEigMax);
+    zr.take<double>((size_t)NC * kEigMax);
+    zr.take<double>((size_t)NC * kEigMax * kEigMax);
+    zr.take<double>(NL);
+    zr.take<double>(NL);
+    Carver cr(ws_get(h, kBufEig, zr.off));
+    Xa = cr.take<double>((size_t)n * NL);
+    AXa = cr.take<double>((size_t)n * NL);
+    BXa = cr.take<double>((size_t)n * NL);
+    Xf = cr.take<double>((size_t)n * NL);
+    AXf = cr.take<double>((size_t)n * NL);
+    BXf = cr.take<double>((size_t)n * NL);
+    Hm = cr.take<double>((size_t)NC * kEigMax * kEigMax);
+    Om = cr.take<double>((size_t)NC * kEigMax);
+    Ym = cr.take<double>((size_t)NC * kEigMax * kEigMax);
+    rr = cr.take<double>(NL);
+    xn = cr.take<double>(NL);
+    std::vector<int> cnts(NC), rowsn(NC, n);
+    std::vector<int*> idxp(NC);
+    for (int q = 0; q < NC; ++q) {
+      cnts[q] = chunks[q].cnt;
+      idxp[q] = ring.vec(chunks[q].cols);
+    }
+    SelectArgs sx;
+    sx.count = ring.vec(cnts);
+    sx.rows = ring.vec(rowsn);
+    sx.in = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return pd[ch.probe].L; }));
+    sx.ldi = n;
+    sx.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return Xa + (size_t)ch.off * n; }));
+    sx.ldo = n;
+    sx.idx = ring.cptrs(idxp);
+    select_launch(sx, NC, (long)n * kEigMax, st);
+    gemm(c, false, false, {n}, {NL}, {n}, {Af}, n, {Xa}, n, {AXa}, n, 1.0, 0.0);
+    gemm(c, false, false, {n}, {NL}, {n}, {Bf}, n, {Xa}, n, {BXa}, n, 1.0, 0.0);
+    auto cX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(Xa + (size_t)ch.off * n); });
+    auto cAX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(AXa + (size_t)ch.off * n); });
+    auto cBX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(BXa + (size_t)ch.off * n); });
+    std::vector<double*> pH(NC), pO(NC), pY(NC);
+    for (int q = 0; q < NC; ++q) {
+      pH[q] = Hm + (size_t)q * kEigMax * kEigMax;
+      pO[q] = Om + (size_t)q * kEigMax;
+      pY[q] = Ym + (size_t)q * kEigMax * kEigMax;
+    }
+    gemm(c, true, false, cnts, cnts, rowsn, cX, n, cAX, n, pH, kEigMax, 1.0, 0.0);
+    EigArgs e;
+    e.m = ring.vec(cnts);
+    e.A = ring.cptrs(pH);
+    e.lda = kEigMax;
+    e.W = ring.ptrs(pO);
+    e.V = ring.ptrs(pY);
+    e.ldv = kEigMax;
+    int cmax = 0;
+    for (int v : cnts) cmax = std::max(cmax, v);
+    eig_launch(e, NC, cmax, st);
+    std::vector<const double*> cY(pY.begin(), pY.end());
+    gemm(c, false, false, rowsn, cnts, cnts, cX, n, cY, kEigMax,
+         act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+    gemm(c, false, false, rowsn, cnts, cnts, cAX, n, cY, kEigMax,
+         act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+    gemm(c, false, false, rowsn, cnts, cnts, cBX, n, cY, kEigMax,
+         act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+    ColDotArgs r1;
+    r1.n = n;
+    r1.ncol = ring.vec(cnts);
+    r1.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }));
+    r1.ldx = n;
+    r1.Y = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }));
+    r1.ldy = n;
+    r1.w = ring.cptrs(pO);
+    r1.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return rr + ch.off; }));
+    r1.mode = 1;
+    r1.partial = static_cast<double*>(ws_get(h, kBufMisc, sizeof(double) * coldot_partial_size(n, NC, kEigMax)));
+    coldot_launch(r1, NC, cmax, st);
+    ColDotArgs r2 = r1;
+    r2.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }));
+    r2.Y = r2.X;
+    r2.ldy = n;
+    r2.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return xn + ch.off; }));
+    r2.mode = 0;
+    coldot_launch(r2, NC, cmax, st);
+    std::vector<double> hr(NL), hx(NL), ho((size_t)NC * kEigMax);
+    SL_HIP(hipMemcpyAsync(hr.data(), rr, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(hx.data(), xn, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(ho.data(), Om, sizeof(double) * NC * kEigMax, hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    for (int q = 0; q < NC; ++q)
+      for (int i = 0; i < chunks[q].cnt; ++i) {
+        const int t = chunks[q].off + i;
+        vals[t] = ho[(size_t)q * kEigMax + i];
+        ress[t] = hr[t] / (anorm * std::sqrt(std::max(hx[t], 1e-300)));
+      }
+  }
+  const double t_rr = ms_since(t_r0);
+  // ---- 4. validation (host) and output
+  const auto t_h0 = Clock::now();
+  std::vector<int64_t> offs(P, 0), cnts(P, 0);
+  {
+    // probe j's values are the concatenation of its chunks
+    for (const auto& ch : chunks) cnts[ch.probe] += ch.cnt;
+    int64_t acc = 0;
+    for (int j = 0; j < P; ++j) {
+      offs[j] = acc;
+      acc += cnts[j];
+    }
+  }
+  std::vector<int32_t> scase(P + 1), sexact(P + 1), scand(P + 1), chosen(std::max(NL, 1), 0);
+  const int64_t nval = validate(P, sig.data(), nu.data(), top, nu_top, offs.data(), cnts.data(),
+                                vals.data(), ress.data(), scase.data(), sexact.data(), scand.data(),
+                                chosen.data());
+  std::vector<int> pick;
+  for (int t = 0; t < NL; ++t)
+    if (chosen[t]) pick.push_back(t);
+  std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) { return vals[x] < vals[y]; });
+  const int nout = (int)std::min<int64_t>(n_e, (int64_t)pick.size());
+  int64_t nconv = 0;
+  bool missing = nval < n_e || (int64_t)pick.size() < n_e;
+  for (int s = 0; s <= P; ++s) missing |= scase[s] == 1;
+  if (nout > 0) {
+    std::vector<const double*> src(nout);
+    std::vector<int> scol(nout);
+    std::vector<double> v(nout), r(nout);
+    for (int q = 0; q < nout; ++q) {
+      src[q] = Xf;
+      scol[q] = pick[q];
+      v[q] = vals[pick[q]];
+      r[q] = ress[pick[q]];
+      nconv += r[q] <= o.tol;
+    }
+    GatherArgs g;
+    g.n = n;
+    g.src = ring.cptrs(std::vector<double*>(src.size(), Xf));
+    g.src_col = ring.vec(scol);
+    g.lds = n;
+    g.dst = evecs;
+    g.ldd = ldx;
+    g.val = ring.vec(v);
+    g.res = ring.vec(r);
+    g.evals = evals;
+    g.resid = resid_out;
+    gather_launch(g, nout, st);
+  }
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  const double t_host = ms_since(t_h0);
+  if (rep) {
+    rep->n_validated = nval;
+    rep->n_converged = nconv;
+    rep->cycles_max = cycles_max;
+    rep->block_steps = block_steps;
+    rep->t_factor_ms = t_factor;
+    rep->t_lanczos_ms = t_lanczos;
+    rep->t_rr_ms = t_rr;
+    rep->t_host_ms = t_host;
+    rep->t_total_ms = ms_since(t_start);
+    (void)t_plan;
+    if (rep->slice_case)
+      for (int s = 0; s <= P; ++s) rep->slice_case[s] = scase[s];
+    if (rep->slice_exact)
+      for (int s = 0; s <= P; ++s) rep->slice_exact[s] = sexact[s];
+    if (rep->slice_cand)
+      for (int s = 0; s <= P; ++s) rep->slice_cand[s] = scand[s];
+  }
+  if (missing) return SISLICE_MISSING_EIGS;
+  if (nconv < n_e) return SISLICE_NOT_CONVERGED;
+  return SISLICE_OK;
+}
+
+}  // namespace sislice
+
+using namespace sislice;
+
+extern "C" {
+
+sislice_status sislice_plan_shifts_kpm(sislice_handle* h, int64_t n, const double* A, int64_t lda,
+                                       const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                                       const sislice_opts* opts, double* sigmas, double* omega_top,
+                                       double* moments, double* bounds) {
+  try {
+    check_handle(h);
+    sislice_opts o;
+    sislice_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(o);
+    SL_CHECK_ARG(n >= 16 && n <= 20000, "n must be in [16, 20000]");
+    SL_CHECK_ARG(n_s >= 1 && n_e >= 1 && n_e < n, "bad n_e / n_s");
+    SL_CHECK_ARG(A && B && lda >= n && ldb >= n && sigmas && omega_top, "bad argument");
+    return plan_impl(h, n, A, lda, B, ldb, n_e, n_s, o, sigmas, omega_top, moments, bounds);
+  } catch (const Error& e) {
+    std::fprintf(stderr, "sislice: %s\n", e.what());
+    return e.status;
+  }
+}
+
+sislice_status sislice_solve(sislice_handle* h, int64_t n, const double* A, int64_t lda,
+                             const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                             const double* sigmas, double* omega_top, const sislice_opts* opts,
+                             double* evals, double* evecs, int64_t ldx, double* resid,
+                             sislice_report* report) {
+  try {
+    check_handle(h);
+    sislice_opts o;
+    sislice_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(o);
+    SL_CHECK_ARG(n >= 32 && n <= 20000, "n must be in [32, 20000]");
+    SL_CHECK_ARG(n_s >= 1 && n_s <= 1024, "n_s must be in [1, 1024]");
+    SL_CHECK_ARG(n_e >= 1 && n_e < n, "n_e must be in [1, n)");
+    SL_CHECK_ARG(A && B && lda >= n && ldb >= n && omega_top, "bad matrix argument");
+    SL_CHECK_ARG(evals && evecs && resid && ldx >= n, "bad output argument");
+    return solve_impl(h, n, A, lda, B, ldb, n_e, n_s, sigmas, omega_top, o, evals, evecs, ldx, resid,
+                      report);
+  } catch (const Error& e) {
+    std::fprintf(stderr, "sislice: %s\n", e.what());
+    return e.status;
+  }
+}
+
+}  // extern "C"

@@ -217,6 +217,7 @@ sislice_status sislice_destroy(sislice_handle* h) {
     if (b.ptr) hipFree(b.ptr);
   if (h->host_stage) hipHostFree(h->host_stage);
   if (h->sync) hipFree(h->sync);
+  if (h->ring_host) hipHostFree(h->ring_host);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
   delete h;

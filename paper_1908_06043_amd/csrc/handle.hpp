@@ -19,11 +19,22 @@ struct sislice_handle {
   unsigned* sync = nullptr;  // epoch flags and ticket counters of the persistent solves
   size_t sync_cap = 0;       // in unsigned words
   unsigned epoch = 0;
+  void* ring_host = nullptr;  // pinned ring for per-step pointer tables
+  size_t ring_cap = 0;
 };
 
 namespace sislice {
 
-enum BufId { kBufFactor = 0, kBufSolve = 1, kBufDriver = 2, kBufKpm = 3, kBufEig = 4, kBufMisc = 5 };
+enum BufId {
+  kBufFactor = 0,
+  kBufSolve = 1,
+  kBufDriver = 2,
+  kBufKpm = 3,
+  kBufEig = 4,
+  kBufMisc = 5,
+  kBufLanczos = 6,
+  kBufRing = 7
+};
 
 // Returns a device buffer of at least `bytes`, reallocating (contents lost) if needed.
 void* ws_get(sislice_handle* h, int id, size_t bytes);

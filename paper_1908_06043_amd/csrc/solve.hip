@@ -213,7 +213,9 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     double v = 0.0;
     if (c < nrhs && row < n) {
       const double z = Z[row + (long)c * a.ldz];
-      if (bt == 1) {
+      if (!a.applyD) {
+        v = z;
+      } else if (bt == 1) {
         v = (d11 != 0.0) ? z / d11 : 0.0;
       } else {
         const double zp = Z[partner + (long)c * a.ldz];
@@ -287,12 +289,16 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
   SL_LAUNCH_CHECK();
 }
 
-void solve_launch(SolveArgs a, hipStream_t st) {
+void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   const int nblk = (int)ceil_div(a.n, SB);
-  hipLaunchKernelGGL(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
-  SL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
-  SL_LAUNCH_CHECK();
+  if (mode == 0 || mode == 1) {
+    hipLaunchKernelGGL(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH_CHECK();
+  }
+  if (mode == 0 || mode == 2) {
+    hipLaunchKernelGGL(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace sislice

@@ -26,12 +26,17 @@ struct SolveArgs {
   unsigned* flags = nullptr;            // nshift * flag_stride (>= 2 * nblk), zero-initialised once
   long flag_stride = 0;
   unsigned* ctr = nullptr;              // nshift ticket counters, zero-initialised once
+  int applyD = 1;                       // backward sweep applies D^{-1} first (0: identity)
 };
+
+// mode 0: X = P^T L^{-T} D^{-1} L^{-1} P Y (both sweeps, Z/V scratch)
+// mode 1: Z = L^{-1} P Y only (forward sweep; the result is left in Z)
+// mode 2: X = P^T L^{-T} [D^{-1}] Z only (backward sweep reading Z)
 
 void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_perm,
                        int* const* d_blk, const double* const* d_LD, long ldld,
                        double* const* d_Linv, hipStream_t st);
-void solve_launch(SolveArgs a, hipStream_t st);
+void solve_launch(SolveArgs a, hipStream_t st, int mode = 0);
 
 inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
 

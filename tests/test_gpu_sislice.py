@@ -1,0 +1,100 @@
+"""End-to-end GPU parity of the plain per-pencil path against the oracle.
+
+Bar: inertia counts bit-exact; eigenvalues within 1e-10 ||A||_2 of the oracle and
+of the construction's spectrum; normalised residuals <= 1e-10; X^T B X = I to
+1e-10; exactly n_e pairs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kpm, sislice as osl
+from paper_1908_06043_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(M):
+    return torch.from_numpy(np.ascontiguousarray(M)).cuda()
+
+
+def check_result(P, out, n_e, anorm_ref=None):
+    ev = out["evals"].cpu().numpy()
+    X = out["evecs"].cpu().numpy()
+    res = out["resid"].cpu().numpy()
+    anorm = anorm_ref if anorm_ref is not None else out["report"]["anorm"]
+    assert out["status"] == 0, (out["status"], out["report"])
+    assert ev.size == n_e
+    assert np.all(np.diff(ev) >= 0)
+    assert np.max(np.abs(ev - P.lam[:n_e])) <= 1e-10 * anorm
+    assert res.max() <= 1e-10
+    G = X.T @ P.B @ X
+    assert np.max(np.abs(G - np.eye(n_e))) <= 1e-10
+    # independent residual check on the host
+    R = P.A @ X - (P.B @ X) * ev[None, :]
+    rn = np.linalg.norm(R, axis=0) / (anorm * np.linalg.norm(X, axis=0))
+    assert rn.max() <= 1e-10
+    return ev
+
+
+@pytest.fixture(scope="module")
+def n200():
+    P = inputs.pencil_clusters4(200, 0)
+    pl = kpm.plan(P.A, P.B, 40, 4, M=64, nv=20, seed=0)
+    sig = inputs.safe_shifts(P.lam, pl["sigmas"])
+    top = inputs.safe_shifts(P.lam, [pl["omega_top"]])[0]
+    ref = osl.solve(P.A, P.B, 40, sig, top, seed=0)
+    return P, sig, top, ref
+
+
+def test_n200_given_shifts_matches_oracle(gpu_lib, n200):
+    P, sig, top, ref = n200
+    out = gpu_lib.solve(dev(P.A), dev(P.B), 40, 4, sigmas=sig, omega_top=top)
+    ev = check_result(P, out, 40)
+    assert np.max(np.abs(ev - ref["evals"])) <= 1e-10 * ref["anorm"]
+    rep = out["report"]
+    assert list(rep["nu"]) == list(ref["nus"])                 # bit-exact inertia
+    assert rep["nu_top"] == ref["nu_top"]
+    assert list(rep["slice_exact"]) == [s["n_exact"] for s in ref["slices"]]
+
+
+def test_n200_planned_shifts(gpu_lib):
+    P = inputs.pencil_clusters4(200, 0)
+    out = gpu_lib.solve(dev(P.A), dev(P.B), 40, 4)
+    check_result(P, out, 40)
+    rep = out["report"]
+    assert [int(x) for x in rep["nu"]] == [int(np.sum(P.lam < s)) for s in rep_sigmas(gpu_lib, P, 40, 4)]
+
+
+def rep_sigmas(gpu_lib, P, n_e, n_s):
+    return gpu_lib.plan_shifts_kpm(dev(P.A), dev(P.B), n_e, n_s)["sigmas"]
+
+
+@pytest.mark.parametrize("n,n_e,n_s", [(200, 40, 4), (1000, 100, 8)])
+def test_kpm_planner_matches_oracle(gpu_lib, n, n_e, n_s):
+    P = inputs.pencil_clusters4(n, 0) if n == 200 else inputs.pencil_scf(n, n_e, seed=1)
+    g = gpu_lib.plan_shifts_kpm(dev(P.A), dev(P.B), n_e, n_s)
+    r = kpm.plan(P.A, P.B, n_e, n_s, M=64, nv=20, seed=0)
+    span = r["b"] - r["a"]
+    assert abs(g["a"] - r["a"]) <= 1e-9 * span and abs(g["b"] - r["b"]) <= 1e-9 * span
+    assert np.max(np.abs(g["mu"] - r["mu"])) <= 1e-10
+    assert np.max(np.abs(g["sigmas"] - r["sigmas"])) <= 1e-8 * span
+    assert abs(g["omega_top"] - r["omega_top"]) <= 1e-8 * span
+
+
+def test_n1000_scf_pencil(gpu_lib):
+    P = inputs.pencil_scf(1000, 100, seed=1)
+    out = gpu_lib.solve(dev(P.A), dev(P.B), 100, 8)
+    check_result(P, out, 100)
+
+
+def test_full_size_n4096_ne400_16_shifts(gpu_lib):
+    """The benchmark workload: N=4096, lowest 400, 16 KPM shifts, Lanczos block 8."""
+    P = inputs.pencil_scf(4096, 400, seed=0)
+    A, B = dev(P.A), dev(P.B)
+    out = gpu_lib.solve(A, B, 400, 16)
+    check_result(P, out, 400)
+    rep = out["report"]
+    sig = gpu_lib.plan_shifts_kpm(A, B, 400, 16)["sigmas"]
+    assert [int(x) for x in rep["nu"]] == [int(np.sum(P.lam < s)) for s in sig]
+    assert rep["nu_top"] == int(np.sum(P.lam < out["omega_top"]))
