@@ -55,7 +55,7 @@ typedef struct {
   int32_t kpm_vectors;   /* Rademacher probe vectors (20)                                */
   int32_t bounds_steps;  /* Lanczos steps of the spectral-bounds estimate (30)           */
   int32_t nb;            /* factorization panel width (0 = library default)             */
-  int32_t reserved_i;    /* must be 0                                                    */
+  int32_t profile;       /* 1: time kernel classes with HIP events into the report (0)  */
   double tol;            /* residual ||Ax - lambda Bx|| / (||A||_2 ||x||) target (1e-10) */
   double top_margin;     /* top boundary at the CDOS root of n_e + top_margin*n_e/n_s (2) */
   uint64_t seed;         /* SplitMix64 seed of every random draw (0)                     */
@@ -82,6 +82,13 @@ typedef struct {
   int32_t *slice_case;     /* [n_shifts+1] 0 equal counts, 1 missing, 2 trimmed        */
   int32_t *slice_exact;    /* [n_shifts+1] exact counts from inertia                   */
   int32_t *slice_cand;     /* [n_shifts+1] validation candidates                       */
+  /* With opts->profile: summed HIP-event durations and launch counts of the
+   * kernel classes 0 Bunch-Kaufman panels, 1 MFMA trailing updates, 2 triangular
+   * solves, 3 GEMMs, 4 projected eigensolves, 5 other; and the algorithmic flops
+   * of the trailing updates (2 kb per lower-triangle element per panel). */
+  double t_kern_ms[6];
+  int64_t n_kern[6];
+  double flops_update;
 } sislice_report;
 
 void sislice_default_opts(sislice_opts *opts);

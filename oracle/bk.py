@@ -31,10 +31,12 @@ import numpy as np
 ALPHA = (1.0 + math.sqrt(17.0)) / 8.0
 
 
-def bk_ldlt(C):
+def bk_ldlt(C, max_steps=None):
     """Factor symmetric C (only symmetry is assumed; the full array is read).
 
-    Returns dict(L, d, e, perm, blk, zero_pivots).
+    Returns dict(L, d, e, perm, blk, zero_pivots, k).  ``max_steps`` stops after
+    that many pivot columns (used to time a bounded sample of a large
+    factorization); ``k`` is the number of columns factored.
     """
     S = np.array(C, dtype=np.float64, copy=True)
     S = 0.5 * (S + S.T)
@@ -55,7 +57,8 @@ def bk_ldlt(C):
         perm[[i, j]] = perm[[j, i]]
 
     k = 0
-    while k < n:
+    limit = n if max_steps is None else min(n, int(max_steps))
+    while k < limit:
         absakk = abs(S[k, k])
         if k + 1 < n:
             col = np.abs(S[k + 1:, k])
@@ -104,7 +107,7 @@ def bk_ldlt(C):
             L[k + 2:, k:k + 2] = Lb
             S[k + 2:, k + 2:] -= Lb @ Cc.T
         k += kstep
-    return dict(L=L, d=d, e=e, perm=perm, blk=blk, zero_pivots=zero_pivots)
+    return dict(L=L, d=d, e=e, perm=perm, blk=blk, zero_pivots=zero_pivots, k=k)
 
 
 def d_matrix(f):

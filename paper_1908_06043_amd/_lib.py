@@ -21,7 +21,7 @@ STATUS = {
 class Opts(C.Structure):
     _fields_ = [("block", C.c_int32), ("max_basis", C.c_int32), ("max_cycles", C.c_int32),
                 ("kpm_moments", C.c_int32), ("kpm_vectors", C.c_int32),
-                ("bounds_steps", C.c_int32), ("nb", C.c_int32), ("reserved_i", C.c_int32),
+                ("bounds_steps", C.c_int32), ("nb", C.c_int32), ("profile", C.c_int32),
                 ("tol", C.c_double), ("top_margin", C.c_double), ("seed", C.c_uint64)]
 
 
@@ -32,7 +32,8 @@ class Report(C.Structure):
                 ("t_factor_ms", C.c_double), ("t_lanczos_ms", C.c_double),
                 ("t_rr_ms", C.c_double), ("t_host_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("flops_factor", C.c_double), ("nu", c_int64_p), ("slice_case", c_int32_p),
-                ("slice_exact", c_int32_p), ("slice_cand", c_int32_p)]
+                ("slice_exact", c_int32_p), ("slice_cand", c_int32_p),
+                ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double)]
 
 
 _SIGS = {

@@ -186,7 +186,10 @@ def solve(A, B, n_e, n_s, sigmas=None, omega_top=None, opts=None, check=True):
                            C.byref(rep))
     if check:
         _check(st, "sislice_solve")
-    report = {f: getattr(rep, f) for f, _ in Report._fields_ if f not in ("nu", "slice_case", "slice_exact", "slice_cand")}
+    skip = ("nu", "slice_case", "slice_exact", "slice_cand", "t_kern_ms", "n_kern")
+    report = {f: getattr(rep, f) for f, _ in Report._fields_ if f not in skip}
+    report["t_kern_ms"] = list(rep.t_kern_ms)
+    report["n_kern"] = list(rep.n_kern)
     report.update(nu=nu, slice_case=sc, slice_exact=se, slice_cand=sd)
     return dict(evals=ev, evecs=Xt.t(), resid=rs, status=st, omega_top=top.value, report=report)
 

@@ -12,6 +12,7 @@
 // global->LDS load pattern (always along the contiguous dimension).
 #include "blas.hpp"
 #include "common.hpp"
+#include "handle.hpp"
 
 namespace sislice {
 
@@ -138,6 +139,8 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
     g.pstride = (long)mmax * nmax;
   }
   dim3 grid((unsigned)ceil_div(mmax, GT), (unsigned)ceil_div(nmax, GT), (unsigned)(batch * g.splits));
+  sislice_handle* ph = current_handle();
+  const int tk = prof_begin(ph, kProfGemm);
   if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
   if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, g);
   if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, g);
@@ -149,6 +152,7 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
                        dim3(256), 0, st, g);
     SL_LAUNCH_CHECK();
   }
+  prof_end(ph, tk);
 }
 
 // F (n x n, ldf) = symmetric completion of the lower triangle of S (lds), tiled

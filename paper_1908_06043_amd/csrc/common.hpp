@@ -55,6 +55,8 @@ struct FactorState {
   int32_t done;      // 1 once every column is factored
   int32_t npanel;    // panels factored so far
   int64_t neg, zero, pos;  // inertia of D accumulated over the pivots
+  int32_t jstart;    // columns of the current panel accepted by the pivot-free path
+  int32_t pad;
 };
 
 // Largest panel width the factorization kernels are built for.

@@ -503,6 +503,9 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   const auto t_start = Clock::now();
   const int n = (int)n64;
   const int P = (int)n_s;
+  set_current_handle(h);
+  prof_reset(h);
+  h->prof = o.profile != 0;
   const int b = kLanczosBlock;
   hipStream_t st = h->stream;
   std::vector<double> sig(P);
@@ -1161,6 +1164,31 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   SL_HIP(hipStreamSynchronize(st));
   ring.synced();
   const double t_host = ms_since(t_h0);
+  if (rep && o.profile) {
+    for (int q = 0; q < 6; ++q) {
+      rep->t_kern_ms[q] = 0.0;
+      rep->n_kern[q] = 0;
+    }
+    prof_collect(h, rep->t_kern_ms, rep->n_kern);
+    // algorithmic flops of the trailing updates from the panel starts of every shift
+    std::vector<int> ps((size_t)S1 * fp.npmax);
+    std::vector<FactorState> fs(S1);
+    SL_HIP(hipMemcpy(ps.data(), fp.pstart_base, sizeof(int) * ps.size(), hipMemcpyDeviceToHost));
+    SL_HIP(hipMemcpy(fs.data(), fp.d_state, sizeof(FactorState) * S1, hipMemcpyDeviceToHost));
+    double fl = 0.0;
+    for (int s = 0; s < S1; ++s) {
+      const int np = fs[s].npanel;
+      for (int q = 0; q < np; ++q) {
+        const int k0 = ps[(size_t)s * fp.npmax + q];
+        const int k1 = q + 1 < np ? ps[(size_t)s * fp.npmax + q + 1] : n;
+        const double m = (double)(n - k1);
+        fl += m * (m + 1.0) * (double)(k1 - k0);
+      }
+    }
+    rep->flops_update = fl;
+  }
+  prof_reset(h);
+  h->prof = false;
   if (rep) {
     rep->n_validated = nval;
     rep->n_converged = nconv;

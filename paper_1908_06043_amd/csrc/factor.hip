@@ -21,9 +21,11 @@
 // Panel widths depend on the pivots (nb-1 or nb columns), so the per-shift
 // progress lives in device memory (FactorState) and the host launches an upper
 // bound of panel/update pairs; launches past the end return at once.
+#include <algorithm>
 #include <climits>
 
 #include "common.hpp"
+#include "handle.hpp"
 #include "kernels.hpp"
 
 namespace sislice {
@@ -97,7 +99,191 @@ __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states,
     z.done = (n == 0);
     z.npanel = 0;
     z.neg = z.zero = z.pos = 0;
+    z.jstart = 0;
+    z.pad = 0;
     states[s] = z;
+  }
+}
+
+
+// ---------------------------------------------------------------- pivot-free path
+//
+// Bunch-Kaufman takes a 1x1 pivot without interchange at column k exactly when
+// |d_k| >= alpha * max_{i>k} |s_ik| for the Schur-complement column s at step k.
+// As long as that holds for every column, the factorization is the pivot-free
+// LDL^T, which parallelises like Cholesky: the panel's diagonal block is factored
+// in LDS (k_fast_diag), the rows below follow from one triangular solve with the
+// block (k_fast_trsm: W21 = C21 L11^{-T}, L21 = W21 D1^{-1}) together with the
+// column maxima of |W|, and k_fast_commit accepts the longest prefix of columns
+// that pass the test.  The pivoting panel kernel then continues from the first
+// rejected column, so the result is the Bunch-Kaufman factorization itself.
+
+__device__ __forceinline__ double u64_to_f64(unsigned long long v) { return __longlong_as_double((long long)v); }
+
+__global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* LDs, long ldld,
+                                                   double* const* Wps, long ldw,
+                                                   double* const* Lps, double* const* auxs,
+                                                   const FactorState* states, int nb) {
+  __shared__ double A[kMaxNb][kMaxNb + 1];
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const FactorState st = states[s];
+  const int k0 = st.k0 + st.kb;
+  if (st.done || k0 >= n) return;
+  const int nbe = min(nb, n - k0);
+  const double* LD = LDs[s];
+  double* Wp = Wps[s];
+  double* Lp = Lps[s];
+  double* aux = auxs[s];
+  double* Dv = aux;
+  double* cin = aux + nb;
+  unsigned long long* cout = reinterpret_cast<unsigned long long*>(aux + 2 * nb);
+  double* Linv = aux + 3 * nb;
+  for (int e = tid; e < kMaxNb * kMaxNb; e += 256) {
+    const int i = e & (kMaxNb - 1), j = e / kMaxNb;
+    A[i][j] = (i < nbe && j < nbe && i >= j) ? LD[(k0 + i) + (long)(k0 + j) * ldld] : 0.0;
+  }
+  for (int c = tid; c < nb; c += 256) cout[c] = 0ull;
+  __syncthreads();
+  for (int k = 0; k < nbe; ++k) {
+    const double d = A[k][k];
+    const int m = nbe - k - 1;
+    for (int e = tid; e < m * m; e += 256) {
+      const int ii = k + 1 + e % m, jj = k + 1 + e / m;
+      if (ii >= jj) A[ii][jj] -= A[ii][k] * (A[jj][k] / d);
+    }
+    __syncthreads();
+  }
+  // outputs: D, unscaled W and scaled L of the block, column maxima inside the block
+  for (int e = tid; e < nbe * nbe; e += 256) {
+    const int i = e % nbe, k = e / nbe;
+    if (i >= k) {
+      const double w = A[i][k];
+      Wp[(k0 + i) + (long)k * ldw] = w;
+      if (i > k) Lp[(k0 + i) + (long)k * ldw] = w / A[k][k];
+    }
+  }
+  if (tid < nbe) {
+    const int k = tid;
+    double mx = 0.0;
+    for (int i = k + 1; i < nbe; ++i) {
+      const double a = fabs(A[i][k]);
+      mx = (a > mx || a != a) ? a : mx;
+    }
+    cin[k] = mx;
+    Dv[k] = A[k][k];
+  }
+  __syncthreads();
+  // Linv = L11^{-1} (unit lower), one column per thread, column-major nb x nb
+  if (tid < nbe) {
+    const int c = tid;
+    for (int i = 0; i < nbe; ++i) {
+      double x = (i == c) ? 1.0 : 0.0;
+      if (i > c)
+        for (int k = c; k < i; ++k) x -= (A[i][k] / A[k][k]) * Linv[k + (long)c * nb];
+      Linv[i + (long)c * nb] = (i >= c) ? x : 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* LDs, long ldld,
+                                                   double* const* Wps, long ldw,
+                                                   double* const* Lps, double* const* auxs,
+                                                   const FactorState* states, int nb) {
+  __shared__ double C[64][kMaxNb + 1];
+  __shared__ double Li[kMaxNb][kMaxNb + 1];
+  __shared__ double Dsh[kMaxNb];
+  const int s = blockIdx.y, tid = threadIdx.x;
+  const FactorState st = states[s];
+  const int k0 = st.k0 + st.kb;
+  if (st.done || k0 >= n) return;
+  const int nbe = min(nb, n - k0);
+  const int r0 = k0 + nbe + 64 * blockIdx.x;
+  if (r0 >= n) return;
+  const double* LD = LDs[s];
+  double* Wp = Wps[s];
+  double* Lp = Lps[s];
+  const double* aux = auxs[s];
+  unsigned long long* cout = reinterpret_cast<unsigned long long*>(const_cast<double*>(aux) + 2 * nb);
+  const double* Linv = aux + 3 * nb;
+  for (int e = tid; e < 64 * nbe; e += 256) {
+    const int r = e & 63, k = e >> 6;
+    C[r][k] = (r0 + r < n) ? LD[(r0 + r) + (long)(k0 + k) * ldld] : 0.0;
+  }
+  for (int e = tid; e < nbe * nbe; e += 256) {
+    const int i = e % nbe, k = e / nbe;
+    Li[i][k] = Linv[i + (long)k * nb];
+  }
+  if (tid < nbe) Dsh[tid] = aux[tid];
+  __syncthreads();
+  // wavefront cg handles columns cg, cg+4, ...; lane r handles row r0 + r
+  const int r = tid & 63, cg = tid >> 6;
+  for (int c = cg; c < nbe; c += 4) {
+    double w = 0.0;
+    for (int k = 0; k <= c; ++k) w += C[r][k] * Li[c][k];
+    if (r0 + r < n) {
+      Wp[(r0 + r) + (long)c * ldw] = w;
+      Lp[(r0 + r) + (long)c * ldw] = w / Dsh[c];
+    }
+    double mx = (r0 + r < n) ? fabs(w) : 0.0;
+    if (mx != mx) mx = __longlong_as_double(0x7FF0000000000000ll);  // NaN ranks as +inf
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (r == 0) atomicMax(cout + c, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+template <bool PIVOT>
+__global__ __launch_bounds__(256) void k_fast_commit(int n, double* const* LDs, long ldld,
+                                                     const double* const* Lps, long ldw,
+                                                     const double* const* auxs, int* const* blks,
+                                                     int* const* colpanels, FactorState* states,
+                                                     int nb) {
+  __shared__ int js;
+  const int s = blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
+  const FactorState st = states[s];
+  const int k0 = st.k0 + st.kb;
+  if (st.done || k0 >= n) return;
+  const int nbe = min(nb, n - k0);
+  if (c >= nbe) return;
+  const double* aux = auxs[s];
+  const double* Dv = aux;
+  const double* cin = aux + nb;
+  const unsigned long long* cout = reinterpret_cast<const unsigned long long*>(aux + 2 * nb);
+  if (tid == 0) {
+    int j = 0;
+    for (; j < nbe; ++j) {
+      const double d = Dv[j];
+      const double cm = fmax(cin[j], u64_to_f64(cout[j]));
+      bool ok = isfinite(d) && d != 0.0 && isfinite(cm) && cin[j] == cin[j];
+      if (PIVOT) ok = ok && fabs(d) >= kBkAlpha * cm;
+      if (!ok) break;
+    }
+    js = j;
+  }
+  __syncthreads();
+  const int jst = js;
+  if (c < jst) {
+    double* LD = LDs[s];
+    const double* Lp = Lps[s];
+    const int col = k0 + c;
+    for (int i = col + 1 + tid; i < n; i += 256) LD[i + (long)col * ldld] = Lp[i + (long)c * ldw];
+    if (tid == 0) {
+      LD[col + (long)col * ldld] = Dv[c];
+      blks[s][col] = 1;
+      colpanels[s][col] = st.npanel;
+    }
+  }
+  if (c == 0 && tid == 0) {
+    long neg = 0, pos = 0;
+    for (int q = 0; q < jst; ++q) {
+      if (Dv[q] < 0.0)
+        ++neg;
+      else
+        ++pos;
+    }
+    states[s].jstart = jst;
+    states[s].neg += neg;
+    states[s].pos += pos;
   }
 }
 
@@ -106,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
                                                    double* const* Wps, long ldw, int* const* perms,
                                                    int* const* swps, int* const* blks,
                                                    int* const* colpanels, int* const* pstarts,
-                                                   FactorState* states, int nb) {
+                                                   FactorState* states, int nb, int nbpiv) {
   constexpr int NT = 1024, NW = NT / 64;
   const int s = blockIdx.x, tid = threadIdx.x;
   FactorState* st = states + s;
@@ -122,13 +308,14 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
   __shared__ double red_v[NW];
   __shared__ int red_i[NW];
   __shared__ double sh_absakk, sh_arr;
-  __shared__ int sh_k0, sh_done, sh_panel;
+  __shared__ int sh_k0, sh_done, sh_panel, sh_jstart;
 
   if (tid == 0) {
     const int k0 = st->k0 + st->kb;
     sh_k0 = k0;
     sh_done = (k0 >= n) || st->done;
     sh_panel = st->npanel;
+    sh_jstart = st->jstart;
   }
   __syncthreads();
   if (sh_done) {
@@ -141,10 +328,12 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
   }
   const int k0 = sh_k0, P = sh_panel;
   const int rem = n - k0;
-  const int jmax = (rem <= nb) ? rem : nb - 1;
+  const int jstart = sh_jstart;
+  const int jmax0 = (rem <= nb) ? rem : nb - 1;
+  const int jmax = min(jmax0, jstart + nbpiv);
   long neg = 0, zer = 0, pos = 0;
 
-  int j = 0;
+  int j = jstart;
   while (j < jmax) {
     const int k = k0 + j;
     // row k of the panel's W
@@ -153,18 +342,45 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
     // column k of the Schur complement -> W(:, j); argmax below the diagonal
     double bv = -1.0;
     int bi = INT_MAX;
-    for (int i = k + tid; i < n; i += NT) {
-      double acc = LD[i + (long)k * ldld];
-      const double* Lr = LD + i + (long)k0 * ldld;
-      for (int p = 0; p < j; ++p) acc -= Lr[(long)p * ldld] * wk[p];
-      Wp[i + (long)j * ldw] = acc;
-      if (i == k) {
-        sh_absakk = fabs(acc);
+    for (int i0 = k + tid; i0 < n; i0 += 2 * NT) {
+      const int i1 = i0 + NT;
+      const bool two = i1 < n;
+      double a0 = LD[i0 + (long)k * ldld], a1 = two ? LD[i1 + (long)k * ldld] : 0.0;
+      double b0 = 0.0, b1 = 0.0;
+      const double* L0 = LD + i0 + (long)k0 * ldld;
+      const double* L1 = LD + (two ? i1 : i0) + (long)k0 * ldld;
+      int p = 0;
+      for (; p + 1 < j; p += 2) {
+        const double w0 = wk[p], w1 = wk[p + 1];
+        const double x00 = L0[(long)p * ldld], x01 = L0[(long)(p + 1) * ldld];
+        const double x10 = L1[(long)p * ldld], x11 = L1[(long)(p + 1) * ldld];
+        a0 -= x00 * w0;
+        b0 -= x01 * w1;
+        a1 -= x10 * w0;
+        b1 -= x11 * w1;
+      }
+      if (p < j) {
+        a0 -= L0[(long)p * ldld] * wk[p];
+        a1 -= L1[(long)p * ldld] * wk[p];
+      }
+      a0 += b0;
+      a1 += b1;
+      Wp[i0 + (long)j * ldw] = a0;
+      if (two) Wp[i1 + (long)j * ldw] = a1;
+      if (i0 == k) {
+        sh_absakk = fabs(a0);
       } else {
-        const double a = fabs(acc);
+        const double a = fabs(a0);
         if (a > bv) {
           bv = a;
-          bi = i;
+          bi = i0;
+        }
+      }
+      if (two) {
+        const double a = fabs(a1);
+        if (a > bv) {
+          bv = a;
+          bi = i1;
         }
       }
     }
@@ -327,6 +543,7 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
     st->neg += neg;
     st->zero += zer;
     st->pos += pos;
+    st->jstart = 0;
     pstart[P] = k0;
   }
 }
@@ -483,25 +700,71 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
   hipLaunchKernelGGL(k_factor_init, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
                      fp.d_state, fp.d_perm, fp.d_sw);
   SL_LAUNCH_CHECK();
-  const int npmax = (int)ceil_div(n, nb - 1) + 1;
-  for (int p = 0; p < npmax; ++p) {
-    if (fp.pivot)
-      hipLaunchKernelGGL(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W,
-                         fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart,
-                         fp.d_state, nb);
-    else
-      hipLaunchKernelGGL(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
-                         fp.d_W, fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel,
-                         fp.d_pstart, fp.d_state, nb);
-    SL_LAUNCH_CHECK();
-    const long k1_lb = (long)(p + 1) * (nb - 1);
-    if (k1_lb >= n) continue;
-    const long T = ceil_div(n - k1_lb, 64);
-    const size_t lds = (size_t)2 * ((nb + 3) & ~3) * 64 * sizeof(double);
-    hipLaunchKernelGGL(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), lds,
-                       st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
-    SL_LAUNCH_CHECK();
+  sislice_handle* ph = current_handle();
+  const int nbpiv = fp.fast ? fp.nbpiv : nb;
+  const int min_kb = factor_min_panel(nb, fp.nbpiv, fp.fast != 0);
+  // Panel widths depend on the pivots: launch chunks of panel steps and read the
+  // per-shift progress back between chunks (kmin = least factored prefix).
+  constexpr int kChunk = 8;
+  FactorState* hs = static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S));
+  long kmin = 0;
+  int steps = 0;
+  const int step_cap = factor_npanel_max(n, nb, fp.nbpiv, fp.fast != 0);
+  SL_CHECK_ARG(step_cap <= fp.npmax, "panel bookkeeping smaller than the step bound");
+  while (kmin < n && steps < step_cap) {
+    for (int q = 0; q < kChunk && steps < step_cap; ++q, ++steps) {
+      // lower bound of this step's first column: kmin + q * min_kb
+      const long k0_lb = std::min<long>(n, kmin + (long)q * min_kb);
+      if (fp.fast) {
+        const int tf = prof_begin(ph, kProfPanel);
+        hipLaunchKernelGGL(k_fast_diag, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
+                           fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+        SL_LAUNCH_CHECK();
+        const long rows = n - k0_lb - 1;
+        if (rows > 0) {
+          hipLaunchKernelGGL(k_fast_trsm, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+                             (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                             fp.d_state, nb);
+          SL_LAUNCH_CHECK();
+        }
+        if (fp.pivot)
+          hipLaunchKernelGGL(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+                             (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
+                             fp.d_blk, fp.d_colpanel, fp.d_state, nb);
+        else
+          hipLaunchKernelGGL(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+                             (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
+                             fp.d_blk, fp.d_colpanel, fp.d_state, nb);
+        SL_LAUNCH_CHECK();
+        prof_end(ph, tf);
+      }
+      const int tp = prof_begin(ph, kProfPanel);
+      if (fp.pivot)
+        hipLaunchKernelGGL(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W,
+                           fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart,
+                           fp.d_state, nb, nbpiv);
+      else
+        hipLaunchKernelGGL(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
+                           fp.d_W, fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel,
+                           fp.d_pstart, fp.d_state, nb, nbpiv);
+      SL_LAUNCH_CHECK();
+      prof_end(ph, tp);
+      const long k1_lb = std::min<long>(n, k0_lb + min_kb);
+      if (k1_lb >= n) continue;
+      const long T = ceil_div(n - k1_lb, 64);
+      const size_t lds = (size_t)2 * ((nb + 3) & ~3) * 64 * sizeof(double);
+      const int tu = prof_begin(ph, kProfUpdate);
+      hipLaunchKernelGGL(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), lds,
+                         st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+      SL_LAUNCH_CHECK();
+      prof_end(ph, tu);
+    }
+    SL_HIP(hipMemcpyAsync(hs, fp.d_state, sizeof(FactorState) * S, hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    kmin = n;
+    for (int q = 0; q < S; ++q) kmin = std::min<long>(kmin, hs[q].done ? n : hs[q].k0 + hs[q].kb);
   }
+  SL_CHECK_ARG(kmin >= n, "factorization did not complete");
   if (fp.pivot) {
     static bool attr_set = false;
     if (!attr_set) {

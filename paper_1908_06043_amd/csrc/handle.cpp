@@ -1,6 +1,7 @@
 // Handle lifecycle, workspaces, status strings and the factorization entry points.
 #include "handle.hpp"
 
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -9,9 +10,14 @@
 
 namespace sislice {
 
+static thread_local sislice_handle* g_current = nullptr;
+sislice_handle* current_handle() { return g_current; }
+void set_current_handle(sislice_handle* h) { g_current = h; }
+
 void check_handle(sislice_handle* h) {
   SL_CHECK_ARG(h != nullptr, "null handle");
   SL_HIP(hipSetDevice(h->device));
+  set_current_handle(h);
 }
 
 void* ws_get(sislice_handle* h, int id, size_t bytes) {
@@ -71,13 +77,50 @@ unsigned* sync_words(sislice_handle* h, size_t words) {
   return h->sync;
 }
 
+int prof_begin(sislice_handle* h, int cat) {
+  if (!h || !h->prof) return -1;
+  if (h->evnext + 2 > h->evpool.size()) {
+    const size_t grow = std::max<size_t>(256, h->evpool.size());
+    for (size_t q = 0; q < grow; ++q) {
+      hipEvent_t e;
+      SL_HIP(hipEventCreate(&e));
+      h->evpool.push_back(e);
+    }
+  }
+  hipEvent_t a = h->evpool[h->evnext++];
+  hipEvent_t b = h->evpool[h->evnext++];
+  SL_HIP(hipEventRecord(a, h->stream));
+  h->recs.push_back({cat, a, b});
+  return (int)h->recs.size() - 1;
+}
+
+void prof_end(sislice_handle* h, int ticket) {
+  if (!h || ticket < 0) return;
+  SL_HIP(hipEventRecord(h->recs[ticket].b, h->stream));
+}
+
+void prof_collect(sislice_handle* h, double* ms, int64_t* count) {
+  for (const auto& r : h->recs) {
+    float t = 0.f;
+    SL_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cat] += t;
+    count[r.cat] += 1;
+  }
+}
+
+void prof_reset(sislice_handle* h) {
+  h->recs.clear();
+  h->evnext = 0;
+}
+
 int default_nb(int n) { return n >= 2048 ? 64 : 32; }
 
 FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, long lda,
                         const double* B, long ldb, int S, const double* sigmas_host,
                         double* const* LD_host, long ldld, int32_t* const* ipiv_host, int nb,
                         bool pivot) {
-  const int npmax = factor_npanel_max(n, nb);
+  const FactorPlan defaults;
+  const int npmax = factor_npanel_max(n, nb, defaults.nbpiv, defaults.fast != 0);
   const long ldw = n;
   Sizer z;
   z.take<double>(S);                          // sigmas
@@ -87,7 +130,9 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   z.take<int>((size_t)S * npmax * n);
   z.take<FactorState>(S);
   z.take<int64_t>(3 * (size_t)S);
-  z.take<void*>(9 * (size_t)S);
+  z.take<void*>(11 * (size_t)S);
+  z.take<double>((size_t)S * ldw * nb);            // Lp
+  z.take<double>((size_t)S * (3 * nb + nb * nb));   // aux
   Carver c(ws_get(h, bufid, z.off));
   FactorPlan fp;
   fp.n = n;
@@ -110,9 +155,11 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   int* snap = c.take<int>((size_t)S * npmax * n);
   fp.d_state = c.take<FactorState>(S);
   fp.d_inertia = c.take<int64_t>(3 * (size_t)S);
-  void** tab = c.take<void*>(9 * (size_t)S);
-  // host staging: sigmas then the nine pointer tables
-  size_t hbytes = sizeof(double) * S + sizeof(void*) * 9 * S;
+  void** tab = c.take<void*>(11 * (size_t)S);
+  double* Lp = c.take<double>((size_t)S * ldw * nb);
+  double* aux = c.take<double>((size_t)S * (3 * nb + nb * nb));
+  // host staging: sigmas then the pointer tables
+  size_t hbytes = sizeof(double) * S + sizeof(void*) * 11 * S;
   char* hs = static_cast<char*>(host_stage(h, hbytes));
   std::memcpy(hs, sigmas_host, sizeof(double) * S);
   void** ht = reinterpret_cast<void**>(hs + sizeof(double) * S);
@@ -126,9 +173,11 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
     ht[6 * S + s] = ps + (size_t)s * npmax;
     ht[7 * S + s] = snap + (size_t)s * npmax * n;
     ht[8 * S + s] = ipiv_host[s];
+    ht[9 * S + s] = Lp + (size_t)s * ldw * nb;
+    ht[10 * S + s] = aux + (size_t)s * (3 * nb + nb * nb);
   }
   SL_HIP(hipMemcpyAsync(d_sig, hs, sizeof(double) * S, hipMemcpyHostToDevice, h->stream));
-  SL_HIP(hipMemcpyAsync(tab, ht, sizeof(void*) * 9 * S, hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(tab, ht, sizeof(void*) * 11 * S, hipMemcpyHostToDevice, h->stream));
   fp.d_sigmas = d_sig;
   fp.d_LD = reinterpret_cast<double* const*>(tab + 0 * S);
   fp.d_W = reinterpret_cast<double* const*>(tab + 1 * S);
@@ -137,8 +186,12 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   fp.d_blk = reinterpret_cast<int* const*>(tab + 4 * S);
   fp.d_colpanel = reinterpret_cast<int* const*>(tab + 5 * S);
   fp.d_pstart = reinterpret_cast<int* const*>(tab + 6 * S);
+  fp.pstart_base = ps;
+  fp.npmax = npmax;
   fp.d_snap = reinterpret_cast<int* const*>(tab + 7 * S);
   fp.d_ipiv = reinterpret_cast<int* const*>(tab + 8 * S);
+  fp.d_Lp = reinterpret_cast<double* const*>(tab + 9 * S);
+  fp.d_aux = reinterpret_cast<double* const*>(tab + 10 * S);
   return fp;
 }
 
@@ -173,6 +226,7 @@ void sislice_default_opts(sislice_opts* o) {
   o->tol = 1e-10;
   o->top_margin = 2.0;
   o->seed = 0;
+  o->profile = 0;
 }
 
 const char* sislice_status_string(sislice_status s) {
@@ -218,6 +272,7 @@ sislice_status sislice_destroy(sislice_handle* h) {
   if (h->host_stage) hipHostFree(h->host_stage);
   if (h->sync) hipFree(h->sync);
   if (h->ring_host) hipHostFree(h->ring_host);
+  for (auto e : h->evpool) hipEventDestroy(e);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);
   delete h;

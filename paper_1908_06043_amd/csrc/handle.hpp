@@ -21,6 +21,15 @@ struct sislice_handle {
   unsigned epoch = 0;
   void* ring_host = nullptr;  // pinned ring for per-step pointer tables
   size_t ring_cap = 0;
+  // kernel-class timing with HIP events (enabled per call)
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evnext = 0;
+  struct ProfRec {
+    int cat;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> recs;
 };
 
 namespace sislice {
@@ -71,5 +80,18 @@ void check_handle(sislice_handle* h);
 // re-zeroes) on demand.  Returns the base pointer.
 unsigned* sync_words(sislice_handle* h, size_t words);
 inline unsigned next_epoch(sislice_handle* h) { return ++h->epoch; }
+
+// Kernel-class timing: prof_begin records an event before a launch on the
+// handle's stream and returns a ticket; prof_end records the closing event.
+// prof_collect (after a stream synchronisation) sums durations per class.
+enum ProfCat { kProfPanel = 0, kProfUpdate = 1, kProfSolve = 2, kProfGemm = 3, kProfEig = 4, kProfOther = 5 };
+int prof_begin(sislice_handle* h, int cat);
+void prof_end(sislice_handle* h, int ticket);
+void prof_collect(sislice_handle* h, double* ms, int64_t* count);
+void prof_reset(sislice_handle* h);
+
+// The handle whose stream receives the current launches (set by entry points).
+sislice_handle* current_handle();
+void set_current_handle(sislice_handle* h);
 
 }  // namespace sislice

@@ -1,6 +1,8 @@
 // Launch plans of the device kernels (internal to the library).
 #pragma once
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace sislice {
@@ -26,10 +28,30 @@ struct FactorPlan {
   int* const* d_ipiv = nullptr;
   FactorState* d_state = nullptr;
   int64_t* d_inertia = nullptr;  // device [3 * nshift]
+  int* pstart_base = nullptr;    // device [nshift * npmax] panel starts
+  int npmax = 0;
+  // pivot-free speculative panel path (per shift): staged L of the panel (n x nb),
+  // D of the panel, inverse of the diagonal block (nb x nb), column maxima
+  double* const* d_Lp = nullptr;
+  double* const* d_aux = nullptr;  // [nb] D | [nb] max|w| in block | [nb] max|w| below (uint64 bits) | nb*nb Linv
+  int fast = 1;                    // use the pivot-free path
+  int nbpiv = 16;                  // columns a pivoting panel handles after a rejection
 };
 
 void factor_launch(const FactorPlan& fp, hipStream_t st);
 
-inline int factor_npanel_max(int n, int nb) { return (int)ceil_div(n, nb - 1) + 1; }
+// Narrowest panel that is not the last one: a pivoting panel stops at nb - 1
+// columns (room for a closing 2x2 pivot) and, behind the pivot-free path, after
+// nbpiv columns from the first rejected one.
+inline int factor_min_panel(int nb, int nbpiv, bool fast) {
+  const int w = fast ? std::min(nbpiv, nb - 1) : nb - 1;
+  return w < 1 ? 1 : w;
+}
+
+// Upper bound on the number of panel steps (and so on the panels) of one
+// factorization; sizes the panel-start and interchange-snapshot arrays.
+inline int factor_npanel_max(int n, int nb, int nbpiv, bool fast) {
+  return (int)ceil_div(n, factor_min_panel(nb, nbpiv, fast)) + 2;
+}
 
 }  // namespace sislice

@@ -13,6 +13,7 @@
 // The block-diagonal D^{-1} (1x1 and 2x2 pivots) is applied at the start of the
 // backward sweep.
 #include "common.hpp"
+#include "handle.hpp"
 #include "solve.hpp"
 
 namespace sislice {
@@ -103,9 +104,14 @@ __device__ __forceinline__ void post_flag(unsigned* flag, unsigned epoch) {
 }
 
 // Forward sweep: Z = L^{-1} P Y.  256 threads; thread (i = tid % 64, q = tid / 64)
-// owns rows i of columns q, q+4, ... of the block.
+// owns rows i of columns q, q+4, ... of the block.  The L blocks do not depend on
+// other workgroups, so the next one is prefetched into registers before the
+// flag of the current one is awaited; only the 64 x nrhs block of Z is read
+// after the hand-off.  Inside an off-diagonal block the only slot that can hold
+// D's 2x2 off-diagonal instead of L is its top-right corner (row r0, column
+// r0 - 1), which is zeroed when the column starts a 2x2 pivot.
 __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
-  __shared__ double sM[SB][SB + 1];   // an L block or the diagonal inverse
+  __shared__ double sM[SB][SB + 1];
   __shared__ double sZ[kSolveMaxRhs][SB];
   const int s = blockIdx.y, tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
@@ -118,20 +124,43 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   double* Z = a.Z[s];
   unsigned* flags = a.flags + (long)s * a.flag_stride;
   const int r0 = b * SB;
+  const int row = r0 + i;
+  // everything that does not depend on other blocks is issued first
+  double inv[SB * SB / 256];
+  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+#pragma unroll
+  for (int q = 0; q < SB * SB / 256; ++q) inv[q] = Linv[tid + 256 * q];
+  const bool corner_zero = (b > 0) && (blk[r0 - 1] == 2);
   double acc[kSolveMaxRhs / 4];
 #pragma unroll
   for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
     const int c = q0 + 4 * m;
-    acc[m] = (c < nrhs && r0 + i < n) ? Y[perm[r0 + i] + (long)c * a.ldy] : 0.0;
+    acc[m] = (c < nrhs && row < n) ? Y[perm[row] + (long)c * a.ldy] : 0.0;
   }
+  // L block (rows of this block, columns of block cb): element e -> (e & 63, e >> 6)
+  double lnext[SB * SB / 256];
+  auto load_L = [&](int cb) {
+    const int c0 = cb * SB;
+#pragma unroll
+    for (int q = 0; q < SB * SB / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e & 63, kk = e >> 6;
+      lnext[q] = (r0 + rr < n) ? LD[r0 + rr + (long)(c0 + kk) * a.ldld] : 0.0;
+    }
+  };
+  if (b > 0) load_L(0);
   for (int cb = 0; cb < (int)b; ++cb) {
+    // the corner slot (row r0, column r0 - 1) is element e = 63 * 64 of the block;
+    // its owner writes the structural zero itself
+    const bool zero_now = corner_zero && cb == (int)b - 1;
+#pragma unroll
+    for (int q = 0; q < SB * SB / 256; ++q) {
+      const int e = tid + 256 * q;
+      sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
+    }
+    if (cb + 1 < (int)b) load_L(cb + 1);
     wait_flag(flags + cb, a.epoch);
     const int c0 = cb * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int rr = e & 63, kk = e >> 6;  // rows contiguous
-      const int row = r0 + rr, col = c0 + kk;
-      sM[rr][kk] = (row < n) ? lval(LD, a.ldld, blk, row, col) : 0.0;
-    }
     for (int e = tid; e < nrhs * SB; e += 256) {
       const int rr = e & 63, c = e >> 6;
       sZ[c][rr] = Z[c0 + rr + (long)c * a.ldz];
@@ -142,6 +171,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       const int c = q0 + 4 * m;
       if (c < nrhs) {
         double t = acc[m];
+#pragma unroll 16
         for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
         acc[m] = t;
       }
@@ -149,10 +179,10 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
     __syncthreads();
   }
   // diagonal block: Z_b = Linv_b * acc
-  const double* Linv = a.Linv[s] + (long)b * SB * SB;
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int rr = e & 63, kk = e >> 6;
-    sM[rr][kk] = Linv[rr + kk * SB];
+#pragma unroll
+  for (int q = 0; q < SB * SB / 256; ++q) {
+    const int e = tid + 256 * q;
+    sM[e & 63][e >> 6] = inv[q];
   }
 #pragma unroll
   for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
@@ -163,16 +193,18 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
 #pragma unroll
   for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
     const int c = q0 + 4 * m;
-    if (c < nrhs && r0 + i < n) {
+    if (c < nrhs && row < n) {
       double t = 0.0;
       for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
-      Z[r0 + i + (long)c * a.ldz] = t;
+      Z[row + (long)c * a.ldz] = t;
     }
   }
   post_flag(flags + b, a.epoch);
 }
 
-// Backward sweep: X = P^T L^{-T} D^{-1} Z.
+// Backward sweep: X = P^T L^{-T} D^{-1} Z.  The structural zero inside an
+// off-diagonal block of L^T sits at (row c0, column c0 - 1) of L, i.e. only in
+// the block right below the diagonal (cb = b + 1), at its top-right corner.
 __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   __shared__ double sM[SB][SB + 1];
   __shared__ double sV[kSolveMaxRhs][SB];
@@ -190,6 +222,11 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   unsigned* flags = a.flags + (long)s * a.flag_stride + nblk;
   const int r0 = b * SB;
   const int row = r0 + i;
+  double inv[SB * SB / 256];
+  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+#pragma unroll
+  for (int q = 0; q < SB * SB / 256; ++q) inv[q] = Linv[tid + 256 * q];
+  const bool corner_zero = (b + 1 < nblk) && (blk[r0 + SB - 1] == 2);
   double acc[kSolveMaxRhs / 4];
   // D^{-1} on this block's rows
   double d11 = 1.0, d21 = 0.0, d22 = 1.0;
@@ -228,15 +265,30 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     }
     acc[m] = v;
   }
+  // L block (rows of block cb, columns of this block): element e -> (kk = e & 63, rr = e >> 6)
+  double lnext[SB * SB / 256];
+  auto load_L = [&](int cb) {
+    const int c0 = cb * SB;
+#pragma unroll
+    for (int q = 0; q < SB * SB / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int kk = e & 63, rr = e >> 6;
+      lnext[q] = (c0 + kk < n) ? LD[c0 + kk + (long)(r0 + rr) * a.ldld] : 0.0;
+    }
+  };
+  if (b + 1 < nblk) load_L(nblk - 1);
   for (int cb = nblk - 1; cb > b; --cb) {
+    // corner slot (kk = 0, rr = 63) is element e = 63 * 64, written by its owner
+    const bool zero_now = corner_zero && cb == b + 1;
+#pragma unroll
+    for (int q = 0; q < SB * SB / 256; ++q) {
+      const int e = tid + 256 * q;
+      // sM[kk][rr] = L(c0 + kk, r0 + rr)
+      sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
+    }
+    if (cb - 1 > b) load_L(cb - 1);
     wait_flag(flags + cb, a.epoch);
     const int c0 = cb * SB;
-    // sM[kk][rr] = L(c0 + kk, r0 + rr): columns of this block, rows of block cb
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int kk = e & 63, rr = e >> 6;
-      const int lrow = c0 + kk, lcol = r0 + rr;
-      sM[kk][rr] = (lrow < n) ? lval(LD, a.ldld, blk, lrow, lcol) : 0.0;
-    }
     for (int e = tid; e < nrhs * SB; e += 256) {
       const int kk = e & 63, c = e >> 6;
       sV[c][kk] = (c0 + kk < n) ? V[c0 + kk + (long)c * a.ldz] : 0.0;
@@ -247,6 +299,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       const int c = q0 + 4 * m;
       if (c < nrhs) {
         double tt = acc[m];
+#pragma unroll 16
         for (int k = 0; k < SB; ++k) tt -= sM[k][i] * sV[c][k];
         acc[m] = tt;
       }
@@ -254,10 +307,10 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     __syncthreads();
   }
   // V_b = Linv_b^T * acc
-  const double* Linv = a.Linv[s] + (long)b * SB * SB;
-  for (int e = tid; e < SB * SB; e += 256) {
-    const int rr = e & 63, kk = e >> 6;
-    sM[rr][kk] = Linv[rr + kk * SB];
+#pragma unroll
+  for (int q = 0; q < SB * SB / 256; ++q) {
+    const int e = tid + 256 * q;
+    sM[e & 63][e >> 6] = inv[q];
   }
 #pragma unroll
   for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
@@ -291,6 +344,8 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
 
 void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   const int nblk = (int)ceil_div(a.n, SB);
+  sislice_handle* ph = current_handle();
+  const int tk = prof_begin(ph, kProfSolve);
   if (mode == 0 || mode == 1) {
     hipLaunchKernelGGL(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
@@ -299,6 +354,7 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode) {
     hipLaunchKernelGGL(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
+  prof_end(ph, tk);
 }
 
 }  // namespace sislice
