@@ -141,14 +141,14 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
   dim3 grid((unsigned)ceil_div(mmax, GT), (unsigned)ceil_div(nmax, GT), (unsigned)(batch * g.splits));
   sislice_handle* ph = current_handle();
   const int tk = prof_begin(ph, kProfGemm);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, g);
-  if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, g);
-  if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, g);
-  if (ta && tb) hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, g);
+  if (!ta && !tb) SL_LAUNCH((k_gemm<false, false>), grid, dim3(256), 0, st, g);
+  if (!ta && tb) SL_LAUNCH((k_gemm<false, true>), grid, dim3(256), 0, st, g);
+  if (ta && !tb) SL_LAUNCH((k_gemm<true, false>), grid, dim3(256), 0, st, g);
+  if (ta && tb) SL_LAUNCH((k_gemm<true, true>), grid, dim3(256), 0, st, g);
   SL_LAUNCH_CHECK();
   if (g.splits > 1) {
     const long tot = (long)mmax * nmax;
-    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096), batch),
+    SL_LAUNCH(k_gemm_reduce, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096), batch),
                        dim3(256), 0, st, g);
     SL_LAUNCH_CHECK();
   }
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void k_sym_full(int n, const double* __restric
 
 void sym_full_launch(int n, const double* S, long lds, double* F, long ldf, hipStream_t st) {
   const unsigned T = (unsigned)ceil_div(n, 32);
-  hipLaunchKernelGGL(k_sym_full, dim3(T, T), dim3(256), 0, st, n, S, lds, F, ldf);
+  SL_LAUNCH(k_sym_full, dim3(T, T), dim3(256), 0, st, n, S, lds, F, ldf);
   SL_LAUNCH_CHECK();
 }
 
@@ -228,9 +228,9 @@ __global__ __launch_bounds__(256) void k_coldot_reduce(ColDotArgs a) {
 void coldot_launch(ColDotArgs a, int batch, int maxcol, hipStream_t st) {
   a.maxcol = maxcol;
   a.nchunk = (int)ceil_div(a.n, kDotChunk);
-  hipLaunchKernelGGL(k_coldot_partial, dim3(a.nchunk, maxcol, batch), dim3(256), 0, st, a);
+  SL_LAUNCH(k_coldot_partial, dim3(a.nchunk, maxcol, batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_coldot_reduce, dim3(batch), dim3(256), 0, st, a);
+  SL_LAUNCH(k_coldot_reduce, dim3(batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
 
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_rademacher_block(int n, int ncol, unsig
 void gauss_launch(int n, int ncol, int batch, const unsigned long long* d_seeds, double* const* X,
                   long ldx, hipStream_t st) {
   const long tot = (long)n * ncol;
-  hipLaunchKernelGGL(k_gauss_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048), batch),
+  SL_LAUNCH(k_gauss_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048), batch),
                      dim3(256), 0, st, n, ncol, d_seeds, X, ldx);
   SL_LAUNCH_CHECK();
 }
@@ -277,7 +277,7 @@ void gauss_launch(int n, int ncol, int batch, const unsigned long long* d_seeds,
 void rademacher_launch(int n, int ncol, unsigned long long seed, double* X, long ldx,
                        hipStream_t st) {
   const long tot = (long)n * ncol;
-  hipLaunchKernelGGL(k_rademacher_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048)),
+  SL_LAUNCH(k_rademacher_block, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 2048)),
                      dim3(256), 0, st, n, ncol, seed, X, ldx);
   SL_LAUNCH_CHECK();
 }

@@ -38,7 +38,12 @@ double ms_since(Clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-// Pinned host ring + device ring for the small per-launch tables.
+// Pinned host ring + device ring for the small per-launch tables.  put() only
+// stages a table in the host ring; the tables staged since the last launch go
+// to the device in one copy, issued by the launch macro just before the next
+// kernel (stream order then delivers them first).  The host bytes stay untouched
+// until the stream has passed that copy: the ring is rewound only after a
+// stream synchronisation.
 class Ring {
  public:
   explicit Ring(sislice_handle* h, size_t cap = 16u << 20) : h_(h), cap_(cap) {
@@ -54,23 +59,44 @@ class Ring {
     }
     host_ = static_cast<char*>(h->ring_host);
     dev_ = static_cast<char*>(ws_get(h, kBufRing, cap));
+    h->flush_fn = &Ring::flush_thunk;
+    h->flush_ctx = this;
   }
+  ~Ring() {
+    if (h_->flush_ctx == this) {
+      try {
+        flush();
+      } catch (...) {
+      }
+      h_->flush_fn = nullptr;
+      h_->flush_ctx = nullptr;
+    }
+  }
+  Ring(const Ring&) = delete;
+  Ring& operator=(const Ring&) = delete;
   void* put(const void* src, size_t bytes) {
     if (bytes == 0) bytes = 8;
     const size_t b = (bytes + 255) & ~size_t(255);
     SL_CHECK_ARG(b <= cap_, "table too large for the upload ring");
     if (off_ + b > cap_) {
+      flush();
       SL_HIP(hipStreamSynchronize(h_->stream));
-      off_ = 0;
+      off_ = pend_ = 0;
     }
     if (src)
       std::memcpy(host_ + off_, src, bytes);
     else
       std::memset(host_ + off_, 0, bytes);
-    SL_HIP(hipMemcpyAsync(dev_ + off_, host_ + off_, bytes, hipMemcpyHostToDevice, h_->stream));
     void* r = dev_ + off_;
     off_ += b;
     return r;
+  }
+  void flush() {
+    if (off_ > pend_) {
+      SL_HIP(hipMemcpyAsync(dev_ + pend_, host_ + pend_, off_ - pend_, hipMemcpyHostToDevice,
+                            h_->stream));
+      pend_ = off_;
+    }
   }
   template <class T>
   T* vec(const std::vector<T>& v) {
@@ -85,14 +111,24 @@ class Ring {
     return reinterpret_cast<const T* const*>(
         put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
   }
-  void synced() { off_ = 0; }
+  // caller has synchronised the stream: every uploaded table has been consumed;
+  // tables still staged are uploaded (and waited for) before the ring rewinds
+  void synced() {
+    if (off_ > pend_) {
+      flush();
+      SL_HIP(hipStreamSynchronize(h_->stream));
+    }
+    off_ = pend_ = 0;
+  }
 
  private:
+  static void flush_thunk(void* self) { static_cast<Ring*>(self)->flush(); }
   sislice_handle* h_;
   size_t cap_;
   char* host_;
   char* dev_;
   size_t off_ = 0;
+  size_t pend_ = 0;
 };
 
 struct Ctx {

@@ -174,7 +174,7 @@ void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
   const size_t lds = eig_lds_bytes(mmax);
   SL_CHECK_ARG(lds <= 160 * 1024, "projected problem too large for the LDS eigensolver");
   const int tk = prof_begin(current_handle(), kProfEig);
-  hipLaunchKernelGGL(k_syevj, dim3(batch), dim3(1024), lds, st, a);
+  SL_LAUNCH(k_syevj, dim3(batch), dim3(1024), lds, st, a);
   SL_LAUNCH_CHECK();
   prof_end(current_handle(), tk);
 }

@@ -124,7 +124,11 @@ __global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* L
                                                    double* const* Wps, long ldw,
                                                    double* const* Lps, double* const* auxs,
                                                    const FactorState* states, int nb) {
+  // A: the diagonal block, eliminated in place (column k holds the unscaled W
+  // column of step k once step k - 1 is done); X: L11^{-1}, built alongside by
+  // applying every elimination step to the identity.
   __shared__ double A[kMaxNb][kMaxNb + 1];
+  __shared__ double X[kMaxNb][kMaxNb + 1];
   const int s = blockIdx.x, tid = threadIdx.x;
   const FactorState st = states[s];
   const int k0 = st.k0 + st.kb;
@@ -138,29 +142,36 @@ __global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* L
   double* cin = aux + nb;
   unsigned long long* cout = reinterpret_cast<unsigned long long*>(aux + 2 * nb);
   double* Linv = aux + 3 * nb;
-  for (int e = tid; e < kMaxNb * kMaxNb; e += 256) {
-    const int i = e & (kMaxNb - 1), j = e / kMaxNb;
-    A[i][j] = (i < nbe && j < nbe && i >= j) ? LD[(k0 + i) + (long)(k0 + j) * ldld] : 0.0;
+  const int cl = tid & (kMaxNb - 1), rg = tid >> 6;  // column of this lane, row phase 0..3
+  for (int i = rg; i < kMaxNb; i += 4) {
+    A[i][cl] = (i < nbe && cl < nbe && i >= cl) ? LD[(k0 + i) + (long)(k0 + cl) * ldld] : 0.0;
+    X[i][cl] = (i == cl) ? 1.0 : 0.0;
   }
   for (int c = tid; c < nb; c += 256) cout[c] = 0ull;
   __syncthreads();
-  for (int k = 0; k < nbe; ++k) {
+  for (int k = 0; k + 1 < nbe; ++k) {
     const double d = A[k][k];
-    const int m = nbe - k - 1;
-    for (int e = tid; e < m * m; e += 256) {
-      const int ii = k + 1 + e % m, jj = k + 1 + e / m;
-      if (ii >= jj) A[ii][jj] -= A[ii][k] * (A[jj][k] / d);
+    // trailing lower part of the block: A[i][j] -= A[i][k] A[j][k] / d, i >= j > k
+    if (cl > k && cl < nbe) {
+      const double ljk = A[cl][k] / d;
+      for (int i = cl + rg; i < nbe; i += 4) A[i][cl] -= A[i][k] * ljk;
+    }
+    // rows below k of L^{-1}: X[i][c] -= (A[i][k] / d) X[k][c], c <= k < i
+    if (cl <= k) {
+      const double xkc = X[k][cl];
+      for (int i = k + 1 + rg; i < nbe; i += 4) X[i][cl] -= (A[i][k] / d) * xkc;
     }
     __syncthreads();
   }
-  // outputs: D, unscaled W and scaled L of the block, column maxima inside the block
-  for (int e = tid; e < nbe * nbe; e += 256) {
-    const int i = e % nbe, k = e / nbe;
-    if (i >= k) {
-      const double w = A[i][k];
-      Wp[(k0 + i) + (long)k * ldw] = w;
-      if (i > k) Lp[(k0 + i) + (long)k * ldw] = w / A[k][k];
+  // outputs: D, unscaled W and scaled L of the block, column maxima inside the
+  // block, L11^{-1} column-major
+  for (int i = rg; i < nbe; i += 4) {
+    if (cl < nbe && i >= cl) {
+      const double w = A[i][cl];
+      Wp[(k0 + i) + (long)cl * ldw] = w;
+      if (i > cl) Lp[(k0 + i) + (long)cl * ldw] = w / A[cl][cl];
     }
+    if (cl < nbe) Linv[i + (long)cl * nb] = (i >= cl) ? X[i][cl] : 0.0;
   }
   if (tid < nbe) {
     const int k = tid;
@@ -171,17 +182,6 @@ __global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* L
     }
     cin[k] = mx;
     Dv[k] = A[k][k];
-  }
-  __syncthreads();
-  // Linv = L11^{-1} (unit lower), one column per thread, column-major nb x nb
-  if (tid < nbe) {
-    const int c = tid;
-    for (int i = 0; i < nbe; ++i) {
-      double x = (i == c) ? 1.0 : 0.0;
-      if (i > c)
-        for (int k = c; k < i; ++k) x -= (A[i][k] / A[k][k]) * Linv[k + (long)c * nb];
-      Linv[i + (long)c * nb] = (i >= c) ? x : 0.0;
-    }
   }
 }
 
@@ -694,10 +694,10 @@ __global__ __launch_bounds__(256) void k_factor_finalize(int n, const int* const
 void factor_launch(const FactorPlan& fp, hipStream_t st) {
   const int n = fp.n, S = fp.nshift, nb = fp.nb;
   if (S <= 0 || n <= 0) return;
-  hipLaunchKernelGGL(k_shift_form, dim3(n, S), dim3(256), 0, st, n, fp.A, fp.lda, fp.B, fp.ldb,
+  SL_LAUNCH(k_shift_form, dim3(n, S), dim3(256), 0, st, n, fp.A, fp.lda, fp.B, fp.ldb,
                      fp.d_sigmas, fp.d_LD, fp.ldld);
   SL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_factor_init, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
+  SL_LAUNCH(k_factor_init, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
                      fp.d_state, fp.d_perm, fp.d_sw);
   SL_LAUNCH_CHECK();
   sislice_handle* ph = current_handle();
@@ -717,22 +717,22 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const long k0_lb = std::min<long>(n, kmin + (long)q * min_kb);
       if (fp.fast) {
         const int tf = prof_begin(ph, kProfPanel);
-        hipLaunchKernelGGL(k_fast_diag, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
+        SL_LAUNCH(k_fast_diag, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
                            fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
         SL_LAUNCH_CHECK();
         const long rows = n - k0_lb - 1;
         if (rows > 0) {
-          hipLaunchKernelGGL(k_fast_trsm, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+          SL_LAUNCH(k_fast_trsm, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
                              (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
                              fp.d_state, nb);
           SL_LAUNCH_CHECK();
         }
         if (fp.pivot)
-          hipLaunchKernelGGL(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+          SL_LAUNCH(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
                              (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
                              fp.d_blk, fp.d_colpanel, fp.d_state, nb);
         else
-          hipLaunchKernelGGL(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+          SL_LAUNCH(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
                              (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
                              fp.d_blk, fp.d_colpanel, fp.d_state, nb);
         SL_LAUNCH_CHECK();
@@ -740,11 +740,11 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       }
       const int tp = prof_begin(ph, kProfPanel);
       if (fp.pivot)
-        hipLaunchKernelGGL(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W,
+        SL_LAUNCH(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W,
                            fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart,
                            fp.d_state, nb, nbpiv);
       else
-        hipLaunchKernelGGL(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
+        SL_LAUNCH(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
                            fp.d_W, fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel,
                            fp.d_pstart, fp.d_state, nb, nbpiv);
       SL_LAUNCH_CHECK();
@@ -754,7 +754,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const long T = ceil_div(n - k1_lb, 64);
       const size_t lds = (size_t)2 * ((nb + 3) & ~3) * 64 * sizeof(double);
       const int tu = prof_begin(ph, kProfUpdate);
-      hipLaunchKernelGGL(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), lds,
+      SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), lds,
                          st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
       SL_LAUNCH_CHECK();
       prof_end(ph, tu);
@@ -774,14 +774,14 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
+    SL_LAUNCH(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
                        fp.d_pstart, fp.d_state, fp.d_snap);
     SL_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_left_gather, dim3(n, S), dim3(256), (size_t)n * sizeof(double), st, n,
+    SL_LAUNCH(k_left_gather, dim3(n, S), dim3(256), (size_t)n * sizeof(double), st, n,
                        fp.d_LD, fp.ldld, fp.d_colpanel, fp.d_pstart, fp.d_state, fp.d_snap);
     SL_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL(k_factor_finalize, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
+  SL_LAUNCH(k_factor_finalize, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
                      fp.d_perm, fp.d_blk, fp.d_ipiv, fp.d_state, fp.d_inertia);
   SL_LAUNCH_CHECK();
 }

@@ -21,6 +21,9 @@ struct sislice_handle {
   unsigned epoch = 0;
   void* ring_host = nullptr;  // pinned ring for per-step pointer tables
   size_t ring_cap = 0;
+  // staged-but-not-uploaded tables: flushed (one copy) before the next launch
+  void (*flush_fn)(void*) = nullptr;
+  void* flush_ctx = nullptr;
   // kernel-class timing with HIP events (enabled per call)
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -93,5 +96,23 @@ void prof_reset(sislice_handle* h);
 // The handle whose stream receives the current launches (set by entry points).
 sislice_handle* current_handle();
 void set_current_handle(sislice_handle* h);
+
+// Uploads the kernel-argument tables staged since the last launch (one
+// host-to-device copy on the handle's stream); called before every launch.
+inline void flush_uploads() {
+  sislice_handle* h = current_handle();
+  if (h && h->flush_fn) h->flush_fn(h->flush_ctx);
+}
+
+}  // namespace sislice
+
+// Every kernel launch of the library goes through this macro.
+#define SL_LAUNCH(...)             \
+  do {                             \
+    ::sislice::flush_uploads();    \
+    hipLaunchKernelGGL(__VA_ARGS__); \
+  } while (0)
+
+namespace sislice {
 
 }  // namespace sislice

@@ -5,6 +5,7 @@
 // final gather of validated eigenpairs.  All are batched over probes through
 // pointer tables; a probe with a zero size is skipped.
 #include "common.hpp"
+#include "handle.hpp"
 #include "lanczos.hpp"
 
 namespace sislice {
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(256) void k_cholqr_apply(CholQrArgs a) {
 
 void cholqr_launch(const CholQrArgs& a, int batch, hipStream_t st) {
   const unsigned nchunk = (unsigned)std::min<long>(ceil_div(a.n, 256), 64);
-  hipLaunchKernelGGL(k_cholqr_apply, dim3(nchunk, batch), dim3(256), 0, st, a);
+  SL_LAUNCH(k_cholqr_apply, dim3(nchunk, batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
 
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void k_t_write(TWriteArgs a) {
 }
 
 void twrite_launch(const TWriteArgs& a, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_t_write, dim3(batch), dim3(256), 0, st, a);
+  SL_LAUNCH(k_t_write, dim3(batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
 
@@ -144,7 +145,7 @@ __global__ __launch_bounds__(64) void k_t_coupling(CouplingArgs a) {
 }
 
 void coupling_launch(const CouplingArgs& a, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_t_coupling, dim3(batch), dim3(64), 0, st, a);
+  SL_LAUNCH(k_t_coupling, dim3(batch), dim3(64), 0, st, a);
   SL_LAUNCH_CHECK();
 }
 
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(128) void k_ritz_est(RitzEstArgs a) {
 }
 
 void ritz_est_launch(const RitzEstArgs& a, int batch, hipStream_t st) {
-  hipLaunchKernelGGL(k_ritz_est, dim3(batch), dim3(128), 0, st, a);
+  SL_LAUNCH(k_ritz_est, dim3(batch), dim3(128), 0, st, a);
   SL_LAUNCH_CHECK();
 }
 
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void k_select_cols(SelectArgs a) {
 }
 
 void select_launch(const SelectArgs& a, int batch, long maxelems, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_cols, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(maxelems, 256), 1024)), batch),
+  SL_LAUNCH(k_select_cols, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(maxelems, 256), 1024)), batch),
                      dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
@@ -210,7 +211,7 @@ __global__ __launch_bounds__(256) void k_copy_cols(CopyArgs a) {
 
 void copy_launch(const CopyArgs& a, int batch, int maxcol, hipStream_t st) {
   const long tot = (long)a.n * maxcol;
-  hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 4096)), batch),
+  SL_LAUNCH(k_copy_cols, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 4096)), batch),
                      dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(256) void k_t_reset(TResetArgs a) {
 
 void treset_launch(const TResetArgs& a, int batch, hipStream_t st) {
   const long tot = (long)a.dim * a.dim;
-  hipLaunchKernelGGL(k_t_reset, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 256)), batch),
+  SL_LAUNCH(k_t_reset, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 256)), batch),
                      dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }
@@ -256,14 +257,14 @@ __global__ __launch_bounds__(256) void k_inv_sqrt_diag(int n, const double* LD, 
 
 void row_scale_launch(int n, int ncol, const double* scale, double* X, long ldx, hipStream_t st) {
   const long tot = (long)n * ncol;
-  hipLaunchKernelGGL(k_row_scale, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 4096))),
+  SL_LAUNCH(k_row_scale, dim3((unsigned)std::max<long>(1, std::min<long>(ceil_div(tot, 256), 4096))),
                      dim3(256), 0, st, n, ncol, scale, X, ldx);
   SL_LAUNCH_CHECK();
 }
 
 void inv_sqrt_diag_launch(int n, const double* LD, long ldld, double* scale, int* bad,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_inv_sqrt_diag, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, LD,
+  SL_LAUNCH(k_inv_sqrt_diag, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, st, n, LD,
                      ldld, scale, bad);
   SL_LAUNCH_CHECK();
 }
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(256) void k_gather_out(GatherArgs a) {
 
 void gather_launch(const GatherArgs& a, int count, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_gather_out, dim3((unsigned)std::min<long>(ceil_div(a.n, 256), 64), count),
+  SL_LAUNCH(k_gather_out, dim3((unsigned)std::min<long>(ceil_div(a.n, 256), 64), count),
                      dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
 }

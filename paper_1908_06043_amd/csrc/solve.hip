@@ -334,10 +334,10 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
 void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_perm,
                        int* const* d_blk, const double* const* d_LD, long ldld,
                        double* const* d_Linv, hipStream_t st) {
-  hipLaunchKernelGGL(k_solve_prep, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n, d_ipiv,
+  SL_LAUNCH(k_solve_prep, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n, d_ipiv,
                      d_perm, d_blk);
   SL_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_diag_inv_blk, dim3((unsigned)ceil_div(n, SB), S), dim3(64), 0, st, n, d_LD,
+  SL_LAUNCH(k_diag_inv_blk, dim3((unsigned)ceil_div(n, SB), S), dim3(64), 0, st, n, d_LD,
                      ldld, (const int* const*)d_blk, d_Linv);
   SL_LAUNCH_CHECK();
 }
@@ -347,11 +347,11 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   sislice_handle* ph = current_handle();
   const int tk = prof_begin(ph, kProfSolve);
   if (mode == 0 || mode == 1) {
-    hipLaunchKernelGGL(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   if (mode == 0 || mode == 2) {
-    hipLaunchKernelGGL(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   prof_end(ph, tk);
