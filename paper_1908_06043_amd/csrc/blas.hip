@@ -155,6 +155,204 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
   prof_end(ph, tk);
 }
 
+// ------------------------------------------------------------ skinny products
+//
+// C = alpha * M X + beta * C with M square n x n (column-major, ldm) and X n x k,
+// k <= kSkinnyMaxCol.  The product is bound by reading M once from HBM (8 n^2
+// bytes, halved for a triangular M), so it is written for streaming: a
+// workgroup owns 64 rows and a K chunk of kSkinnyKc columns of M, each of its
+// four wavefronts a quarter of the chunk; lane i of a wavefront holds row i0 + i
+// and accumulates NC columns with FMA.  M is read in unconditional 8-deep
+// batches of contiguous 512-byte column segments (rows past n are clamped and
+// never stored); the X chunk sits in LDS (k-major, so the NC entries a step
+// needs are one broadcast read).  The quarters are summed in LDS in order, the
+// chunks by k_skinny_reduce in chunk order, so results are deterministic.  A
+// triangular M (tri = 1 lower, 2 upper, zeros stored in the other half) skips the
+// chunks that do not meet a row tile.
+
+__device__ __forceinline__ bool skinny_chunk_live(int tri, int i0, int kc) {
+  if (tri == 1) return kc <= i0 + 63;                    // lower: columns <= row
+  if (tri == 2) return kc + kSkinnyKc > i0;               // upper: columns >= row
+  return true;
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_skinny_mm(int n, const double* __restrict__ M, long ldm,
+                                                   int tri, const double* __restrict__ X, long ldx,
+                                                   double* __restrict__ P, int pcols, int c_off) {
+  constexpr int KQ = kSkinnyKc / 4;  // columns of M per wavefront
+  constexpr int NCP = NC + (NC & 1);
+  __shared__ double sh[(kSkinnyKc * NCP > 3 * NC * 64) ? kSkinnyKc * NCP : 3 * NC * 64];
+  const int t = blockIdx.x, q = blockIdx.y;
+  const int i0 = t * 64, kc = q * kSkinnyKc;
+  if (!skinny_chunk_live(tri, i0, kc)) return;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  // X chunk, k-major: sh[k * NCP + c] = X(kc + k, c)
+  for (int e = tid; e < kSkinnyKc * NC; e += 256) {
+    const int k = e % kSkinnyKc, c = e / kSkinnyKc;
+    sh[k * NCP + c] = (kc + k < n) ? X[kc + k + (long)c * ldx] : 0.0;
+  }
+  __syncthreads();
+  const int row = i0 + l;
+  const double* Mr = M + min(row, n - 1);
+  double acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+  const int kb = kc + w * KQ;
+  const int ke = min(n, kb + KQ);
+  int k = kb;
+  for (; k + 8 <= ke; k += 8) {
+    double m8[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) m8[u] = Mr[(long)(k + u) * ldm];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double* xs = sh + (k - kc + u) * NCP;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] += m8[u] * xs[c];
+    }
+  }
+  for (; k < ke; ++k) {
+    const double mv = Mr[(long)k * ldm];
+    const double* xs = sh + (k - kc) * NCP;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += mv * xs[c];
+  }
+  __syncthreads();  // the X chunk is dead: reuse LDS for the quarter sums
+  if (w > 0) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) sh[((w - 1) * NC + c) * 64 + l] = acc[c];
+  }
+  __syncthreads();
+  if (w == 0 && row < n) {
+    double* Pq = P + (long)q * n * pcols + (long)c_off * n;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      Pq[row + (long)c * n] =
+          ((acc[c] + sh[(0 * NC + c) * 64 + l]) + sh[(1 * NC + c) * 64 + l]) + sh[(2 * NC + c) * 64 + l];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_skinny_reduce(int n, int ncol, int nchunk, int tri,
+                                                       const double* __restrict__ P, double alpha,
+                                                       double beta, double* __restrict__ C,
+                                                       long ldc) {
+  const long tot = (long)n * ncol;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    const int i0 = (i / 64) * 64;
+    double s = 0.0;
+    for (int q = 0; q < nchunk; ++q)
+      if (skinny_chunk_live(tri, i0, q * kSkinnyKc)) s += P[(long)q * tot + i + (long)c * n];
+    double* cp = C + i + (long)c * ldc;
+    const double v = alpha * s;
+    *cp = (beta == 0.0) ? v : v + beta * *cp;
+  }
+}
+
+template <int NC>
+static void skinny_part(int n, const double* M, long ldm, int tri, const double* X, long ldx,
+                        double* partial, int pcols, int c_off, hipStream_t st) {
+  const int nchunk = (int)ceil_div(n, kSkinnyKc);
+  SL_LAUNCH((k_skinny_mm<NC>), dim3((unsigned)ceil_div(n, 64), nchunk), dim3(256), 0, st, n, M,
+            ldm, tri, X + (long)c_off * ldx, ldx, partial, pcols, c_off);
+  SL_LAUNCH_CHECK();
+}
+
+void skinny_launch(int n, int ncol, const double* M, long ldm, int tri, const double* X, long ldx,
+                   double alpha, double beta, double* C, long ldc, double* partial,
+                   hipStream_t st) {
+  if (n <= 0 || ncol <= 0) return;
+  SL_CHECK_ARG(ncol <= kSkinnyMaxCol, "skinny product: too many columns");
+  sislice_handle* ph = current_handle();
+  const int tk = prof_begin(ph, kProfGemm);
+  // column pieces of instantiated widths (each piece streams M once)
+  int c0 = 0;
+  while (c0 < ncol) {
+    const int r = ncol - c0;
+    int wdt;
+    if (r >= 32) { skinny_part<32>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 32; }
+    else if (r >= 24) { skinny_part<24>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 24; }
+    else if (r >= 20) { skinny_part<20>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 20; }
+    else if (r >= 16) { skinny_part<16>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 16; }
+    else if (r >= 8) { skinny_part<8>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 8; }
+    else if (r >= 4) { skinny_part<4>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 4; }
+    else if (r >= 2) { skinny_part<2>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 2; }
+    else { skinny_part<1>(n, M, ldm, tri, X, ldx, partial, ncol, c0, st); wdt = 1; }
+    c0 += wdt;
+  }
+  const int nchunk = (int)ceil_div(n, kSkinnyKc);
+  const long tot = (long)n * ncol;
+  SL_LAUNCH(k_skinny_reduce, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096)), dim3(256),
+            0, st, n, ncol, nchunk, tri, partial, alpha, beta, C, ldc);
+  SL_LAUNCH_CHECK();
+  prof_end(ph, tk);
+}
+
+// out = f1 * X + f2 * Y + f3 * Z elementwise over n x ncol blocks (ld n); Z may
+// be null (f3 ignored).
+__global__ __launch_bounds__(256) void k_lincomb3(long tot, double f1, const double* __restrict__ X,
+                                                  double f2, const double* __restrict__ Y,
+                                                  double f3, const double* __restrict__ Z,
+                                                  double* __restrict__ out) {
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+    double v = f1 * X[e] + f2 * Y[e];
+    if (Z) v += f3 * Z[e];
+    out[e] = v;
+  }
+}
+
+void lincomb3_launch(long tot, double f1, const double* X, double f2, const double* Y, double f3,
+                     const double* Z, double* out, hipStream_t st) {
+  if (tot <= 0) return;
+  SL_LAUNCH(k_lincomb3, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096)), dim3(256), 0, st,
+            tot, f1, X, f2, Y, f3, Z, out);
+  SL_LAUNCH_CHECK();
+}
+
+// y = x / sqrt(s2[0]) (a zero norm gives y = 0), and rec[0] = sqrt(s2[0]) when rec
+// is non-null: normalisation by a norm that stays on the device.
+__global__ __launch_bounds__(256) void k_scale_by_norm(int n, const double* __restrict__ s2,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y,
+                                                       double* __restrict__ rec) {
+  const double nr = sqrt(fmax(s2[0], 0.0));
+  const double f = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) y[i] = x[i] * f;
+  if (rec && blockIdx.x == 0 && threadIdx.x == 0) rec[0] = nr;
+}
+
+void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, double* rec,
+                          hipStream_t st) {
+  SL_LAUNCH(k_scale_by_norm, dim3((unsigned)std::min<long>(ceil_div(n, 256), 1024)), dim3(256), 0,
+            st, n, s2, x, y, rec);
+  SL_LAUNCH_CHECK();
+}
+
+// Out-of-place transpose T = S^T of an n x n matrix, 32 x 32 tiles through LDS.
+__global__ __launch_bounds__(256) void k_transpose(int n, const double* __restrict__ S, long lds,
+                                                   double* __restrict__ T, long ldt) {
+  __shared__ double t[32][33];
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = bi * 32 + tx, j = bj * 32 + yy;
+    t[yy][tx] = (i < n && j < n) ? S[i + (long)j * lds] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int i = bj * 32 + tx, j = bi * 32 + yy;
+    if (i < n && j < n) T[i + (long)j * ldt] = t[tx][yy];
+  }
+}
+
+void transpose_launch(int n, const double* S, long lds, double* T, long ldt, hipStream_t st) {
+  const unsigned G = (unsigned)ceil_div(n, 32);
+  SL_LAUNCH(k_transpose, dim3(G, G), dim3(256), 0, st, n, S, lds, T, ldt);
+  SL_LAUNCH_CHECK();
+}
+
 // F (n x n, ldf) = symmetric completion of the lower triangle of S (lds), tiled
 // through LDS so both the read and the mirrored write are coalesced.
 __global__ __launch_bounds__(256) void k_sym_full(int n, const double* __restrict__ S, long lds,

@@ -30,6 +30,22 @@ struct GemmArgs {
 void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hipStream_t st);
 void sym_full_launch(int n, const double* S, long lds, double* F, long ldf, hipStream_t st);
 
+// C = alpha M X + beta C, M n x n (tri: 0 full, 1 lower, 2 upper with zeros stored
+// in the other half), X n x ncol, ncol <= kSkinnyMaxCol; `partial` holds
+// ceil(n / kSkinnyKc) * n * ncol doubles.
+constexpr int kSkinnyMaxCol = 32;
+constexpr int kSkinnyKc = 256;
+inline size_t skinny_partial_size(int n, int ncol) {
+  return (size_t)ceil_div(n, kSkinnyKc) * n * ncol;
+}
+void skinny_launch(int n, int ncol, const double* M, long ldm, int tri, const double* X, long ldx,
+                   double alpha, double beta, double* C, long ldc, double* partial, hipStream_t st);
+void lincomb3_launch(long tot, double f1, const double* X, double f2, const double* Y, double f3,
+                     const double* Z, double* out, hipStream_t st);
+void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, double* rec,
+                          hipStream_t st);
+void transpose_launch(int n, const double* S, long lds, double* T, long ldt, hipStream_t st);
+
 constexpr int kDotChunk = 2048;
 
 // mode 0: out[b][c] = X[:,c] . Y[:,c];  mode 1: out[b][c] = ||X[:,c] - w[b][c] Y[:,c]||_2

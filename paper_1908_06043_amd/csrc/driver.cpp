@@ -258,24 +258,29 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   Ring ring(h);
   Ctx c{h, st, &ring};
   const long nblk = solve_nblk(n);
+  const int m_b = std::min(bs, n);  // Lanczos steps for the bounds
   // workspace
   Sizer z;
-  z.take<double>((size_t)n * n);      // Af
+  z.take<double>((size_t)n * n);      // Af: A with both triangles
   z.take<double>((size_t)n * n);      // LD of B
+  z.take<double>((size_t)n * n);      // M = D^{-1/2} L^{-1} (lower)
+  z.take<double>((size_t)n * n);      // M^T (upper); scratch of the inversion before that
   z.take<int32_t>(n);                 // ipiv
   z.take<int>(n);                     // perm
   z.take<int>(n);                     // blk
   z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
   z.take<double>(n);                  // D^{-1/2}
-  for (int q = 0; q < 7; ++q) z.take<double>((size_t)n * nv);  // t_prev, t_cur, t_next, tmp1..3, V0
-  z.take<double>((size_t)n * (bs + 1));  // Lanczos basis
-  z.take<double>((size_t)n * 4);         // w, misc
-  z.take<double>(4096);                  // small scalars
-  z.take<double>((size_t)(bs + 1) * (bs + 1) * 2);
+  for (int q = 0; q < 6; ++q) z.take<double>((size_t)n * nv);  // t_prev, t_cur, t_next, X1..X3
+  z.take<double>((size_t)n * (m_b + 1));  // Lanczos basis
+  z.take<double>((size_t)n * 4);          // w
+  z.take<double>(8192);                   // small scalars
+  z.take<double>(skinny_partial_size(n, std::max(nv, 1)));
   z.take<int>(64);
   Carver cv(ws_get(h, kBufKpm, z.off));
   double* Af = cv.take<double>((size_t)n * n);
   double* LDB = cv.take<double>((size_t)n * n);
+  double* Mi = cv.take<double>((size_t)n * n);
+  double* MT = cv.take<double>((size_t)n * n);
   int32_t* ipB = cv.take<int32_t>(n);
   int* permB = cv.take<int>(n);
   int* blkB = cv.take<int>(n);
@@ -287,12 +292,12 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   double* X1 = cv.take<double>((size_t)n * nv);
   double* X2 = cv.take<double>((size_t)n * nv);
   double* X3 = cv.take<double>((size_t)n * nv);
-  double* V0 = cv.take<double>((size_t)n * nv);
-  double* Vb = cv.take<double>((size_t)n * (bs + 1));
+  double* Vb = cv.take<double>((size_t)n * (m_b + 1));
   double* wv = cv.take<double>((size_t)n * 4);
-  double* small = cv.take<double>(4096);
-  double* Tm = cv.take<double>((size_t)(bs + 1) * (bs + 1) * 2);
+  double* small = cv.take<double>(8192);
+  double* spart = cv.take<double>(skinny_partial_size(n, std::max(nv, 1)));
   int* iflag = cv.take<int>(64);
+  SL_CHECK_ARG(nv >= 1 && nv <= kSkinnyMaxCol, "kpm_vectors must be in [1, 32]");
   SL_HIP(hipMemsetAsync(iflag, 0, 64 * sizeof(int), st));
   sym_full_launch(n, A, lda, Af, n, st);
   // B = L D L^T without interchanges (B is SPD), so L_B = L D^{1/2}
@@ -309,9 +314,6 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     ring.synced();
     if (inert[0] != 0 || inert[1] != 0) throw Error(SISLICE_ERR_ARG, "B is not positive definite");
   }
-  const double* ldtab[1] = {LDB};
-  const int* iptab[1] = {ipB};
-  (void)iptab;
   {
     auto tLD = ring.cptrs(std::vector<double*>{LDB});
     auto tip = ring.cptrs(std::vector<int32_t*>{ipB});
@@ -320,44 +322,43 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     auto tLinv = ring.ptrs(std::vector<double*>{LinvB});
     solve_prep_launch(n, 1, reinterpret_cast<const int* const*>(tip), tperm, tblk, tLD, n, tLinv, st);
   }
-  (void)ldtab;
   inv_sqrt_diag_launch(n, LDB, n, dsc, iflag, st);
-  unsigned* sync = sync_words(h, 64 + 2 * nblk);
-  // H Y for k columns: D^{-1/2} L^{-1} A L^{-T} D^{-1/2} Y  (result in out)
+  // Explicit L^{-1} by doubling: starting from the inverted 64x64 diagonal blocks,
+  // each level joins neighbouring groups of h rows,
+  //   inv([X11 0; L21 X22]) has lower-left block -X22 (L21 X11),
+  // with the groups of one level as one batched MFMA GEMM (MT is the scratch).
+  SL_HIP(hipMemsetAsync(Mi, 0, sizeof(double) * (size_t)n * n, st));
+  diag_inv_scatter_launch(n, LinvB, Mi, n, st);
+  for (int hh = kSolveBlock; hh < n; hh *= 2) {
+    std::vector<int> gm, gn, gk2;
+    std::vector<const double*> aL, aX11, aX22, aT;
+    std::vector<double*> oT, oX21;
+    for (int r0 = 0; r0 + hh < n; r0 += 2 * hh) {
+      const int r1 = std::min(r0 + 2 * hh, n), m2 = r1 - r0 - hh;
+      gm.push_back(m2);
+      gn.push_back(hh);
+      gk2.push_back(m2);
+      aL.push_back(LDB + (r0 + hh) + (size_t)r0 * n);
+      aX11.push_back(Mi + r0 + (size_t)r0 * n);
+      aX22.push_back(Mi + (r0 + hh) + (size_t)(r0 + hh) * n);
+      oT.push_back(MT + (r0 + hh) + (size_t)r0 * n);
+      aT.push_back(MT + (r0 + hh) + (size_t)r0 * n);
+      oX21.push_back(Mi + (r0 + hh) + (size_t)r0 * n);
+    }
+    std::vector<int> gk1(gm.size(), hh);
+    gemm(c, false, false, gm, gn, gk1, aL, n, aX11, n, oT, n, 1.0, 0.0);
+    gemm(c, false, false, gm, gn, gk2, aX22, n, aT, n, oX21, n, -1.0, 0.0);
+  }
+  row_scale_launch(n, n, dsc, Mi, n, st);  // M = D^{-1/2} L^{-1}
+  transpose_launch(n, Mi, n, MT, n, st);
+  // H Y = M A M^T Y for k <= 32 columns: three HBM-bound skinny products
   auto apply_H = [&](const double* Yin, double* out, int k) {
-    SL_HIP(hipMemcpyAsync(X1, Yin, sizeof(double) * n * k, hipMemcpyDeviceToDevice, st));
-    row_scale_launch(n, k, dsc, X1, n, st);
-    SolveArgs a;
-    a.n = n;
-    a.nshift = 1;
-    a.nrhs = k;
-    a.LD = ring.cptrs(std::vector<double*>{LDB});
-    a.ldld = n;
-    a.perm = ring.cptrs(std::vector<int*>{permB});
-    a.blk = ring.cptrs(std::vector<int*>{blkB});
-    a.Linv = ring.cptrs(std::vector<double*>{LinvB});
-    a.flags = sync + 64;
-    a.flag_stride = 2 * nblk;
-    a.ctr = sync;
-    a.applyD = 0;
-    a.ldy = a.ldx = a.ldz = n;
-    // backward sweep reads Z = X1, writes X = X2 (V scratch = X3)
-    a.epoch = next_epoch(h);
-    a.Z = ring.ptrs(std::vector<double*>{X1});
-    a.V = ring.ptrs(std::vector<double*>{X3});
-    a.X = ring.ptrs(std::vector<double*>{X2});
-    a.Y = a.Z;
-    solve_launch(a, st, 2);
-    gemm(c, false, false, {n}, {k}, {n}, {Af}, n, {X2}, n, {X3}, n, 1.0, 0.0);
-    // forward sweep reads Y = X3, writes Z = out
-    a.epoch = next_epoch(h);
-    a.Y = ring.cptrs(std::vector<double*>{X3});
-    a.Z = ring.ptrs(std::vector<double*>{out});
-    a.X = a.Z;
-    solve_launch(a, st, 1);
-    row_scale_launch(n, k, dsc, out, n, st);
+    skinny_launch(n, k, MT, n, 2, Yin, n, 1.0, 0.0, X1, n, spart, st);
+    skinny_launch(n, k, Af, n, 0, X1, n, 1.0, 0.0, X3, n, spart, st);
+    skinny_launch(n, k, Mi, n, 1, X3, n, 1.0, 0.0, out, n, spart, st);
   };
-  // ---- spectral bounds: bs-step Lanczos on H with full reorthogonalisation
+  // ---- spectral bounds: m_b-step Lanczos on H with full reorthogonalisation; the
+  // normalisations stay on the device, alpha and beta are read once at the end
   std::vector<unsigned long long> sdb{rng_derive(o.seed, kTagBounds)};
   gauss_launch(n, 1, 1, ring.vec(sdb), ring.ptrs(std::vector<double*>{Vb}), n, st);
   ColDotArgs cd;
@@ -374,51 +375,39 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     d.out = ring.ptrs(std::vector<double*>{out});
     coldot_launch(d, 1, 1, st);
   };
-  double nrm2;
-  dot1(Vb, Vb, small);
-  SL_HIP(hipMemcpyAsync(&nrm2, small, sizeof(double), hipMemcpyDeviceToHost, st));
-  SL_HIP(hipStreamSynchronize(st));
-  ring.synced();
-  {
-    std::vector<double> sc(n, 1.0 / std::sqrt(nrm2));
-    double* dsc2 = small + 16;
-    (void)dsc2;
-    // scale the start vector by a uniform factor through a one-column GEMM with a 1x1 matrix
-    double s1 = 1.0 / std::sqrt(nrm2);
-    SL_HIP(hipMemcpyAsync(small + 8, &s1, sizeof(double), hipMemcpyHostToDevice, st));
-    gemm(c, false, false, {n}, {1}, {1}, {Vb}, n, {small + 8}, 1, {wv}, n, 1.0, 0.0);
-    SL_HIP(hipMemcpyAsync(Vb, wv, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-  }
-  std::vector<double> alpha(bs, 0.0), beta(bs, 0.0);
-  int m = bs;
-  for (int j = 0; j < bs; ++j) {
+  double* d_alpha = small + 128;  // [m_b]
+  double* d_s2 = small + 192;     // [m_b + 1] squared norms
+  double* d_beta = small + 256;   // [m_b]
+  SL_CHECK_ARG(m_b <= 60, "bounds_steps too large");
+  dot1(Vb, Vb, d_s2 + m_b);
+  scale_by_norm_launch(n, d_s2 + m_b, Vb, Vb, nullptr, st);
+  for (int j = 0; j < m_b; ++j) {
     double* vj = Vb + (size_t)j * n;
     apply_H(vj, wv, 1);
-    dot1(vj, wv, small);
+    dot1(vj, wv, d_alpha + j);
     for (int pass = 0; pass < 2; ++pass) {
       // coef = V^T w ; w -= V coef
-      gemm(c, true, false, {j + 1}, {1}, {n}, {Vb}, n, {wv}, n, {small + 64}, j + 1, 1.0, 0.0);
-      gemm(c, false, false, {n}, {1}, {j + 1}, {Vb}, n, {small + 64}, j + 1, {wv}, n, -1.0, 1.0);
+      gemm(c, true, false, {j + 1}, {1}, {n}, {Vb}, n, {wv}, n, {small + 512}, j + 1, 1.0, 0.0);
+      gemm(c, false, false, {n}, {1}, {j + 1}, {Vb}, n, {small + 512}, j + 1, {wv}, n, -1.0, 1.0);
     }
-    dot1(wv, wv, small + 1);
-    double ab[2];
-    SL_HIP(hipMemcpyAsync(ab, small, sizeof(ab), hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
-    ring.synced();
-    alpha[j] = ab[0];
-    beta[j] = std::sqrt(std::max(ab[1], 0.0));
+    dot1(wv, wv, d_s2 + j);
+    scale_by_norm_launch(n, d_s2 + j, wv, Vb + (size_t)(j + 1) * n, d_beta + j, st);
+  }
+  std::vector<double> alpha(m_b, 0.0), beta(m_b, 0.0);
+  SL_HIP(hipMemcpyAsync(alpha.data(), d_alpha, sizeof(double) * m_b, hipMemcpyDeviceToHost, st));
+  SL_HIP(hipMemcpyAsync(beta.data(), d_beta, sizeof(double) * m_b, hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  int m = m_b;
+  for (int j = 0; j < m_b; ++j)
     if (beta[j] == 0.0) {
       m = j + 1;
       break;
     }
-    if (j + 1 < bs + 1) {
-      const double inv = 1.0 / beta[j];
-      SL_HIP(hipMemcpyAsync(small + 8, &inv, sizeof(double), hipMemcpyHostToDevice, st));
-      gemm(c, false, false, {n}, {1}, {1}, {wv}, n, {small + 8}, 1, {Vb + (size_t)(j + 1) * n}, n,
-           1.0, 0.0);
-    }
-  }
   // Ritz values of the tridiagonal T_m on the device eigensolver
+  double* Tm = small + 1024;  // m*m, then m Ritz values
+  double* Sv = small + 2048;  // m*m
+  SL_CHECK_ARG((size_t)m * m + m <= 1024, "bounds_steps too large");
   std::vector<double> Th((size_t)m * m, 0.0);
   for (int j = 0; j < m; ++j) {
     Th[j + (size_t)j * m] = alpha[j];
@@ -426,8 +415,6 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   }
   SL_HIP(hipMemcpyAsync(Tm, Th.data(), sizeof(double) * m * m, hipMemcpyHostToDevice, st));
   double* thv = Tm + (size_t)m * m;
-  double* Sv = small + 256;
-  SL_CHECK_ARG((size_t)m * m + 256 <= 4096, "bounds_steps too large");
   {
     EigArgs e;
     e.m = ring.vec(std::vector<int>{m});
@@ -450,10 +437,10 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   // ---- Chebyshev moments: doubling identities mu_{2k} = 2<t_k,t_k> - mu_0,
   // mu_{2k+1} = 2<t_{k+1},t_k> - mu_1 with t_k = T_k(H~) v
   const double cc = 0.5 * (a + bb), dd = 0.5 * (bb - a);
-  rademacher_launch(n, nv, rng_derive(o.seed, kTagKpm), V0, n, st);
+  rademacher_launch(n, nv, rng_derive(o.seed, kTagKpm), T0, n, st);
   const int K = M / 2 + 1;  // t_0 .. t_K
-  double* dots = small + 1024;  // [2K+2][nv]
-  SL_CHECK_ARG((size_t)(2 * K + 2) * nv + 1024 <= 4096, "too many moments for the scratch area");
+  double* dots = small + 4096;  // [2K+2][nv]
+  SL_CHECK_ARG((size_t)(2 * K + 2) * nv + 4096 <= 8192, "too many moments for the scratch area");
   ColDotArgs cdv = cd;
   cdv.ncol0 = nv;
   auto dotv = [&](const double* x, const double* y, double* out) {
@@ -465,28 +452,16 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     d.out = ring.ptrs(std::vector<double*>{out});
     coldot_launch(d, 1, nv, st);
   };
-  // H~ X = (H X - c X) / d via GEMM-free combination on the device:
-  // out = (1/d) H X - (c/d) X, prev-combination for the recurrence
+  // t_next = 2 H~ t_cur - t_prev = (2/d) H t_cur - (2c/d) t_cur - t_prev  (t_1 = H~ t_0)
   auto scaled_step = [&](const double* tcur, const double* tprev, double* tnext, bool first) {
-    apply_H(tcur, X2, nv);  // X2 = H tcur (X2 is free again after apply_H)
-    // tnext = f1 * X2 + f2 * tcur + f3 * tprev   (columnwise, via two 1x1-GEMM updates)
+    apply_H(tcur, X2, nv);
     const double f1 = first ? 1.0 / dd : 2.0 / dd;
     const double f2 = first ? -cc / dd : -2.0 * cc / dd;
-    double coefs[3] = {f1, f2, -1.0};
-    SL_HIP(hipMemcpyAsync(small + 32, coefs, sizeof(coefs), hipMemcpyHostToDevice, st));
-    // treat the n x nv blocks as (n*nv) x 1 vectors
-    gemm(c, false, false, {n * nv}, {1}, {1}, {X2}, (long)n * nv, {small + 32}, 1, {tnext},
-         (long)n * nv, 1.0, 0.0);
-    gemm(c, false, false, {n * nv}, {1}, {1}, {tcur}, (long)n * nv, {small + 33}, 1, {tnext},
-         (long)n * nv, 1.0, 1.0);
-    if (!first)
-      gemm(c, false, false, {n * nv}, {1}, {1}, {tprev}, (long)n * nv, {small + 34}, 1, {tnext},
-           (long)n * nv, 1.0, 1.0);
+    lincomb3_launch((long)n * nv, f1, X2, f2, tcur, -1.0, first ? nullptr : tprev, tnext, st);
   };
   double* tp = T0;
   double* tc = T1;
   double* tn = T2;
-  SL_HIP(hipMemcpyAsync(tp, V0, sizeof(double) * n * nv, hipMemcpyDeviceToDevice, st));
   dotv(tp, tp, dots + 0 * nv);            // <t0,t0>
   scaled_step(tp, nullptr, tc, true);     // t1
   dotv(tc, tp, dots + 1 * nv);            // <t1,t0>

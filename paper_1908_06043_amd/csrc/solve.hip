@@ -331,6 +331,23 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   post_flag(flags + b, a.epoch);
 }
 
+// Li (ldli, zero elsewhere) receives the 64x64 inverses of L's diagonal blocks on
+// its block diagonal: the starting point of the explicit inverse of L.
+__global__ __launch_bounds__(256) void k_diag_inv_scatter(int n, const double* __restrict__ Linv,
+                                                          double* __restrict__ Li, long ldli) {
+  const int b = blockIdx.x;
+  for (int e = threadIdx.x; e < SB * SB; e += 256) {
+    const int r = b * SB + (e & 63), c = b * SB + (e >> 6);
+    if (r < n && c < n) Li[r + (long)c * ldli] = Linv[(long)b * SB * SB + e];
+  }
+}
+
+void diag_inv_scatter_launch(int n, const double* Linv, double* Li, long ldli, hipStream_t st) {
+  SL_LAUNCH(k_diag_inv_scatter, dim3((unsigned)ceil_div(n, SB)), dim3(256), 0, st, n, Linv, Li,
+            ldli);
+  SL_LAUNCH_CHECK();
+}
+
 void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_perm,
                        int* const* d_blk, const double* const* d_LD, long ldld,
                        double* const* d_Linv, hipStream_t st) {

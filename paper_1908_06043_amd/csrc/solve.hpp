@@ -37,6 +37,9 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
                        int* const* d_blk, const double* const* d_LD, long ldld,
                        double* const* d_Linv, hipStream_t st);
 void solve_launch(SolveArgs a, hipStream_t st, int mode = 0);
+// Scatter the 64x64 diagonal-block inverses (layout of solve_prep_launch's Linv)
+// onto the block diagonal of an n x n matrix.
+void diag_inv_scatter_launch(int n, const double* Linv, double* Li, long ldli, hipStream_t st);
 
 inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
 
