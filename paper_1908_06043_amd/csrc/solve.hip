@@ -87,20 +87,45 @@ __device__ __forceinline__ unsigned ticket(unsigned* ctr, unsigned nblk) {
   return t;
 }
 
+// Hand-off between workgroups.  The 64-row result blocks that other workgroups
+// of the same sweep read are written and read as relaxed agent-scope atomics,
+// which go to the device coherence point instead of a (per-XCD, non-coherent) L2
+// line; a block is published by draining this wave's stores (vmcnt(0)) in every
+// wave, a barrier, and one relaxed agent-scope flag store.  The waiter polls the
+// flag with relaxed loads: an acquire load (or fence) per poll invalidates the
+// caches each time, and with hundreds of pollers that serialises the whole chip.
+constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15)
+
+__device__ __forceinline__ double ld_shared_blk(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_shared_blk(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ void wait_flag(const unsigned* flag, unsigned epoch) {
   if (threadIdx.x == 0) {
-    while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < epoch)
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
       __builtin_amdgcn_s_sleep(1);
   }
   __syncthreads();
 }
 
 __device__ __forceinline__ void post_flag(unsigned* flag, unsigned epoch) {
+  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    __hip_atomic_store(flag, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id.  Shift s is
+// served by the workgroups of XCD s % 8 only, so its dependency chain stays on one
+// L2: workgroup g (XCD g % 8, local index g / 8) serves local shift (g / 8) / nblk
+// of its XCD.  Returns -1 for the padding workgroups of an unbalanced split.
+__device__ __forceinline__ int solve_shift_of(int g, int nblk, int nshift) {
+  const int x = g & 7, j = g >> 3;
+  const int s = x + 8 * (j / nblk);
+  return s < nshift ? s : -1;
 }
 
 // Forward sweep: Z = L^{-1} P Y.  256 threads; thread (i = tid % 64, q = tid / 64)
@@ -113,9 +138,11 @@ __device__ __forceinline__ void post_flag(unsigned* flag, unsigned epoch) {
 __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   __shared__ double sM[SB][SB + 1];
   __shared__ double sZ[kSolveMaxRhs][SB];
-  const int s = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
+  const int s = solve_shift_of(blockIdx.x, nblk, a.nshift);
+  if (s < 0) return;
   const unsigned b = ticket(a.ctr + s, nblk);
   const double* LD = a.LD[s];
   const int* blk = a.blk[s];
@@ -163,7 +190,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
     const int c0 = cb * SB;
     for (int e = tid; e < nrhs * SB; e += 256) {
       const int rr = e & 63, c = e >> 6;
-      sZ[c][rr] = Z[c0 + rr + (long)c * a.ldz];
+      sZ[c][rr] = ld_shared_blk(Z + c0 + rr + (long)c * a.ldz);
     }
     __syncthreads();
 #pragma unroll
@@ -196,7 +223,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
     if (c < nrhs && row < n) {
       double t = 0.0;
       for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
-      Z[row + (long)c * a.ldz] = t;
+      st_shared_blk(Z + row + (long)c * a.ldz, t);
     }
   }
   post_flag(flags + b, a.epoch);
@@ -208,9 +235,11 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
 __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   __shared__ double sM[SB][SB + 1];
   __shared__ double sV[kSolveMaxRhs][SB];
-  const int s = blockIdx.y, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
+  const int s = solve_shift_of(blockIdx.x, nblk, a.nshift);
+  if (s < 0) return;
   const unsigned t = ticket(a.ctr + s, nblk);
   const int b = nblk - 1 - (int)t;
   const double* LD = a.LD[s];
@@ -291,7 +320,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     const int c0 = cb * SB;
     for (int e = tid; e < nrhs * SB; e += 256) {
       const int kk = e & 63, c = e >> 6;
-      sV[c][kk] = (c0 + kk < n) ? V[c0 + kk + (long)c * a.ldz] : 0.0;
+      sV[c][kk] = (c0 + kk < n) ? ld_shared_blk(V + c0 + kk + (long)c * a.ldz) : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -324,7 +353,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     if (c < nrhs && row < n) {
       double tt = 0.0;
       for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
-      V[row + (long)c * a.ldz] = tt;
+      st_shared_blk(V + row + (long)c * a.ldz, tt);
       X[perm[row] + (long)c * a.ldx] = tt;
     }
   }
@@ -361,14 +390,16 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
 
 void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   const int nblk = (int)ceil_div(a.n, SB);
+  // 8 XCDs x ceil(nshift / 8) shift slots x nblk blocks (see solve_shift_of)
+  const unsigned grid = (unsigned)(8 * ceil_div(a.nshift, 8) * nblk);
   sislice_handle* ph = current_handle();
   const int tk = prof_begin(ph, kProfSolve);
   if (mode == 0 || mode == 1) {
-    SL_LAUNCH(k_fwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH(k_fwd, dim3(grid), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   if (mode == 0 || mode == 2) {
-    SL_LAUNCH(k_bwd, dim3(nblk, a.nshift), dim3(256), 0, st, a);
+    SL_LAUNCH(k_bwd, dim3(grid), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   prof_end(ph, tk);
