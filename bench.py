@@ -71,6 +71,9 @@ def main():
     ap.add_argument("--ne", type=int, default=400)
     ap.add_argument("--ns", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the steps, run one elementwise copy kernel over 512 MiB (reads and "
+                         "writes 512 MiB: the reference that scales FETCH_SIZE / WRITE_SIZE to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -164,6 +167,13 @@ def main():
         "converged_per_step": conv_total / args.steps,
         "roofline": roof,
     }
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = {"read": src.numel() * 8, "written": dst.numel() * 8}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(P, state["prev"], n_e, n_s)
     print(json.dumps(line), flush=True)
