@@ -120,16 +120,30 @@ __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states,
 
 __device__ __forceinline__ double u64_to_f64(unsigned long long v) { return __longlong_as_double((long long)v); }
 
-__global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* LDs, long ldld,
-                                                   double* const* Wps, long ldw,
-                                                   double* const* Lps, double* const* auxs,
-                                                   const FactorState* states, int nb) {
-  // A: the diagonal block, eliminated in place (column k holds the unscaled W
-  // column of step k once step k - 1 is done); X: L11^{-1}, built alongside by
-  // applying every elimination step to the identity.
-  __shared__ double A[kMaxNb][kMaxNb + 1];
-  __shared__ double X[kMaxNb][kMaxNb + 1];
-  const int s = blockIdx.x, tid = threadIdx.x;
+// Pivot-free LDL^T of the panel's diagonal block (nbe <= NB columns), one
+// wavefront per shift: lane i holds row i of the block in registers, so no step
+// needs a barrier across wavefronts.  The register window is rotated by four
+// columns every four steps, which keeps every register index static (the pivot
+// column of step k is a[k - t0] inside the unrolled group t0 .. t0 + 3).  The
+// pivot is broadcast with readlane, the multipliers l_ck = A[c][k] / d through
+// LDS.  The finished W columns are kept in LDS for the outputs: the block's rows
+// of W (unscaled) and L, D, the in-block column maxima of |W|, and L11
+// column-major for the row solves of k_fast_trsm.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+template <int NB>
+__global__ __launch_bounds__(64) void k_fast_diag(int n, const double* const* LDs, long ldld,
+                                                  double* const* Wps, long ldw,
+                                                  double* const* Lps, double* const* auxs,
+                                                  const FactorState* states, int nb) {
+  __shared__ double Wb[NB][NB + 1];  // Wb[i][k]: final W of column k (rows >= k)
+  __shared__ double lcol[NB + 64];   // multipliers; zero past NB (window registers past the block)
+  const int s = blockIdx.x, i = threadIdx.x;
   const FactorState st = states[s];
   const int k0 = st.k0 + st.kb;
   if (st.done || k0 >= n) return;
@@ -141,57 +155,81 @@ __global__ __launch_bounds__(256) void k_fast_diag(int n, const double* const* L
   double* Dv = aux;
   double* cin = aux + nb;
   unsigned long long* cout = reinterpret_cast<unsigned long long*>(aux + 2 * nb);
-  double* Linv = aux + 3 * nb;
-  const int cl = tid & (kMaxNb - 1), rg = tid >> 6;  // column of this lane, row phase 0..3
-  for (int i = rg; i < kMaxNb; i += 4) {
-    A[i][cl] = (i < nbe && cl < nbe && i >= cl) ? LD[(k0 + i) + (long)(k0 + cl) * ldld] : 0.0;
-    X[i][cl] = (i == cl) ? 1.0 : 0.0;
+  double* L11 = aux + 3 * nb;  // column-major nb x nb, strictly lower part
+  const bool lane_ok = i < NB;
+  double a[NB];  // a[j] = A[i][t0 + j] for the current group start t0
+#pragma unroll
+  for (int j = 0; j < NB; ++j)
+    a[j] = (lane_ok && i < nbe && j < nbe && i >= j) ? LD[(k0 + i) + (long)(k0 + j) * ldld] : 0.0;
+  for (int c = i; c < nb; c += 64) cout[c] = 0ull;
+  lcol[NB + i] = 0.0;
+  for (int t0 = 0; t0 < nbe; t0 += 4) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int k = t0 + kk;
+      if (k < nbe) {
+        const double ak = a[kk];  // A[i][k]
+        const double d = readlane_f64(ak, k);
+        const double r = 1.0 / d;
+        if (lane_ok) {
+          Wb[i][k] = ak;
+          lcol[i] = ak * r;
+        }
+        __syncthreads();
+        // A[i][c] -= A[i][k] l_ck for the columns c = t0 + j > k of the window
+        // (registers past column NB - 1 hold no column and meet zero multipliers)
+        const double* lc = lcol + t0;
+#pragma unroll
+        for (int j = kk + 1; j < NB; ++j) a[j] -= ak * lc[j];
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int j = 0; j + 4 < NB; ++j) a[j] = a[j + 4];
+#pragma unroll
+    for (int j = NB - 4; j < NB; ++j) a[j] = 0.0;
   }
-  for (int c = tid; c < nb; c += 256) cout[c] = 0ull;
   __syncthreads();
-  for (int k = 0; k + 1 < nbe; ++k) {
-    const double d = A[k][k];
-    // trailing lower part of the block: A[i][j] -= A[i][k] A[j][k] / d, i >= j > k
-    if (cl > k && cl < nbe) {
-      const double ljk = A[cl][k] / d;
-      for (int i = cl + rg; i < nbe; i += 4) A[i][cl] -= A[i][k] * ljk;
+  // outputs (columns k < nbe; lane i = row i)
+  for (int k = 0; k < nbe; ++k) {
+    const double rd = 1.0 / Wb[k][k];
+    if (lane_ok && i < nbe) {
+      const double w = Wb[i][k];
+      const double lv = (i > k) ? w * rd : 0.0;
+      if (i >= k) Wp[(k0 + i) + (long)k * ldw] = w;
+      if (i > k) Lp[(k0 + i) + (long)k * ldw] = lv;
+      L11[i + (long)k * nb] = lv;
     }
-    // rows below k of L^{-1}: X[i][c] -= (A[i][k] / d) X[k][c], c <= k < i
-    if (cl <= k) {
-      const double xkc = X[k][cl];
-      for (int i = k + 1 + rg; i < nbe; i += 4) X[i][cl] -= (A[i][k] / d) * xkc;
-    }
-    __syncthreads();
   }
-  // outputs: D, unscaled W and scaled L of the block, column maxima inside the
-  // block, L11^{-1} column-major
-  for (int i = rg; i < nbe; i += 4) {
-    if (cl < nbe && i >= cl) {
-      const double w = A[i][cl];
-      Wp[(k0 + i) + (long)cl * ldw] = w;
-      if (i > cl) Lp[(k0 + i) + (long)cl * ldw] = w / A[cl][cl];
-    }
-    if (cl < nbe) Linv[i + (long)cl * nb] = (i >= cl) ? X[i][cl] : 0.0;
-  }
-  if (tid < nbe) {
-    const int k = tid;
+  if (lane_ok && i < nbe) {
     double mx = 0.0;
-    for (int i = k + 1; i < nbe; ++i) {
-      const double a = fabs(A[i][k]);
-      mx = (a > mx || a != a) ? a : mx;
+    for (int r = i + 1; r < nbe; ++r) {
+      const double v = fabs(Wb[r][i]);
+      mx = (v > mx || v != v) ? v : mx;
     }
-    cin[k] = mx;
-    Dv[k] = A[k][k];
+    cin[i] = mx;
+    Dv[i] = Wb[i][i];
   }
 }
 
+// Rows below the diagonal block: W21 = C21 L11^{-T} by forward substitution
+// along each row (w_c = c_c - sum_{q<c} w_q L11[c][q], taken right-looking so the
+// updates of one step are independent), L21 = W21 D1^{-1}, and the column maxima
+// of |W21| (atomic max on the bit patterns of non-negative doubles).  The rows
+// below a panel are too few to give every SIMD a wavefront when each is one
+// thread, so a row is shared by four consecutive lanes: lane g of a row holds
+// columns g, g + 4, ... (registers rotated by one every four steps, so the
+// column of step q is always register 0 of lane q % 4), and w_q reaches the
+// row's other lanes with a shuffle.  64 rows per 256-thread workgroup; L11 is
+// read from LDS.
+template <int NB>
 __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* LDs, long ldld,
                                                    double* const* Wps, long ldw,
                                                    double* const* Lps, double* const* auxs,
                                                    const FactorState* states, int nb) {
-  __shared__ double C[64][kMaxNb + 1];
-  __shared__ double Li[kMaxNb][kMaxNb + 1];
-  __shared__ double Dsh[kMaxNb];
+  constexpr int M = NB / 4;
+  __shared__ double sL[NB * NB];  // column-major: sL[q * NB + c] = L11[c][q]
+  __shared__ double sRD[NB];
   const int s = blockIdx.y, tid = threadIdx.x;
   const FactorState st = states[s];
   const int k0 = st.k0 + st.kb;
@@ -204,31 +242,53 @@ __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* L
   double* Lp = Lps[s];
   const double* aux = auxs[s];
   unsigned long long* cout = reinterpret_cast<unsigned long long*>(const_cast<double*>(aux) + 2 * nb);
-  const double* Linv = aux + 3 * nb;
-  for (int e = tid; e < 64 * nbe; e += 256) {
-    const int r = e & 63, k = e >> 6;
-    C[r][k] = (r0 + r < n) ? LD[(r0 + r) + (long)(k0 + k) * ldld] : 0.0;
+  const double* L11 = aux + 3 * nb;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int c = e % NB, q = e / NB;
+    sL[e] = (c < nbe && q < nbe) ? L11[c + (long)q * nb] : 0.0;
   }
-  for (int e = tid; e < nbe * nbe; e += 256) {
-    const int i = e % nbe, k = e / nbe;
-    Li[i][k] = Linv[i + (long)k * nb];
+  if (tid < NB) sRD[tid] = (tid < nbe) ? 1.0 / aux[tid] : 0.0;
+  const int g = tid & 3;
+  const int row = r0 + (tid >> 2);
+  const bool rv = row < n;
+  const double* Cr = LD + (rv ? row : n - 1) + (long)k0 * ldld;
+  double w[M];  // w[m] = W[row][t0 + g + 4m] for the current group start t0
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int c = g + 4 * m;
+    w[m] = (c < nbe) ? Cr[(long)c * ldld] : 0.0;
   }
-  if (tid < nbe) Dsh[tid] = aux[tid];
   __syncthreads();
-  // wavefront cg handles columns cg, cg+4, ...; lane r handles row r0 + r
-  const int r = tid & 63, cg = tid >> 6;
-  for (int c = cg; c < nbe; c += 4) {
-    double w = 0.0;
-    for (int k = 0; k <= c; ++k) w += C[r][k] * Li[c][k];
-    if (r0 + r < n) {
-      Wp[(r0 + r) + (long)c * ldw] = w;
-      Lp[(r0 + r) + (long)c * ldw] = w / Dsh[c];
+  const int lane0 = (tid & 63) & ~3;
+  for (int t0 = 0; t0 < nbe; t0 += 4) {
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int q = t0 + kk;
+      if (q < nbe) {
+        const double wq = __shfl(w[0], lane0 | kk);
+        const double* Lq = sL + q * NB;
+        // register m holds column c = t0 + g + 4m; it is updated when c > q
+        const double u0 = w[0] - wq * Lq[min(t0 + g, NB - 1)];
+        w[0] = (g > kk) ? u0 : w[0];
+#pragma unroll
+        for (int m = 1; m < M; ++m) w[m] -= wq * Lq[min(t0 + g + 4 * m, NB - 1)];
+      }
     }
-    double mx = (r0 + r < n) ? fabs(w) : 0.0;
+    // column t0 + g is final: write it, fold it into the column maximum, rotate
+    const int c0 = t0 + g;
+    if (rv && c0 < nbe) {
+      Wp[row + (long)c0 * ldw] = w[0];
+      Lp[row + (long)c0 * ldw] = w[0] * sRD[c0];
+    }
+    double mx = (rv && c0 < nbe) ? fabs(w[0]) : 0.0;
     if (mx != mx) mx = __longlong_as_double(0x7FF0000000000000ll);  // NaN ranks as +inf
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    if (r == 0) atomicMax(cout + c, (unsigned long long)__double_as_longlong(mx));
+    for (int off = 4; off < 64; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((tid & 63) < 4 && c0 < nbe)
+      atomicMax(cout + c0, (unsigned long long)__double_as_longlong(mx));
+#pragma unroll
+    for (int m = 0; m + 1 < M; ++m) w[m] = w[m + 1];
+    w[M - 1] = 0.0;
   }
 }
 
@@ -550,14 +610,17 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
 
 // C22 -= L21 W21^T on the lower triangle of the trailing matrix of every shift.
 // 64x64 tile per 256-thread workgroup; each wavefront owns a 32x32 quarter as
-// 2x2 MFMA 16x16 blocks.  The A operand is W (tile columns), the B operand is L
-// (tile rows), so that accumulator element r of lane l is C(i0 + l%16,
-// j0 + l/16 + 4r): sixteen consecutive rows of one column per register,
-// i.e. coalesced column-major reads and writes.
+// 2x2 v_mfma_f64_16x16x4 blocks.  The A operand is -W (tile columns), the B
+// operand is L (tile rows), so that accumulator element r of lane l is
+// C(i0 + l%16, j0 + l/16 + 4r): sixteen consecutive rows of one column per
+// register.  The tile of C is loaded straight into the accumulators, every
+// operand of the panel's K <= 64 columns is issued from global memory up front
+// (no LDS, no barrier: occupancy is bounded by registers only), and the
+// accumulators are stored back: one read and one write of C per panel.
 __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* LDs, long ldld,
                                                          double* const* Wps, long ldw,
                                                          const FactorState* states) {
-  extern __shared__ double smem[];
+  constexpr int KS = kMaxNb / 4;  // k-steps of 4
   const int s = blockIdx.y;
   const int k0 = states[s].k0, kb = states[s].kb;
   const int k1 = k0 + kb;
@@ -570,47 +633,66 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
   while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
   const int tj = lin - ti * (ti + 1) / 2;
   const int row0 = k1 + ti * 64, col0 = k1 + tj * 64;
-  const double* LD0 = LDs[s];
   double* LD = LDs[s];
   const double* Wp = Wps[s];
-  const int Kp = (kb + 3) & ~3;
-  double* sL = smem;            // [Kp][64]: L(row0 + i, k0 + k)
-  double* sW = smem + Kp * 64;  // [Kp][64]: W(col0 + j, k)
   const int tid = threadIdx.x;
-  for (int e = tid; e < Kp * 64; e += 256) {
-    const int i = e & 63, k = e >> 6;
-    const bool okk = k < kb;
-    sL[e] = (okk && row0 + i < n) ? LD0[row0 + i + (long)(k0 + k) * ldld] : 0.0;
-    sW[e] = (okk && col0 + i < n) ? Wp[col0 + i + (long)k * ldw] : 0.0;
-  }
-  __syncthreads();
-  const int w = tid >> 6, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int wi = (w & 1) * 32, wj = (w >> 1) * 32;
+  const int lr = l & 15, lk = l >> 4;
+  const int nks = (kb + 3) >> 2;
+  // tile rows / columns of this lane (clamped for the loads, masked for the stores)
+  int ri[2], cj[2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x) ri[x] = row0 + wi + 16 * x + lr;
+#pragma unroll
+  for (int y = 0; y < 2; ++y) cj[y] = col0 + wj + 16 * y + lr;
   d4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-  const int lr = l & 15, lk = l >> 4;
-  for (int kk = 0; kk < Kp; kk += 4) {
-    const double* pl = sL + (kk + lk) * 64;
-    const double* pw = sW + (kk + lk) * 64;
-    const double b0 = pl[wi + lr], b1 = pl[wi + 16 + lr];
-    const double a0 = pw[wj + lr], a1 = pw[wj + 16 + lr];
-    acc[0][0] = mfma16x16x4(a0, b0, acc[0][0]);
-    acc[0][1] = mfma16x16x4(a1, b0, acc[0][1]);
-    acc[1][0] = mfma16x16x4(a0, b1, acc[1][0]);
-    acc[1][1] = mfma16x16x4(a1, b1, acc[1][1]);
-  }
-#pragma unroll
-  for (int bi = 0; bi < 2; ++bi) {
-    const int i = row0 + wi + 16 * bi + lr;
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
+    for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int jc = col0 + wj + 16 * bj + lk + 4 * r;
-        if (i < n && jc < n && i >= jc) LD[i + (long)jc * ldld] -= acc[bi][bj][r];
+        const int i = min(ri[x], n - 1), j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
+        acc[x][y][r] = LD[i + (long)j * ldld];
+      }
+  double lop[2][KS], wop[2][KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks < nks) {
+      const int k = 4 * ks + lk;
+      const bool kv = k < kb;
+      const int kc = kv ? k : 0;
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const double v = LD[min(ri[x], n - 1) + (long)(k0 + kc) * ldld];
+        lop[x][ks] = kv ? v : 0.0;
+      }
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const double v = Wp[min(cj[y], n - 1) + (long)kc * ldw];
+        wop[y][ks] = kv ? -v : 0.0;
+      }
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    if (ks < nks) {
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(wop[y][ks], lop[x][ks], acc[x][y]);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 2; ++x) {
+    const int i = ri[x];
+#pragma unroll
+    for (int y = 0; y < 2; ++y) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jc = col0 + wj + 16 * y + lk + 4 * r;
+        if (i < n && jc < n && i >= jc) LD[i + (long)jc * ldld] = acc[x][y][r];
       }
     }
   }
@@ -717,15 +799,27 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const long k0_lb = std::min<long>(n, kmin + (long)q * min_kb);
       if (fp.fast) {
         const int tf = prof_begin(ph, kProfPanel);
-        SL_LAUNCH(k_fast_diag, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
-                           fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
-        SL_LAUNCH_CHECK();
         const long rows = n - k0_lb - 1;
-        if (rows > 0) {
-          SL_LAUNCH(k_fast_trsm, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
-                             (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
-                             fp.d_state, nb);
+        if (nb > 32) {
+          SL_LAUNCH(k_fast_diag<64>, dim3(S), dim3(64), 0, st, n, (const double* const*)fp.d_LD,
+                    fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
           SL_LAUNCH_CHECK();
+          if (rows > 0) {
+            SL_LAUNCH(k_fast_trsm<64>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+                      (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                      fp.d_state, nb);
+            SL_LAUNCH_CHECK();
+          }
+        } else {
+          SL_LAUNCH(k_fast_diag<32>, dim3(S), dim3(64), 0, st, n, (const double* const*)fp.d_LD,
+                    fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+          SL_LAUNCH_CHECK();
+          if (rows > 0) {
+            SL_LAUNCH(k_fast_trsm<32>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+                      (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                      fp.d_state, nb);
+            SL_LAUNCH_CHECK();
+          }
         }
         if (fp.pivot)
           SL_LAUNCH(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
@@ -752,9 +846,8 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const long k1_lb = std::min<long>(n, k0_lb + min_kb);
       if (k1_lb >= n) continue;
       const long T = ceil_div(n - k1_lb, 64);
-      const size_t lds = (size_t)2 * ((nb + 3) & ~3) * 64 * sizeof(double);
       const int tu = prof_begin(ph, kProfUpdate);
-      SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), lds,
+      SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0,
                          st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
       SL_LAUNCH_CHECK();
       prof_end(ph, tu);
