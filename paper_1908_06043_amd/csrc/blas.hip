@@ -290,6 +290,180 @@ void skinny_launch(int n, int ncol, const double* M, long ldm, int tri, const do
   prof_end(ph, tk);
 }
 
+// ------------------------------------------------- tall-skinny products, 8 columns
+//
+// The Lanczos block is 8 columns wide, so the reorthogonalisation and CholeskyQR
+// products are (n x m)^T (n x 8) and (n x m) (m x 8) with n >> m: bound by
+// reading the n x m basis once.  The generic 64x64-tile GEMM spends 8x its work on
+// padding here; these kernels stream the basis instead.
+//
+// k_tsmt: C_b = V_b^T X_b (m_b x 8).  A workgroup takes kTsRows rows of one batch
+// entry and 64 columns of V, stages 64-row slices of V through LDS (coalesced
+// along the rows) and accumulates 8 dot products per column in four row phases;
+// per-chunk partials are summed in chunk order by k_tsmt_reduce.
+__global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
+  __shared__ double sV[64][65];
+  __shared__ double sX[kTsRows][8];
+  const int b = blockIdx.z, q = blockIdx.x;
+  const int m = a.m[b];
+  const int i0 = blockIdx.y * 64;
+  if (i0 >= m) return;
+  const int n = a.n, r0 = q * kTsRows;
+  const double* V = a.V[b];
+  const double* X = a.X[b];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kTsRows * 8; e += 256) {
+    const int r = e % kTsRows, c = e / kTsRows;
+    sX[r][c] = (r0 + r < n) ? X[r0 + r + (long)c * a.ldx] : 0.0;
+  }
+  const int i = tid & 63, rg = tid >> 6;
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int st = 0; st < kTsRows / 64; ++st) {
+    const int rs = r0 + 64 * st;
+    __syncthreads();
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e & 63, ii = e >> 6;
+      sV[r][ii] = (rs + r < n && i0 + ii < m) ? V[rs + r + (long)(i0 + ii) * a.ldv] : 0.0;
+    }
+    __syncthreads();
+    for (int rr = rg; rr < 64; rr += 4) {
+      const double v = sV[rr][i];
+      const double* xr = sX[64 * st + rr];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] += v * xr[c];
+    }
+  }
+  __syncthreads();
+  double* red = &sV[0][0];  // [3][64][8]
+  if (rg > 0) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) red[((rg - 1) * 64 + i) * 8 + c] = acc[c];
+  }
+  __syncthreads();
+  if (rg == 0 && i0 + i < m) {
+    double* P = a.partial + (((long)b * a.nchunk + q) * a.mmax + (i0 + i)) * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      P[c] = ((acc[c] + red[(0 * 64 + i) * 8 + c]) + red[(1 * 64 + i) * 8 + c]) + red[(2 * 64 + i) * 8 + c];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tsmt_reduce(TsArgs a) {
+  const int b = blockIdx.y;
+  const int m = a.m[b];
+  double* C = a.C[b];
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < m * 8; e += gridDim.x * 256) {
+    const int i = e >> 3, c = e & 7;
+    double s = 0.0;
+    for (int q = 0; q < a.nchunk; ++q) s += a.partial[(((long)b * a.nchunk + q) * a.mmax + i) * 8 + c];
+    const long ldc = a.ldcb ? a.ldcb[b] : a.ldc;
+    C[i + (long)c * ldc] = a.alpha * s;
+  }
+}
+
+void tsmt_launch(TsArgs a, int batch, int mmax, hipStream_t st) {
+  if (batch <= 0 || mmax <= 0) return;
+  a.mmax = mmax;
+  a.nchunk = (int)ceil_div(a.n, kTsRows);
+  sislice_handle* ph = current_handle();
+  const int tk = prof_begin(ph, kProfGemm);
+  SL_LAUNCH(k_tsmt, dim3(a.nchunk, (unsigned)ceil_div(mmax, 64), batch), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+  SL_LAUNCH(k_tsmt_reduce, dim3((unsigned)ceil_div(mmax * 8, 256), batch), dim3(256), 0, st, a);
+  SL_LAUNCH_CHECK();
+  prof_end(ph, tk);
+}
+
+// k_tsmm: Y_b = beta Y_b + alpha (V_b C_b + V2_b C2_b), n x 8.  The coefficients
+// sit in LDS; four consecutive lanes share a row (two output columns each), so a
+// wavefront reads 16 consecutive rows of V per column: one 128-byte segment.
+__global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
+  extern __shared__ double sC[];  // [m1 + m2][8]
+  const int b = blockIdx.y, tid = threadIdx.x;
+  const int m1 = a.m[b], m2 = a.m2 ? a.m2[b] : 0;
+  const double* C1 = a.C[b];
+  for (int e = tid; e < m1 * 8; e += 256) {
+    const int k = e % m1, c = e / m1;
+    sC[k * 8 + c] = C1[k + (long)c * a.ldc];
+  }
+  if (m2 > 0) {
+    const double* C2 = a.C2[b];
+    for (int e = tid; e < m2 * 8; e += 256) {
+      const int k = e % m2, c = e / m2;
+      sC[(m1 + k) * 8 + c] = C2[k + (long)c * a.ldc2];
+    }
+  }
+  __syncthreads();
+  const int n = a.n;
+  const int row = blockIdx.x * 64 + (tid >> 2), g = tid & 3;
+  const bool rv = row < n;
+  const int rc = rv ? row : n - 1;
+  double acc0 = 0.0, acc1 = 0.0;
+  const double* V1 = a.V[b] + rc;
+  int k = 0;
+  for (; k + 4 <= m1; k += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = V1[(long)(k + u) * a.ldv];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc0 += v[u] * sC[(k + u) * 8 + 2 * g];
+      acc1 += v[u] * sC[(k + u) * 8 + 2 * g + 1];
+    }
+  }
+  for (; k < m1; ++k) {
+    const double v = V1[(long)k * a.ldv];
+    acc0 += v * sC[k * 8 + 2 * g];
+    acc1 += v * sC[k * 8 + 2 * g + 1];
+  }
+  if (m2 > 0) {
+    const double* V2 = a.V2[b] + rc;
+    const double* sC2 = sC + m1 * 8;
+    int k2 = 0;
+    for (; k2 + 4 <= m2; k2 += 4) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = V2[(long)(k2 + u) * a.ldv2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc0 += v[u] * sC2[(k2 + u) * 8 + 2 * g];
+        acc1 += v[u] * sC2[(k2 + u) * 8 + 2 * g + 1];
+      }
+    }
+    for (; k2 < m2; ++k2) {
+      const double v = V2[(long)k2 * a.ldv2];
+      acc0 += v * sC2[k2 * 8 + 2 * g];
+      acc1 += v * sC2[k2 * 8 + 2 * g + 1];
+    }
+  }
+  if (rv) {
+    double* Y = a.Y[b] + row;
+    double* y0 = Y + (long)(2 * g) * a.ldy;
+    double* y1 = Y + (long)(2 * g + 1) * a.ldy;
+    *y0 = (a.beta == 0.0) ? a.alpha * acc0 : a.beta * *y0 + a.alpha * acc0;
+    *y1 = (a.beta == 0.0) ? a.alpha * acc1 : a.beta * *y1 + a.alpha * acc1;
+  }
+}
+
+void tsmm_launch(TsArgs a, int batch, int mtot_max, hipStream_t st) {
+  if (batch <= 0) return;
+  const size_t lds = (size_t)std::max(mtot_max, 1) * 8 * sizeof(double);
+  SL_CHECK_ARG(lds <= kTsmmMaxLds, "tall-skinny product: too many basis columns");
+  static bool attr = false;
+  if (!attr) {
+    SL_HIP(hipFuncSetAttribute((const void*)k_tsmm, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kTsmmMaxLds));
+    attr = true;
+  }
+  sislice_handle* ph = current_handle();
+  const int tk = prof_begin(ph, kProfGemm);
+  SL_LAUNCH(k_tsmm, dim3((unsigned)ceil_div(a.n, 64), batch), dim3(256), lds, st, a);
+  SL_LAUNCH_CHECK();
+  prof_end(ph, tk);
+}
+
 // out = f1 * X + f2 * Y + f3 * Z elementwise over n x ncol blocks (ld n); Z may
 // be null (f3 ignored).
 __global__ __launch_bounds__(256) void k_lincomb3(long tot, double f1, const double* __restrict__ X,

@@ -46,6 +46,40 @@ void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, d
                           hipStream_t st);
 void transpose_launch(int n, const double* S, long lds, double* T, long ldt, hipStream_t st);
 
+// Batched tall-skinny products with 8 columns (the Lanczos block):
+//   tsmt: C_b (m_b x 8, ldc) = alpha V_b^T X_b          (V_b n x m_b, X_b n x 8)
+//   tsmm: Y_b (n x 8, ldy) = beta Y_b + alpha (V_b C_b + V2_b C2_b)
+//         (V2/C2/m2 optional; C_b m_b x 8 with ldc, C2_b m2_b x 8 with ldc2)
+// tsmt needs `partial` with batch * ceil(n / kTsRows) * mmax * 8 doubles.
+constexpr int kTsRows = 256;
+constexpr size_t kTsmmMaxLds = 160 * 1024;
+struct TsArgs {
+  int n = 0;
+  const int* m = nullptr;
+  const double* const* V = nullptr;
+  long ldv = 0;
+  const double* const* X = nullptr;
+  long ldx = 0;
+  double* const* C = nullptr;
+  long ldc = 0;
+  const int* ldcb = nullptr;  // tsmt: per-entry output leading dimension (overrides ldc)
+  const int* m2 = nullptr;
+  const double* const* V2 = nullptr;
+  long ldv2 = 0;
+  const double* const* C2 = nullptr;
+  long ldc2 = 0;
+  double* const* Y = nullptr;
+  long ldy = 0;
+  double alpha = 1.0, beta = 0.0;
+  double* partial = nullptr;
+  int nchunk = 0, mmax = 0;
+};
+inline size_t tsmt_partial_size(int n, int batch, int mmax) {
+  return (size_t)batch * ceil_div(n, kTsRows) * mmax * 8;
+}
+void tsmt_launch(TsArgs a, int batch, int mmax, hipStream_t st);
+void tsmm_launch(TsArgs a, int batch, int mtot_max, hipStream_t st);
+
 constexpr int kDotChunk = 2048;
 
 // mode 0: out[b][c] = X[:,c] . Y[:,c];  mode 1: out[b][c] = ||X[:,c] - w[b][c] Y[:,c]||_2

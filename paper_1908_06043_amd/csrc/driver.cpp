@@ -658,6 +658,8 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     zl.take<int>(2 * QC);              // idx lock / keep
   }
   zl.take<int>(P);  // flags
+  const int ts_mmax = std::max(LC, QC);
+  zl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));  // tall-skinny partials
   Carver cl(ws_get(h, kBufLanczos, zl.off));
   double* Wall = cl.take<double>((size_t)n * b * P);
   double* Zall = cl.take<double>((size_t)n * b * P);
@@ -694,8 +696,9 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     d.ik = ii + QC;
   }
   int* dflags = cl.take<int>(P);
+  double* tspart = cl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));
   for (int j = 0; j < P; ++j) SL_HIP(hipMemsetAsync(pd[j].T, 0, sizeof(double) * QC * QC, st));
-  unsigned* sync = sync_words(h, 64 + (size_t)P * 2 * nblk + 64);
+  unsigned* sync = sync_words(h, (size_t)P + 64);  // one ticket counter per probe
   auto Wj = [&](int j) { return Wall + (size_t)j * n * b; };
   auto Zj = [&](int j) { return Zall + (size_t)j * n * b; };
   // start blocks: Gaussian from the shared stream, B-orthonormalised (CholeskyQR2)
@@ -723,7 +726,20 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     const int na = (int)js.size();
     std::vector<int> ones(na, 1), bs(na, b), ns(na, n);
     std::vector<const double*> cV(Vin.begin(), Vin.end()), cU(Uin.begin(), Uin.end());
-    gemm(c, true, false, bs, bs, ns, cV, ldin, cU, ldin, act_vec(js, [&](int j) { return pd[j].G; }), b, 1.0, 0.0);
+    auto gram = [&](const std::vector<const double*>& Vv, const std::vector<const double*>& Uv, long ld) {
+      TsArgs ta;
+      ta.n = n;
+      ta.m = ring.vec(bs);
+      ta.V = ring.cptrs(Vv);
+      ta.ldv = ld;
+      ta.X = ring.cptrs(Uv);
+      ta.ldx = ld;
+      ta.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].G; }));
+      ta.ldc = b;
+      ta.partial = tspart;
+      tsmt_launch(ta, na, b, st);
+    };
+    gram(cV, cU, ldin);
     CholQrArgs q;
     q.n = n;
     q.active = ring.vec(ones);
@@ -738,7 +754,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     q.flag = dflags;  // indexed by position; only read when all probes are active
     cholqr_launch(q, na, st);
     std::vector<const double*> cVo(Vout.begin(), Vout.end()), cUo(Uout.begin(), Uout.end());
-    gemm(c, true, false, bs, bs, ns, cVo, n, cUo, n, act_vec(js, [&](int j) { return pd[j].G; }), b, 1.0, 0.0);
+    gram(cVo, cUo, n);
     q.Vin = ring.cptrs(Vout);
     q.Uin = ring.cptrs(Uout);
     q.ldin = n;
@@ -815,8 +831,6 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       sa.Z = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Zs; }));
       sa.V = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Vs; }));
       sa.ldz = n;
-      sa.flags = sync + 64;
-      sa.flag_stride = 2 * nblk;
       sa.ctr = sync;
       solve_launch(sa, st, 0);
       // b. full B-reorthogonalisation, twice; T's new column block from the projections
@@ -826,15 +840,49 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       const auto vnl = act_vec(js, [&](int j) { return pr[j].nl; });
       const auto pW = act_vec(js, [&](int j) { return (const double*)Wj(j); });
       const auto pWm = act_vec(js, Wj);
+      // one tall-skinny launch computes both projections (locked basis: CL = UL^T W,
+      // active basis: CQ = UQ^T W) and one applies W -= L CL + Q CQ
+      std::vector<int> m_lq(vnl);
+      m_lq.insert(m_lq.end(), vmq.begin(), vmq.end());
+      std::vector<int> ld_lq(na, LC);
+      ld_lq.insert(ld_lq.end(), na, QC);
+      std::vector<const double*> v_lq = act_vec(js, [&](int j) { return (const double*)pd[j].UL; });
+      for (int j : js) v_lq.push_back(pd[j].UQ);
+      std::vector<const double*> x_lq(pW);
+      x_lq.insert(x_lq.end(), pW.begin(), pW.end());
+      std::vector<double*> c_lq = act_vec(js, [&](int j) { return pd[j].CL; });
+      for (int j : js) c_lq.push_back(pd[j].CQ);
+      int mtot = 0;
+      for (int q = 0; q < na; ++q) mtot = std::max(mtot, vnl[q] + vmq[q]);
       for (int pass = 0; pass < 2; ++pass) {
-        gemm(c, true, false, vnl, vb, vn, act_vec(js, [&](int j) { return (const double*)pd[j].UL; }), n,
-             pW, n, act_vec(js, [&](int j) { return pd[j].CL; }), LC, 1.0, 0.0);
-        gemm(c, true, false, vmq, vb, vn, act_vec(js, [&](int j) { return (const double*)pd[j].UQ; }), n,
-             pW, n, act_vec(js, [&](int j) { return pd[j].CQ; }), QC, 1.0, 0.0);
-        gemm(c, false, false, vn, vb, vnl, act_vec(js, [&](int j) { return (const double*)pd[j].L; }), n,
-             act_vec(js, [&](int j) { return (const double*)pd[j].CL; }), LC, pWm, n, -1.0, 1.0);
-        gemm(c, false, false, vn, vb, vmq, act_vec(js, [&](int j) { return (const double*)pd[j].Q; }), n,
-             act_vec(js, [&](int j) { return (const double*)pd[j].CQ; }), QC, pWm, n, -1.0, 1.0);
+        TsArgs ta;
+        ta.n = n;
+        ta.m = ring.vec(m_lq);
+        ta.V = ring.cptrs(v_lq);
+        ta.ldv = n;
+        ta.X = ring.cptrs(x_lq);
+        ta.ldx = n;
+        ta.C = ring.ptrs(c_lq);
+        ta.ldcb = ring.vec(ld_lq);
+        ta.partial = tspart;
+        tsmt_launch(ta, 2 * na, ts_mmax, st);
+        TsArgs tm;
+        tm.n = n;
+        tm.m = ring.vec(vnl);
+        tm.V = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].L; }));
+        tm.ldv = n;
+        tm.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].CL; }));
+        tm.ldc = LC;
+        tm.m2 = ring.vec(vmq);
+        tm.V2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].Q; }));
+        tm.ldv2 = n;
+        tm.C2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].CQ; }));
+        tm.ldc2 = QC;
+        tm.Y = ring.ptrs(pWm);
+        tm.ldy = n;
+        tm.alpha = -1.0;
+        tm.beta = 1.0;
+        tsmm_launch(tm, na, mtot, st);
         TWriteArgs tw;
         tw.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
         tw.ldt = QC;

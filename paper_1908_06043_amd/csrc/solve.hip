@@ -6,10 +6,10 @@
 // of 64.  Each solve is one persistent launch per direction: workgroups take
 // row blocks in dependency order from a per-shift ticket counter (so a block
 // only ever waits for blocks already owned by running workgroups), accumulate
-// the off-diagonal contributions of finished blocks as their epoch flags appear
-// (agent-scope release/acquire), and finish their block with a precomputed
-// inverse of the 64x64 unit-lower diagonal block, so the critical path per
-// block is one flag hand-off plus a 64x64 GEMV.  L is read once per direction.
+// the off-diagonal contributions of finished blocks as those blocks appear
+// (sentinel hand-off below), and finish their block with a precomputed inverse
+// of the 64x64 unit-lower diagonal block, so the critical path per block is one
+// hand-off plus a 64x64 GEMV.  L is read once per direction.
 // The block-diagonal D^{-1} (1x1 and 2x2 pivots) is applied at the start of the
 // backward sweep.
 #include "common.hpp"
@@ -87,14 +87,16 @@ __device__ __forceinline__ unsigned ticket(unsigned* ctr, unsigned nblk) {
   return t;
 }
 
-// Hand-off between workgroups.  The 64-row result blocks that other workgroups
-// of the same sweep read are written and read as relaxed agent-scope atomics,
-// which go to the device coherence point instead of a (per-XCD, non-coherent) L2
-// line; a block is published by draining this wave's stores (vmcnt(0)) in every
-// wave, a barrier, and one relaxed agent-scope flag store.  The waiter polls the
-// flag with relaxed loads: an acquire load (or fence) per poll invalidates the
-// caches each time, and with hundreds of pollers that serialises the whole chip.
-constexpr int kWaitVmcnt0 = 0x0F70;  // s_waitcnt vmcnt(0) expcnt(7) lgkmcnt(15)
+// Hand-off between workgroups without flags.  Before a sweep, its result buffer
+// is filled with a signalling-NaN sentinel (no arithmetic result is a signalling
+// NaN, and the fill kernel has completed before the sweep starts).  A block is
+// published by storing its values as relaxed agent-scope atomics, which go to
+// the device coherence point instead of a per-XCD L2 line; a waiter polls the
+// block itself with agent-scope loads until no sentinel is left.  One round trip
+// per hand-off, no drain on the producer's side.  (Polling a flag with acquire
+// loads would invalidate the caches on every poll; with hundreds of waiters that
+// serialises the whole chip.)
+constexpr unsigned long long kSentinelBits = 0x7FF4000000000001ull;
 
 __device__ __forceinline__ double ld_shared_blk(const double* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -104,27 +106,52 @@ __device__ __forceinline__ void st_shared_blk(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void wait_flag(const unsigned* flag, unsigned epoch) {
-  if (threadIdx.x == 0) {
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch)
-      __builtin_amdgcn_s_sleep(1);
-  }
-  __syncthreads();
+__device__ __forceinline__ bool is_sentinel(double v) {
+  return (unsigned long long)__double_as_longlong(v) == kSentinelBits;
 }
 
-__device__ __forceinline__ void post_flag(unsigned* flag, unsigned epoch) {
-  __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// sX[c][rr] = block rows rr < rows of column c of B (ld ldb), once none is the
+// sentinel; rows past `rows` read as zero.
+__device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, long ldb, int nrhs,
+                                           int rows) {
+  for (;;) {
+    int ok = 1;
+    for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
+      const int rr = e & 63, c = e >> 6;
+      double v = 0.0;
+      if (rr < rows) {
+        v = ld_shared_blk(B + rr + (long)c * ldb);
+        if (is_sentinel(v)) ok = 0;
+      }
+      sX[c][rr] = v;
+    }
+    if (__syncthreads_and(ok)) return;
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_sentinel(int n, int nrhs, int nshift,
+                                                       double* const* A, double* const* B, long ld) {
+  const int s = blockIdx.y;
+  const double sv = __longlong_as_double((long long)kSentinelBits);
+  const long tot = (long)n * nrhs;
+  for (long e = blockIdx.x * 256L + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
+    const long off = (e % n) + (e / n) * ld;
+    if (A) A[s][off] = sv;
+    if (B) B[s][off] = sv;
+  }
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin by linear id.  Shift s is
 // served by the workgroups of XCD s % 8 only, so its dependency chain stays on one
-// L2: workgroup g (XCD g % 8, local index g / 8) serves local shift (g / 8) / nblk
-// of its XCD.  Returns -1 for the padding workgroups of an unbalanced split.
-__device__ __forceinline__ int solve_shift_of(int g, int nblk, int nshift) {
+// L2.  On each XCD the shifts are interleaved by rank (local index j = rank * U + u
+// serves shift x + 8u, U = ceil(nshift / 8)), so every shift's first workgroups
+// are dispatched before any shift's later ones.  Returns -1 for the padding
+// workgroups of an unbalanced split.
+__device__ __forceinline__ int solve_shift_of(int g, int nshift) {
   const int x = g & 7, j = g >> 3;
-  const int s = x + 8 * (j / nblk);
+  const int U = (nshift + 7) >> 3;
+  const int s = x + 8 * (j % U);
   return s < nshift ? s : -1;
 }
 
@@ -141,7 +168,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
-  const int s = solve_shift_of(blockIdx.x, nblk, a.nshift);
+  const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
   const unsigned b = ticket(a.ctr + s, nblk);
   const double* LD = a.LD[s];
@@ -149,7 +176,6 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   const int* perm = a.perm[s];
   const double* Y = a.Y[s];
   double* Z = a.Z[s];
-  unsigned* flags = a.flags + (long)s * a.flag_stride;
   const int r0 = b * SB;
   const int row = r0 + i;
   // everything that does not depend on other blocks is issued first
@@ -186,13 +212,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
     }
     if (cb + 1 < (int)b) load_L(cb + 1);
-    wait_flag(flags + cb, a.epoch);
-    const int c0 = cb * SB;
-    for (int e = tid; e < nrhs * SB; e += 256) {
-      const int rr = e & 63, c = e >> 6;
-      sZ[c][rr] = ld_shared_blk(Z + c0 + rr + (long)c * a.ldz);
-    }
-    __syncthreads();
+    poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB);
 #pragma unroll
     for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -226,7 +246,6 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       st_shared_blk(Z + row + (long)c * a.ldz, t);
     }
   }
-  post_flag(flags + b, a.epoch);
 }
 
 // Backward sweep: X = P^T L^{-T} D^{-1} Z.  The structural zero inside an
@@ -238,7 +257,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
-  const int s = solve_shift_of(blockIdx.x, nblk, a.nshift);
+  const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
   const unsigned t = ticket(a.ctr + s, nblk);
   const int b = nblk - 1 - (int)t;
@@ -248,7 +267,6 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   const double* Z = a.Z[s];
   double* V = a.V[s];
   double* X = a.X[s];
-  unsigned* flags = a.flags + (long)s * a.flag_stride + nblk;
   const int r0 = b * SB;
   const int row = r0 + i;
   double inv[SB * SB / 256];
@@ -316,13 +334,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
     }
     if (cb - 1 > b) load_L(cb - 1);
-    wait_flag(flags + cb, a.epoch);
-    const int c0 = cb * SB;
-    for (int e = tid; e < nrhs * SB; e += 256) {
-      const int kk = e & 63, c = e >> 6;
-      sV[c][kk] = (c0 + kk < n) ? ld_shared_blk(V + c0 + kk + (long)c * a.ldz) : 0.0;
-    }
-    __syncthreads();
+    poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB));
 #pragma unroll
     for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -357,7 +369,6 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       X[perm[row] + (long)c * a.ldx] = tt;
     }
   }
-  post_flag(flags + b, a.epoch);
 }
 
 // Li (ldli, zero elsewhere) receives the 64x64 inverses of L's diagonal blocks on
@@ -390,10 +401,17 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
 
 void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   const int nblk = (int)ceil_div(a.n, SB);
+  SL_CHECK_ARG(a.nrhs >= 0 && a.nrhs <= kSolveMaxRhs, "too many right-hand sides for one sweep");
   // 8 XCDs x ceil(nshift / 8) shift slots x nblk blocks (see solve_shift_of)
   const unsigned grid = (unsigned)(8 * ceil_div(a.nshift, 8) * nblk);
   sislice_handle* ph = current_handle();
   const int tk = prof_begin(ph, kProfSolve);
+  // sentinels in the result buffers of the sweeps of this launch
+  const long tot = (long)a.n * a.nrhs;
+  SL_LAUNCH(k_fill_sentinel, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 1024), a.nshift),
+            dim3(256), 0, st, a.n, a.nrhs, a.nshift, (mode == 0 || mode == 1) ? a.Z : nullptr,
+            (mode == 0 || mode == 2) ? a.V : nullptr, a.ldz);
+  SL_LAUNCH_CHECK();
   if (mode == 0 || mode == 1) {
     SL_LAUNCH(k_fwd, dim3(grid), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();

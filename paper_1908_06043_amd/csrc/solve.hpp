@@ -20,11 +20,9 @@ struct SolveArgs {
   long ldy = 0;
   double* const* X = nullptr;           // output n x nrhs (ldx); may alias Y
   long ldx = 0;
-  double* const* Z = nullptr;           // scratch n x nrhs (ldz)
-  double* const* V = nullptr;           // scratch n x nrhs (ldz)
+  double* const* Z = nullptr;           // scratch n x nrhs (ldz); the forward result
+  double* const* V = nullptr;           // scratch n x nrhs (ldz); the backward result
   long ldz = 0;
-  unsigned* flags = nullptr;            // nshift * flag_stride (>= 2 * nblk), zero-initialised once
-  long flag_stride = 0;
   unsigned* ctr = nullptr;              // nshift ticket counters, zero-initialised once
   int applyD = 1;                       // backward sweep applies D^{-1} first (0: identity)
 };
@@ -42,5 +40,6 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode = 0);
 void diag_inv_scatter_launch(int n, const double* Linv, double* Li, long ldli, hipStream_t st);
 
 inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
+
 
 }  // namespace sislice

@@ -28,7 +28,7 @@ extern "C" sislice_status sislice_ldlt_solve(sislice_handle* h, int64_t n, const
     double* Zs = c.take<double>((size_t)n * kSolveMaxRhs);
     double* Vs = c.take<double>((size_t)n * kSolveMaxRhs);
     void** tab = c.take<void*>(16);
-    unsigned* sync = sync_words(h, 2 * nblk + 64);
+    unsigned* sync = sync_words(h, 64);
     // tables: LD, ipiv, perm, blk, Linv, Z, V, Y/X (filled per chunk)
     void** ht = static_cast<void**>(host_stage(h, sizeof(void*) * 16));
     ht[0] = const_cast<double*>(LD);
@@ -67,8 +67,6 @@ extern "C" sislice_status sislice_ldlt_solve(sislice_handle* h, int64_t n, const
       a.Z = reinterpret_cast<double* const*>(tab + 5);
       a.V = reinterpret_cast<double* const*>(tab + 6);
       a.ldz = n;
-      a.flags = sync + 64;
-      a.flag_stride = 2 * nblk;
       a.ctr = sync;
       solve_launch(a, h->stream);
     }
