@@ -268,7 +268,7 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   z.take<int32_t>(n);                 // ipiv
   z.take<int>(n);                     // perm
   z.take<int>(n);                     // blk
-  z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  z.take<double>(solve_linv_size(n));
   z.take<double>(n);                  // D^{-1/2}
   for (int q = 0; q < 6; ++q) z.take<double>((size_t)n * nv);  // t_prev, t_cur, t_next, X1..X3
   z.take<double>((size_t)n * (m_b + 1));  // Lanczos basis
@@ -284,7 +284,7 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   int32_t* ipB = cv.take<int32_t>(n);
   int* permB = cv.take<int>(n);
   int* blkB = cv.take<int>(n);
-  double* LinvB = cv.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+  double* LinvB = cv.take<double>(solve_linv_size(n));
   double* dsc = cv.take<double>(n);
   double* T0 = cv.take<double>((size_t)n * nv);
   double* T1 = cv.take<double>((size_t)n * nv);
@@ -545,7 +545,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   for (int s = 0; s < P; ++s) {
     z.take<int>(n);
     z.take<int>(n);
-    z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+    z.take<double>(solve_linv_size(n));
   }
   z.take<double>(64 * 8);  // norm estimation scratch
   z.take<double>((size_t)n * 8 * 2);
@@ -562,7 +562,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   for (int s = 0; s < P; ++s) {
     perm[s] = cv.take<int>(n);
     blk[s] = cv.take<int>(n);
-    Linv[s] = cv.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+    Linv[s] = cv.take<double>(solve_linv_size(n));
   }
   double* nsmall = cv.take<double>(64 * 8);
   double* nX = cv.take<double>((size_t)n * 8 * 2);

@@ -77,6 +77,58 @@ __global__ __launch_bounds__(64) void k_diag_inv_blk(int n, const double* const*
   for (int k = 0; k < SB; ++k) Linv[t + k * SB] = sX[k][t];
 }
 
+// Look-ahead blocks (per shift, after the nblk diagonal inverses):
+//   Mf_b = Linv_b L_{b,b-1}           (forward sweep, b >= 1)
+//   Mb_b = Linv_b^T L_{b+1,b}^T       (backward sweep, b <= nblk - 2)
+// so that a block's result is P_b - M_b x (previous block) with P_b formed before
+// the previous block is available.  L's structural zeros inside 2x2 pivots are
+// applied here (lval), so the sweeps read these blocks as plain matrices.
+// Layout: column-major 64x64, Mf at nblk*SB*SB, Mb at 2*nblk*SB*SB of the Linv buffer.
+__global__ __launch_bounds__(256) void k_lookahead(int n, const double* const* LDs, long ldld,
+                                                   const int* const* blks, double* const* Linvs) {
+  __shared__ double sA[SB][SB + 1];  // Linv_b(i, k)
+  __shared__ double sB[SB][SB + 1];
+  const int b = blockIdx.x, s = blockIdx.y, tid = threadIdx.x;
+  const int nblk = (n + SB - 1) / SB;
+  const double* LD = LDs[s];
+  const int* blk = blks[s];
+  double* base = Linvs[s];
+  const double* Li = base + (long)b * SB * SB;
+  const int r0 = b * SB;
+  for (int e = tid; e < SB * SB; e += 256) sA[e & 63][e >> 6] = Li[e];
+  // forward: sB[j][k] = L(r0 + j, r0 - 64 + k)
+  if (b >= 1) {
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int j = e & 63, k = e >> 6, row = r0 + j;
+      sB[j][k] = (row < n) ? lval(LD, ldld, blk, row, r0 - SB + k) : 0.0;
+    }
+    __syncthreads();
+    double* Mf = base + (long)nblk * SB * SB + (long)b * SB * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int i = e & 63, k = e >> 6;
+      double v = 0.0;
+      for (int j = 0; j <= i; ++j) v += sA[i][j] * sB[j][k];
+      Mf[e] = v;
+    }
+    __syncthreads();
+  }
+  // backward: G = L_{b+1,b} Linv_b, sB[i][j] = L(r0 + 64 + i, r0 + j); Mb = G^T
+  if (b + 1 < nblk) {
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int ii = e & 63, j = e >> 6, row = r0 + SB + ii;
+      sB[ii][j] = (row < n) ? lval(LD, ldld, blk, row, r0 + j) : 0.0;
+    }
+    __syncthreads();
+    double* Mb = base + 2L * nblk * SB * SB + (long)b * SB * SB;
+    for (int e = tid; e < SB * SB; e += 256) {
+      const int i = e & 63, k = e >> 6;  // Mb(i, k) = G(k, i) = sum_j L(k, j) Linv(j, i)
+      double v = 0.0;
+      for (int j = i; j < SB; ++j) v += sB[k][j] * sA[j][i];
+      Mb[e] = v;
+    }
+  }
+}
+
 __device__ __forceinline__ unsigned ticket(unsigned* ctr, unsigned nblk) {
   __shared__ unsigned t;
   if (threadIdx.x == 0) {
@@ -157,64 +209,64 @@ __device__ __forceinline__ int solve_shift_of(int g, int nshift) {
 
 // Forward sweep: Z = L^{-1} P Y.  256 threads; thread (i = tid % 64, q = tid / 64)
 // owns rows i of columns q, q+4, ... of the block.  The L blocks do not depend on
-// other workgroups, so the next one is prefetched into registers before the
-// flag of the current one is awaited; only the 64 x nrhs block of Z is read
-// after the hand-off.  Inside an off-diagonal block the only slot that can hold
-// D's 2x2 off-diagonal instead of L is its top-right corner (row r0, column
-// r0 - 1), which is zeroed when the column starts a 2x2 pivot.
+// other workgroups, so the next one is prefetched into registers while the
+// current result block is awaited.  The contributions of blocks 0 .. b-2 are
+// accumulated as they appear, P_b = Linv_b acc is formed before block b-1 is
+// available, and after the hand-off only Z_b = P_b - Mf_b Z_{b-1} remains.
+template <int NR>
 __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
+  constexpr int Q = SB * SB / 256;
   __shared__ double sM[SB][SB + 1];
-  __shared__ double sZ[kSolveMaxRhs][SB];
+  __shared__ double sZ[NR][SB];
   const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
-  const unsigned b = ticket(a.ctr + s, nblk);
+  const int b = (int)ticket(a.ctr + s, nblk);
   const double* LD = a.LD[s];
-  const int* blk = a.blk[s];
   const int* perm = a.perm[s];
   const double* Y = a.Y[s];
   double* Z = a.Z[s];
   const int r0 = b * SB;
   const int row = r0 + i;
   // everything that does not depend on other blocks is issued first
-  double inv[SB * SB / 256];
-  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+  double inv[Q], mf[Q];
+  const double* Lbase = a.Linv[s];
 #pragma unroll
-  for (int q = 0; q < SB * SB / 256; ++q) inv[q] = Linv[tid + 256 * q];
-  const bool corner_zero = (b > 0) && (blk[r0 - 1] == 2);
-  double acc[kSolveMaxRhs / 4];
+  for (int q = 0; q < Q; ++q) inv[q] = Lbase[(long)b * SB * SB + tid + 256 * q];
+  if (b > 0) {
 #pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    for (int q = 0; q < Q; ++q) mf[q] = Lbase[((long)nblk + b) * SB * SB + tid + 256 * q];
+  }
+  double acc[NR / 4];
+#pragma unroll
+  for (int m = 0; m < NR / 4; ++m) {
     const int c = q0 + 4 * m;
     acc[m] = (c < nrhs && row < n) ? Y[perm[row] + (long)c * a.ldy] : 0.0;
   }
   // L block (rows of this block, columns of block cb): element e -> (e & 63, e >> 6)
-  double lnext[SB * SB / 256];
+  double lnext[Q];
   auto load_L = [&](int cb) {
     const int c0 = cb * SB;
 #pragma unroll
-    for (int q = 0; q < SB * SB / 256; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       const int rr = e & 63, kk = e >> 6;
       lnext[q] = (r0 + rr < n) ? LD[r0 + rr + (long)(c0 + kk) * a.ldld] : 0.0;
     }
   };
-  if (b > 0) load_L(0);
-  for (int cb = 0; cb < (int)b; ++cb) {
-    // the corner slot (row r0, column r0 - 1) is element e = 63 * 64 of the block;
-    // its owner writes the structural zero itself
-    const bool zero_now = corner_zero && cb == (int)b - 1;
+  if (b > 1) load_L(0);
+  for (int cb = 0; cb + 1 < b; ++cb) {
 #pragma unroll
-    for (int q = 0; q < SB * SB / 256; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
+      sM[e & 63][e >> 6] = lnext[q];
     }
-    if (cb + 1 < (int)b) load_L(cb + 1);
+    if (cb + 2 < b) load_L(cb + 1);
     poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB);
 #pragma unroll
-    for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
       if (c < nrhs) {
         double t = acc[m];
@@ -225,42 +277,68 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
     }
     __syncthreads();
   }
-  // diagonal block: Z_b = Linv_b * acc
+  // P_b = Linv_b acc
 #pragma unroll
-  for (int q = 0; q < SB * SB / 256; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int e = tid + 256 * q;
     sM[e & 63][e >> 6] = inv[q];
   }
 #pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+  for (int m = 0; m < NR / 4; ++m) {
     const int c = q0 + 4 * m;
     if (c < nrhs) sZ[c][i] = acc[m];
   }
   __syncthreads();
+  double pb[NR / 4];
 #pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+  for (int m = 0; m < NR / 4; ++m) {
     const int c = q0 + 4 * m;
-    if (c < nrhs && row < n) {
-      double t = 0.0;
+    double t = 0.0;
+    if (c < nrhs)
       for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
-      st_shared_blk(Z + row + (long)c * a.ldz, t);
+    pb[m] = t;
+  }
+  if (b > 0) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      sM[e & 63][e >> 6] = mf[q];
     }
+    poll_block(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB);
+#pragma unroll
+    for (int m = 0; m < NR / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double t = pb[m];
+#pragma unroll 16
+        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
+        pb[m] = t;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NR / 4; ++m) {
+    const int c = q0 + 4 * m;
+    if (c < nrhs && row < n) st_shared_blk(Z + row + (long)c * a.ldz, pb[m]);
   }
 }
 
-// Backward sweep: X = P^T L^{-T} D^{-1} Z.  The structural zero inside an
-// off-diagonal block of L^T sits at (row c0, column c0 - 1) of L, i.e. only in
-// the block right below the diagonal (cb = b + 1), at its top-right corner.
+// Backward sweep: X = P^T L^{-T} D^{-1} Z, from the last block up, with the same
+// look-ahead: V_b = P_b - Mb_b V_{b+1}, P_b = Linv_b^T (D^{-1} Z_b - contributions
+// of blocks b+2 ..).
+template <int NR>
 __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
+  constexpr int Q = SB * SB / 256;
   __shared__ double sM[SB][SB + 1];
-  __shared__ double sV[kSolveMaxRhs][SB];
+  __shared__ double sV[NR][SB];
   const int tid = threadIdx.x;
   const int i = tid & 63, q0 = tid >> 6;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
-  const unsigned t = ticket(a.ctr + s, nblk);
-  const int b = nblk - 1 - (int)t;
+  const int t = (int)ticket(a.ctr + s, nblk);
+  const int b = nblk - 1 - t;
   const double* LD = a.LD[s];
   const int* blk = a.blk[s];
   const int* perm = a.perm[s];
@@ -269,74 +347,77 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   double* X = a.X[s];
   const int r0 = b * SB;
   const int row = r0 + i;
-  double inv[SB * SB / 256];
-  const double* Linv = a.Linv[s] + (long)b * SB * SB;
+  double inv[Q], mb[Q];
+  const double* Lbase = a.Linv[s];
 #pragma unroll
-  for (int q = 0; q < SB * SB / 256; ++q) inv[q] = Linv[tid + 256 * q];
-  const bool corner_zero = (b + 1 < nblk) && (blk[r0 + SB - 1] == 2);
-  double acc[kSolveMaxRhs / 4];
-  // D^{-1} on this block's rows
-  double d11 = 1.0, d21 = 0.0, d22 = 1.0;
-  int bt = 1, partner = row;
-  if (row < n) {
-    bt = blk[row];
-    if (bt == 2) partner = row + 1;
-    if (bt == 0) partner = row - 1;
-    if (bt == 1) {
-      d11 = LD[row + (long)row * a.ldld];
-    } else {
-      const int k = bt == 2 ? row : row - 1;
-      d11 = LD[k + (long)k * a.ldld];
-      d21 = LD[k + 1 + (long)k * a.ldld];
-      d22 = LD[k + 1 + (long)(k + 1) * a.ldld];
-    }
+  for (int q = 0; q < Q; ++q) inv[q] = Lbase[(long)b * SB * SB + tid + 256 * q];
+  if (b + 1 < nblk) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) mb[q] = Lbase[(2L * nblk + b) * SB * SB + tid + 256 * q];
   }
-#pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
-    const int c = q0 + 4 * m;
-    double v = 0.0;
-    if (c < nrhs && row < n) {
-      const double z = Z[row + (long)c * a.ldz];
-      if (!a.applyD) {
-        v = z;
-      } else if (bt == 1) {
-        v = (d11 != 0.0) ? z / d11 : 0.0;
+  double acc[NR / 4];
+  // D^{-1} on this block's rows
+  {
+    double d11 = 1.0, d21 = 0.0, d22 = 1.0;
+    int bt = 1, partner = row;
+    if (row < n) {
+      bt = blk[row];
+      if (bt == 2) partner = row + 1;
+      if (bt == 0) partner = row - 1;
+      if (bt == 1) {
+        d11 = LD[row + (long)row * a.ldld];
       } else {
-        const double zp = Z[partner + (long)c * a.ldz];
-        // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
-        const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
-        const double aa = d11 / d21, gg = d22 / d21;
-        const double tt = 1.0 / (d21 * (aa * gg - 1.0));
-        v = bt == 2 ? tt * (gg * z1 - z2) : tt * (aa * z2 - z1);
+        const int k = bt == 2 ? row : row - 1;
+        d11 = LD[k + (long)k * a.ldld];
+        d21 = LD[k + 1 + (long)k * a.ldld];
+        d22 = LD[k + 1 + (long)(k + 1) * a.ldld];
       }
     }
-    acc[m] = v;
+#pragma unroll
+    for (int m = 0; m < NR / 4; ++m) {
+      const int c = q0 + 4 * m;
+      double v = 0.0;
+      if (c < nrhs && row < n) {
+        const double z = Z[row + (long)c * a.ldz];
+        if (!a.applyD) {
+          v = z;
+        } else if (bt == 1) {
+          v = (d11 != 0.0) ? z / d11 : 0.0;
+        } else {
+          const double zp = Z[partner + (long)c * a.ldz];
+          // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
+          const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
+          const double aa = d11 / d21, gg = d22 / d21;
+          const double tt = 1.0 / (d21 * (aa * gg - 1.0));
+          v = bt == 2 ? tt * (gg * z1 - z2) : tt * (aa * z2 - z1);
+        }
+      }
+      acc[m] = v;
+    }
   }
   // L block (rows of block cb, columns of this block): element e -> (kk = e & 63, rr = e >> 6)
-  double lnext[SB * SB / 256];
+  double lnext[Q];
   auto load_L = [&](int cb) {
     const int c0 = cb * SB;
 #pragma unroll
-    for (int q = 0; q < SB * SB / 256; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       const int kk = e & 63, rr = e >> 6;
       lnext[q] = (c0 + kk < n) ? LD[c0 + kk + (long)(r0 + rr) * a.ldld] : 0.0;
     }
   };
-  if (b + 1 < nblk) load_L(nblk - 1);
-  for (int cb = nblk - 1; cb > b; --cb) {
-    // corner slot (kk = 0, rr = 63) is element e = 63 * 64, written by its owner
-    const bool zero_now = corner_zero && cb == b + 1;
+  if (b + 2 < nblk) load_L(nblk - 1);
+  for (int cb = nblk - 1; cb > b + 1; --cb) {
 #pragma unroll
-    for (int q = 0; q < SB * SB / 256; ++q) {
+    for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       // sM[kk][rr] = L(c0 + kk, r0 + rr)
-      sM[e & 63][e >> 6] = (zero_now && e == (SB - 1) * SB) ? 0.0 : lnext[q];
+      sM[e & 63][e >> 6] = lnext[q];
     }
-    if (cb - 1 > b) load_L(cb - 1);
+    if (cb - 1 > b + 1) load_L(cb - 1);
     poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB));
 #pragma unroll
-    for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+    for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
       if (c < nrhs) {
         double tt = acc[m];
@@ -347,26 +428,52 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     }
     __syncthreads();
   }
-  // V_b = Linv_b^T * acc
+  // P_b = Linv_b^T acc
 #pragma unroll
-  for (int q = 0; q < SB * SB / 256; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int e = tid + 256 * q;
     sM[e & 63][e >> 6] = inv[q];
   }
 #pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+  for (int m = 0; m < NR / 4; ++m) {
     const int c = q0 + 4 * m;
     if (c < nrhs) sV[c][i] = acc[m];
   }
   __syncthreads();
+  double pb[NR / 4];
 #pragma unroll
-  for (int m = 0; m < kSolveMaxRhs / 4; ++m) {
+  for (int m = 0; m < NR / 4; ++m) {
+    const int c = q0 + 4 * m;
+    double tt = 0.0;
+    if (c < nrhs)
+      for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
+    pb[m] = tt;
+  }
+  if (b + 1 < nblk) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      sM[e & 63][e >> 6] = mb[q];
+    }
+    poll_block(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB));
+#pragma unroll
+    for (int m = 0; m < NR / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double tt = pb[m];
+#pragma unroll 16
+        for (int k = 0; k < SB; ++k) tt -= sM[i][k] * sV[c][k];
+        pb[m] = tt;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < NR / 4; ++m) {
     const int c = q0 + 4 * m;
     if (c < nrhs && row < n) {
-      double tt = 0.0;
-      for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
-      st_shared_blk(V + row + (long)c * a.ldz, tt);
-      X[perm[row] + (long)c * a.ldx] = tt;
+      st_shared_blk(V + row + (long)c * a.ldz, pb[m]);
+      X[perm[row] + (long)c * a.ldx] = pb[m];
     }
   }
 }
@@ -397,6 +504,9 @@ void solve_prep_launch(int n, int S, const int* const* d_ipiv, int* const* d_per
   SL_LAUNCH(k_diag_inv_blk, dim3((unsigned)ceil_div(n, SB), S), dim3(64), 0, st, n, d_LD,
                      ldld, (const int* const*)d_blk, d_Linv);
   SL_LAUNCH_CHECK();
+  SL_LAUNCH(k_lookahead, dim3((unsigned)ceil_div(n, SB), S), dim3(256), 0, st, n, d_LD, ldld,
+            (const int* const*)d_blk, d_Linv);
+  SL_LAUNCH_CHECK();
 }
 
 void solve_launch(SolveArgs a, hipStream_t st, int mode) {
@@ -412,12 +522,19 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode) {
             dim3(256), 0, st, a.n, a.nrhs, a.nshift, (mode == 0 || mode == 1) ? a.Z : nullptr,
             (mode == 0 || mode == 2) ? a.V : nullptr, a.ldz);
   SL_LAUNCH_CHECK();
+  const bool small = a.nrhs <= 8;
   if (mode == 0 || mode == 1) {
-    SL_LAUNCH(k_fwd, dim3(grid), dim3(256), 0, st, a);
+    if (small)
+      SL_LAUNCH(k_fwd<8>, dim3(grid), dim3(256), 0, st, a);
+    else
+      SL_LAUNCH(k_fwd<kSolveMaxRhs>, dim3(grid), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   if (mode == 0 || mode == 2) {
-    SL_LAUNCH(k_bwd, dim3(grid), dim3(256), 0, st, a);
+    if (small)
+      SL_LAUNCH(k_bwd<8>, dim3(grid), dim3(256), 0, st, a);
+    else
+      SL_LAUNCH(k_bwd<kSolveMaxRhs>, dim3(grid), dim3(256), 0, st, a);
     SL_LAUNCH_CHECK();
   }
   prof_end(ph, tk);

@@ -15,7 +15,7 @@ struct SolveArgs {
   long ldld = 0;
   const int* const* perm = nullptr;
   const int* const* blk = nullptr;
-  const double* const* Linv = nullptr;  // nblk * 64 * 64 per shift
+  const double* const* Linv = nullptr;  // solve_linv_size(n) doubles per shift (solve_prep_launch)
   const double* const* Y = nullptr;     // input  n x nrhs (ldy)
   long ldy = 0;
   double* const* X = nullptr;           // output n x nrhs (ldx); may alias Y
@@ -40,6 +40,11 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode = 0);
 void diag_inv_scatter_launch(int n, const double* Linv, double* Li, long ldli, hipStream_t st);
 
 inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
+// per shift: the 64x64 diagonal-block inverses of L, then the forward and the
+// backward look-ahead blocks (3 * nblk column-major 64x64 blocks)
+inline size_t solve_linv_size(long n) {
+  return 3 * (size_t)solve_nblk(n) * kSolveBlock * kSolveBlock;
+}
 
 
 }  // namespace sislice

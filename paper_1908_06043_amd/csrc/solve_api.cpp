@@ -17,14 +17,14 @@ extern "C" sislice_status sislice_ldlt_solve(sislice_handle* h, int64_t n, const
     Sizer z;
     z.take<int>(n);
     z.take<int>(n);
-    z.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+    z.take<double>(solve_linv_size(n));
     z.take<double>((size_t)n * kSolveMaxRhs);
     z.take<double>((size_t)n * kSolveMaxRhs);
     z.take<void*>(16);
     Carver c(ws_get(h, kBufSolve, z.off));
     int* perm = c.take<int>(n);
     int* blk = c.take<int>(n);
-    double* Linv = c.take<double>((size_t)nblk * kSolveBlock * kSolveBlock);
+    double* Linv = c.take<double>(solve_linv_size(n));
     double* Zs = c.take<double>((size_t)n * kSolveMaxRhs);
     double* Vs = c.take<double>((size_t)n * kSolveMaxRhs);
     void** tab = c.take<void*>(16);
