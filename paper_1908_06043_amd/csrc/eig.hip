@@ -54,10 +54,42 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
   }
   __syncthreads();
   const int ntask_blk = h * (h + 1) / 2;
+  // Each thread's tasks are the same in every round: decode them once.
+  //   A: 2x2 block tasks t = tid + 1024 j -> pair indices (k >= l)
+  //   V: column-pair tasks t = tid + 1024 j -> (row i, pair k)
+  constexpr int JA = 2, JV = 7;  // enough for m <= kEigMax (h <= 56)
+  int tk[JA], tl[JA], vi[JV], vk[JV];
+#pragma unroll
+  for (int j = 0; j < JA; ++j) {
+    const int t = tid + 1024 * j;
+    int k = -1, l = 0;
+    if (t < ntask_blk) {
+      k = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (k * (k + 1) / 2 > t) --k;
+      while ((k + 1) * (k + 2) / 2 <= t) ++k;
+      l = t - k * (k + 1) / 2;
+    }
+    tk[j] = k;
+    tl[j] = l;
+  }
+#pragma unroll
+  for (int j = 0; j < JV; ++j) {
+    const int t = tid + 1024 * j;
+    vi[j] = (t < m * h) ? t % m : -1;
+    vk[j] = (t < m * h) ? t / m : 0;
+  }
+  // flag[0]: a rotation happened in this sweep; rflag[r & 1]: in round r (the slot
+  // of the next round is cleared by thread 0 while the current one is being set)
+  int* rflag = flag + 2;
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
-    if (tid == 0) flag[0] = 0;
+    if (tid == 0) {
+      flag[0] = 0;
+      rflag[0] = 0;
+      rflag[1] = 0;
+    }
     __syncthreads();
     for (int r = 0; r < M - 1; ++r) {
+      if (tid == 0) rflag[(r + 1) & 1] = 0;
       if (tid < h) {
         int p = rr_player(tid, r, M), q = rr_player(M - 1 - tid, r, M);
         if (p > q) {
@@ -76,6 +108,7 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
             c = 1.0 / sqrt(1.0 + t * t);
             s = t * c;
             flag[0] = 1;
+            rflag[r & 1] = 1;
           }
         }
         pp[tid] = p;
@@ -84,12 +117,12 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
         sn[tid] = s;
       }
       __syncthreads();
+      if (rflag[r & 1] == 0) continue;  // no rotation in this round: A and V unchanged
       // A <- J^T A J as independent 2x2 blocks of pair pairs (k >= l)
-      for (int t = tid; t < ntask_blk; t += blockDim.x) {
-        int k = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while (k * (k + 1) / 2 > t) --k;
-        while ((k + 1) * (k + 2) / 2 <= t) ++k;
-        const int l = t - k * (k + 1) / 2;
+#pragma unroll
+      for (int j = 0; j < JA; ++j) {
+        const int k = tk[j], l = tl[j];
+        if (k < 0) continue;
         const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
         if (sk == 0.0 && sl == 0.0) continue;
         const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
@@ -120,8 +153,10 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
         }
       }
       // V <- V J
-      for (int t = tid; t < m * h; t += blockDim.x) {
-        const int i = t % m, k = t / m;
+#pragma unroll
+      for (int j = 0; j < JV; ++j) {
+        const int i = vi[j], k = vk[j];
+        if (i < 0) continue;
         const double c = cs[k], s = sn[k];
         if (s == 0.0) continue;
         const int p = pp[k], q = qq[k];
