@@ -89,6 +89,9 @@ typedef struct {
   double t_kern_ms[6];
   int64_t n_kern[6];
   double flops_update;
+  /* Algorithmic bytes of the triangular sweeps: 8 n^2 per shift and
+   * forward/backward pair (the packed L read once per direction). */
+  double bytes_solve;
 } sislice_report;
 
 void sislice_default_opts(sislice_opts *opts);

@@ -33,7 +33,8 @@ class Report(C.Structure):
                 ("t_rr_ms", C.c_double), ("t_host_ms", C.c_double), ("t_total_ms", C.c_double),
                 ("flops_factor", C.c_double), ("nu", c_int64_p), ("slice_case", c_int32_p),
                 ("slice_exact", c_int32_p), ("slice_cand", c_int32_p),
-                ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double)]
+                ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double),
+                ("bytes_solve", C.c_double)]
 
 
 _SIGS = {

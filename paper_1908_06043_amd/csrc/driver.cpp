@@ -798,6 +798,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     return cnt >= n_exact[s];
   };
   int block_steps = 0, cycles_max = 0;
+  double bytes_solve = 0.0;
   const double lock_tol = o.tol / 100.0;
   for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
     std::vector<int> act;
@@ -833,6 +834,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       sa.ldz = n;
       sa.ctr = sync;
       solve_launch(sa, st, 0);
+      bytes_solve += 8.0 * (double)n * (double)n * na;
       // b. full B-reorthogonalisation, twice; T's new column block from the projections
       const auto vb = std::vector<int>(na, b);
       const auto vn = std::vector<int>(na, n);
@@ -1245,6 +1247,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       }
     }
     rep->flops_update = fl;
+    rep->bytes_solve = bytes_solve;
   }
   prof_reset(h);
   h->prof = false;

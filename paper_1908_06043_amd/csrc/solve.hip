@@ -163,9 +163,17 @@ __device__ __forceinline__ bool is_sentinel(double v) {
 }
 
 // sX[c][rr] = block rows rr < rows of column c of B (ld ldb), once none is the
-// sentinel; rows past `rows` read as zero.
+// sentinel; rows past `rows` read as zero.  One lane waits on a single element
+// first (the last one of the block), so the waiting workgroups do not stream the
+// whole block from the coherence point on every poll; the block is then loaded
+// and checked in full (other lanes' stores may still be on their way).
 __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, long ldb, int nrhs,
                                            int rows) {
+  if (threadIdx.x == 0) {
+    const double* last = B + (rows - 1) + (long)(nrhs - 1) * ldb;
+    while (is_sentinel(ld_shared_blk(last))) __builtin_amdgcn_s_sleep(1);
+  }
+  __syncthreads();
   for (;;) {
     int ok = 1;
     for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
