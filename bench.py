@@ -33,6 +33,28 @@ PEAK_HBM = 8000.0     # GB/s, MI355X HBM3E
 KCLASS = ["bk_panel", "trailing_update_mfma", "triangular_solve", "gemm", "projected_eig", "other"]
 
 
+def measured_traffic(kernel_class):
+    """HBM bytes per launch of `kernel_class` from the committed counter summary
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a copy kernel of known size), or None
+    when no summary exists or the kernel's source has changed since it was taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*counters*.txt"))):
+        for line in open(path):
+            line = line.strip()
+            if not line.startswith("{"):
+                continue
+            rec = json.loads(line)
+            if rec.get("kernel_class") != kernel_class:
+                continue
+            src = os.path.join(ROOT, rec["source"])
+            if not os.path.exists(src):
+                return None
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            return rec["traffic_bytes_per_launch"] if sha == rec.get("source_sha256") else None
+    return None
+
+
 def cpu_baseline(P, sigmas, n_e, n_s, steps_budget=256):
     """Time the oracle's Bunch-Kaufman on the first `steps_budget` pivot columns of
     one shifted matrix of the workload and extrapolate by flop count to the
@@ -147,6 +169,7 @@ def main():
         roof = {"bound": "mfma", "achieved": None, "peak": PEAK_FP64, "unit": "TFLOP/s",
                 "frac": None, "traffic": None}
     roof["kernel"] = KCLASS[dom]
+    roof["traffic"] = measured_traffic(KCLASS[dom])
     roof["kernel_ms_per_step"] = {KCLASS[q]: round(float(tk[q]) / args.steps, 3) for q in range(6)}
     roof["launches_per_step"] = {KCLASS[q]: int(nk[q]) // args.steps for q in range(6)}
     factor_tf = float(np.mean([r["flops_factor"] / (r["t_factor_ms"] * 1e-3) / 1e12 for r in reps]))
