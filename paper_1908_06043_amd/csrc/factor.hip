@@ -656,32 +656,48 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
         const int i = min(ri[x], n - 1), j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
         acc[x][y][r] = LD[i + (long)j * ldld];
       }
-  double lop[2][KS], wop[2][KS];
+  // operands in chunks of 4 k-steps, double-buffered: the loads of chunk c + 1 are
+  // in flight while chunk c feeds the MFMAs (registers stay low enough for several
+  // resident wavefronts per SIMD)
+  constexpr int CK = 4;
+  const int nch = (nks + CK - 1) / CK;
+  double lop[2][CK][2], wop[2][CK][2];
+  auto load_chunk = [&](int ch, double (&lb)[CK][2], double (&wb)[CK][2]) {
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    if (ks < nks) {
-      const int k = 4 * ks + lk;
+    for (int u = 0; u < CK; ++u) {
+      const int k = 4 * (CK * ch + u) + lk;
       const bool kv = k < kb;
       const int kc = kv ? k : 0;
 #pragma unroll
       for (int x = 0; x < 2; ++x) {
         const double v = LD[min(ri[x], n - 1) + (long)(k0 + kc) * ldld];
-        lop[x][ks] = kv ? v : 0.0;
+        lb[u][x] = kv ? v : 0.0;
       }
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
         const double v = Wp[min(cj[y], n - 1) + (long)kc * ldw];
-        wop[y][ks] = kv ? -v : 0.0;
+        wb[u][y] = kv ? -v : 0.0;
       }
     }
-  }
+  };
+  auto mfma_chunk = [&](const double (&lb)[CK][2], const double (&wb)[CK][2]) {
 #pragma unroll
-  for (int ks = 0; ks < KS; ++ks) {
-    if (ks < nks) {
+    for (int u = 0; u < CK; ++u)
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(wop[y][ks], lop[x][ks], acc[x][y]);
+        for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(wb[u][y], lb[u][x], acc[x][y]);
+  };
+  load_chunk(0, lop[0], wop[0]);
+#pragma unroll
+  for (int ch = 0; ch < KS / CK; ch += 2) {
+    if (ch < nch) {
+      if (ch + 1 < nch) load_chunk(ch + 1, lop[1], wop[1]);
+      mfma_chunk(lop[0], wop[0]);
+    }
+    if (ch + 1 < nch) {
+      if (ch + 2 < nch) load_chunk(ch + 2, lop[0], wop[0]);
+      mfma_chunk(lop[1], wop[1]);
     }
   }
 #pragma unroll

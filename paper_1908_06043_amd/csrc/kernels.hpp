@@ -35,7 +35,7 @@ struct FactorPlan {
   double* const* d_Lp = nullptr;
   double* const* d_aux = nullptr;  // [nb] D | [nb] max|w| in block | [nb] max|w| below (uint64 bits) | nb*nb Linv
   int fast = 1;                    // use the pivot-free path
-  int nbpiv = 16;                  // columns a pivoting panel handles after a rejection
+  int nbpiv = 32;                  // columns a pivoting panel handles after a rejection
 };
 
 void factor_launch(const FactorPlan& fp, hipStream_t st);
