@@ -22,7 +22,11 @@ in the paper's order and notation, sharing no code with the HIP library:
                   (Section 3.2);
 * ``prng``     -- SplitMix64, the counter-based generator both sides implement;
 * ``sislice``  -- the per-pencil driver: factor every shift, run Algorithm 2 per
-                  probe until its window converges, validate, return the lowest n_e.
+                  probe until its window converges, validate, return the lowest n_e;
+* ``adjoint``  -- gradients of a loss of the lowest eigenpairs with respect to A
+                  and B (first-order perturbation theory of the pencil of Section 1;
+                  not a step of the paper): the sum-over-states definition and the
+                  projected-solve form.
 
 Parity pins for every function live in ``tests/test_oracle_*.py``.  The KPM
 moments of a non-diagonal operator are a stochastic estimate: beyond the

@@ -214,3 +214,29 @@ def safe_shifts(lam, sigmas, rel_gap=1e-6, norm=None):
                 s = hi + 2 * tol
         out.append(s)
     return np.array(out)
+
+
+def pencil_adjoint(n=2048, n_e=200, seed=0, gap=0.05) -> Pencil:
+    """Adjoint workload: the SCF-shaped spectrum with lam_{n_e+1} - lam_{n_e} >= gap, so
+    that the occupied subspace (the lowest n_e) is separated from the rest."""
+    return make_pencil(n, lambda r, m: spectrum_scf(r, m, n_e, forced_gap_at=n_e, forced_gap=gap),
+                       seed, meta=dict(workload="adjoint", n_e=n_e, gap=gap))
+
+
+def sym_gaussian(n, seed):
+    """W = (G + G^T) / sqrt(2) with G ~ N(0, 1) entries (the density-matrix weight)."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, n))
+    return np.ascontiguousarray((g + g.T) / np.sqrt(2.0))
+
+
+def sym_directions(n, k, seed):
+    """k symmetric perturbation directions with N(0, 1) entries, each scaled to unit
+    Frobenius norm (finite-difference checks of gradients); shape (k, n, n)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((k, n, n))
+    for t in range(k):
+        g = rng.standard_normal((n, n))
+        e = 0.5 * (g + g.T)
+        out[t] = e / np.linalg.norm(e)
+    return out
