@@ -92,7 +92,24 @@ typedef struct {
   /* Algorithmic bytes of the triangular sweeps: 8 n^2 per shift and
    * forward/backward pair (the packed L read once per direction). */
   double bytes_solve;
+  /* Identifies the factorizations of this solve, which the handle keeps until
+   * its next sislice_solve or sislice_adjoint (pass to sislice_adjoint). */
+  uint64_t factor_id;
 } sislice_report;
+
+/* Report of sislice_adjoint, host memory owned by the caller. */
+typedef struct {
+  int32_t iterations;        /* conjugate-gradient iterations (all columns together)  */
+  int32_t reused_factors;    /* 1: the solve's factorizations were reused             */
+  int32_t n_groups;          /* groups of at most 8 columns sharing one factorization */
+  int32_t breakdowns;        /* columns stopped by a non-positive curvature p^T K p   */
+  double max_rel_residual;   /* max_i ||r_i|| / ||b_i|| of the projected solves        */
+  double t_factor_ms;        /* refactorization (0 when reused)                       */
+  double t_solve_ms;         /* preconditioned conjugate gradients                    */
+  double t_total_ms;
+  double flops_outer;        /* algorithmic flops of the two rank-2k outputs: 4 n^2 n_e */
+  double t_outer_ms;         /* device time of the fused rank-2k output kernel         */
+} sislice_adjoint_report;
 
 void sislice_default_opts(sislice_opts *opts);
 const char *sislice_status_string(sislice_status s);
@@ -170,6 +187,49 @@ sislice_status sislice_solve(sislice_handle *h, int64_t n, const double *A, int6
                              const double *sigmas, double *omega_top, const sislice_opts *opts,
                              double *evals, double *evecs, int64_t ldx, double *resid,
                              sislice_report *report);
+
+/* Reverse-mode derivative of the eigenpairs that sislice_solve returns (the
+ * lowest n_e of the pencil of Sec. 1).  The paper does not differentiate them;
+ * this is first-order perturbation theory of the symmetric-definite problem.
+ * For a loss L with cotangents g_evals = dL/dlambda and g_evecs = dL/dX it
+ * writes symmetric G_A, G_B with dL = tr(G_A dA) + tr(G_B dB) for symmetric
+ * dA, dB:
+ *   G_A = X M_A X^T + (Z X^T + X Z^T) / 2
+ *   G_B = X M_B X^T - (Z Lam X^T + X Lam Z^T) / 2
+ * where K = X^T g_evecs, S and T are its symmetric and antisymmetric parts,
+ * F_ji = 1 / (lambda_i - lambda_j) off the diagonal,
+ *   M_A = diag(g_evals) + T o F
+ *   M_B = -diag(lambda g_evals) - S / 2 - (lambda_i + lambda_j) (T o F) / 2,
+ * and column z_i of Z solves (A - lambda_i B) z_i = -(I - B X X^T) g_i with
+ * X^T B z_i = 0.  Those solves run as conjugate gradients on the B-orthogonal
+ * complement of X (where A - lambda_i B is positive definite), preconditioned
+ * by (A - sigma B)^{-1} for the point sigma nearest lambda_i among those shifts
+ * and top boundary that lie below lambda_{n_e+1} (inertia <= n_e: positive
+ * definite there).  The factorizations are the ones that the last sislice_solve
+ * on this handle left behind when factor_id matches them, else they are
+ * computed again.  Pairs with |lambda_i - lambda_j| <= 64 eps max|lambda| drop
+ * their T o F terms: a loss of the eigenvectors of a degenerate eigenvalue must
+ * be invariant under rotations inside it.
+ *   evals, evecs     device: the eigenpairs (n_e, and n x n_e with ldx >= n).
+ *   g_evals          device double[n_e], or NULL for zero.
+ *   g_evecs          device n x n_e (ldg >= n), or NULL for zero (then Z = 0).
+ *   sigmas, omega_top host: the shifts (n_s, ascending) and top boundary of that
+ *                    solve; at least one point must have inertia <= n_e
+ *                    (SISLICE_ERR_ARG otherwise).
+ *   factor_id        sislice_report.factor_id of that solve, or 0.
+ *   tol, max_iter    relative residual target of the solves (<= 0: 1e-11) and
+ *                    iteration cap (<= 0: 500).
+ *   GA, GB           device n x n out (ldga, ldgb >= n), both triangles written.
+ *   report           host, may be NULL.
+ * Returns SISLICE_NOT_CONVERGED when a solve misses tol within max_iter (the
+ * gradients are still written).  Synchronises. */
+sislice_status sislice_adjoint(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, int64_t n_e, const double *evals,
+                               const double *evecs, int64_t ldx, const double *g_evals,
+                               const double *g_evecs, int64_t ldg, int64_t n_s,
+                               const double *sigmas, double omega_top, uint64_t factor_id,
+                               double tol, int32_t max_iter, double *GA, int64_t ldga, double *GB,
+                               int64_t ldgb, sislice_adjoint_report *report);
 
 /* Shift migration by k-means (Sec. 3.2), host only: Lloyd iterations on the 1-D
  * set `ritz` (host double[n]) from the initial centroids `prev_shifts` (host

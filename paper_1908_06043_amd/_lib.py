@@ -34,7 +34,14 @@ class Report(C.Structure):
                 ("flops_factor", C.c_double), ("nu", c_int64_p), ("slice_case", c_int32_p),
                 ("slice_exact", c_int32_p), ("slice_cand", c_int32_p),
                 ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double),
-                ("bytes_solve", C.c_double)]
+                ("bytes_solve", C.c_double), ("factor_id", C.c_uint64)]
+
+
+class AdjointReport(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("reused_factors", C.c_int32), ("n_groups", C.c_int32),
+                ("breakdowns", C.c_int32), ("max_rel_residual", C.c_double),
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("flops_outer", C.c_double), ("t_outer_ms", C.c_double)]
 
 
 _SIGS = {
@@ -59,6 +66,11 @@ _SIGS = {
                                 C.c_int64, C.c_int64, C.c_int64, c_double_p, c_double_p,
                                 C.POINTER(Opts), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                 C.POINTER(Report)]),
+    "sislice_adjoint": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
+                                  C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, c_double_p,
+                                  C.c_double, C.c_uint64, C.c_double, C.c_int32, C.c_void_p,
+                                  C.c_int64, C.c_void_p, C.c_int64, C.POINTER(AdjointReport)]),
     "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
                                         C.c_uint64, c_double_p, c_int32_p]),
     "sislice_validate": (C.c_int64, [C.c_int64, c_double_p, c_int64_p, C.c_double, C.c_int64,

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import Opts, Report, SisliceError
+from ._lib import AdjointReport, Opts, Report, SisliceError
 
 _handles = {}
 
@@ -191,7 +191,78 @@ def solve(A, B, n_e, n_s, sigmas=None, omega_top=None, opts=None, check=True):
     report["t_kern_ms"] = list(rep.t_kern_ms)
     report["n_kern"] = list(rep.n_kern)
     report.update(nu=nu, slice_case=sc, slice_exact=se, slice_cand=sd)
-    return dict(evals=ev, evecs=Xt.t(), resid=rs, status=st, omega_top=top.value, report=report)
+    return dict(evals=ev, evecs=Xt.t(), resid=rs, status=st, omega_top=top.value, report=report,
+                sigmas=sig)
+
+
+def adjoint(A, B, evals, evecs, g_evals, g_evecs, sigmas, omega_top, factor_id=0, tol=0.0,
+            max_iter=0, check=True):
+    """Symmetric gradients (G_A, G_B) of a loss with cotangents g_evals (n_e,) and
+    g_evecs (n, n_e) of the eigenpairs (evals, evecs) returned by ``solve`` (either
+    cotangent may be None).  Returns (G_A, G_B, report)."""
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n = A.shape[0]
+    n_e = int(evals.shape[0])
+    Xt = evecs.t().contiguous()                        # column-major n x n_e
+    ge = g_evals.contiguous() if g_evals is not None else None
+    gXt = g_evecs.t().contiguous() if g_evecs is not None else None
+    sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
+    GA = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    GB = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    rep = AdjointReport()
+    lib = _lib.load()
+    st = lib.sislice_adjoint(handle(A.device.index), n, A.data_ptr(), n, B.data_ptr(), n, n_e,
+                             evals.contiguous().data_ptr(), Xt.data_ptr(), n,
+                             ge.data_ptr() if ge is not None else None,
+                             gXt.data_ptr() if gXt is not None else None, n, sig.size,
+                             sig.ctypes.data_as(_lib.c_double_p), float(omega_top), int(factor_id),
+                             float(tol), int(max_iter), GA.data_ptr(), n, GB.data_ptr(), n,
+                             C.byref(rep))
+    if check:
+        _check(st, "sislice_adjoint")
+    report = {f: getattr(rep, f) for f, _ in AdjointReport._fields_}
+    report["status"] = st
+    return GA, GB, report
+
+
+class _PencilEig(torch.autograd.Function):
+    """Lowest n_e eigenpairs of (A, B) with the library's adjoint as backward."""
+
+    @staticmethod
+    def forward(ctx, A, B, n_e, n_s, sigmas, omega_top, opts, adj_tol):
+        out = solve(A.detach(), B.detach(), n_e, n_s, sigmas, omega_top, opts)
+        evals = out["evals"]
+        evecs = out["evecs"].contiguous()
+        ctx.save_for_backward(A, B, evals, evecs)
+        ctx.meta = (np.asarray(sigmas, dtype=np.float64), float(out["omega_top"]),
+                    int(out["report"]["factor_id"]), adj_tol)
+        return evals, evecs
+
+    @staticmethod
+    def backward(ctx, g_evals, g_evecs):
+        A, B, evals, evecs = ctx.saved_tensors
+        sig, top, fid, tol = ctx.meta
+        GA, GB, rep = adjoint(A.detach(), B.detach(), evals, evecs, g_evals, g_evecs, sig, top,
+                              fid, tol)
+        global last_adjoint_report
+        last_adjoint_report = rep
+        return GA, GB, None, None, None, None, None, None
+
+
+last_adjoint_report = None
+
+
+def eigh_pencil(A, B, n_e, n_s, sigmas=None, omega_top=None, opts=None, adj_tol=0.0):
+    """Differentiable lowest n_e eigenpairs (evals (n_e,), evecs (n, n_e)) of the
+    symmetric-definite pencil (A, B).  Gradients w.r.t. A and B come back in the
+    symmetric convention (dL = tr(G_A dA) + tr(G_B dB) for symmetric dA, dB).
+    Shifts are planned with the KPM estimator when not given (the plan itself is
+    piecewise constant and not differentiated)."""
+    if sigmas is None:
+        plan = plan_shifts_kpm(A.detach(), B.detach(), n_e, n_s, opts)
+        sigmas, omega_top = plan["sigmas"], plan["omega_top"]
+    return _PencilEig.apply(A, B, n_e, n_s, sigmas, omega_top, opts, adj_tol)
 
 
 # ----------------------------------------------------------- host-only helpers

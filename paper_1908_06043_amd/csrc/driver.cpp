@@ -28,154 +28,11 @@
 #include "handle.hpp"
 #include "lanczos.hpp"
 #include "planner.hpp"
+#include "driver_util.hpp"
 #include "solve.hpp"
 
 namespace sislice {
 namespace {
-
-using Clock = std::chrono::steady_clock;
-double ms_since(Clock::time_point t0) {
-  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
-}
-
-// Pinned host ring + device ring for the small per-launch tables.  put() only
-// stages a table in the host ring; the tables staged since the last launch go
-// to the device in one copy, issued by the launch macro just before the next
-// kernel (stream order then delivers them first).  The host bytes stay untouched
-// until the stream has passed that copy: the ring is rewound only after a
-// stream synchronisation.
-class Ring {
- public:
-  explicit Ring(sislice_handle* h, size_t cap = 16u << 20) : h_(h), cap_(cap) {
-    if (h->ring_cap < cap) {
-      if (h->ring_host) {
-        SL_HIP(hipStreamSynchronize(h->stream));
-        SL_HIP(hipHostFree(h->ring_host));
-        h->ring_host = nullptr;
-        h->ring_cap = 0;
-      }
-      SL_HIP(hipHostMalloc(&h->ring_host, cap, hipHostMallocDefault));
-      h->ring_cap = cap;
-    }
-    host_ = static_cast<char*>(h->ring_host);
-    dev_ = static_cast<char*>(ws_get(h, kBufRing, cap));
-    h->flush_fn = &Ring::flush_thunk;
-    h->flush_ctx = this;
-  }
-  ~Ring() {
-    if (h_->flush_ctx == this) {
-      try {
-        flush();
-      } catch (...) {
-      }
-      h_->flush_fn = nullptr;
-      h_->flush_ctx = nullptr;
-    }
-  }
-  Ring(const Ring&) = delete;
-  Ring& operator=(const Ring&) = delete;
-  void* put(const void* src, size_t bytes) {
-    if (bytes == 0) bytes = 8;
-    const size_t b = (bytes + 255) & ~size_t(255);
-    SL_CHECK_ARG(b <= cap_, "table too large for the upload ring");
-    if (off_ + b > cap_) {
-      flush();
-      SL_HIP(hipStreamSynchronize(h_->stream));
-      off_ = pend_ = 0;
-    }
-    if (src)
-      std::memcpy(host_ + off_, src, bytes);
-    else
-      std::memset(host_ + off_, 0, bytes);
-    void* r = dev_ + off_;
-    off_ += b;
-    return r;
-  }
-  void flush() {
-    if (off_ > pend_) {
-      SL_HIP(hipMemcpyAsync(dev_ + pend_, host_ + pend_, off_ - pend_, hipMemcpyHostToDevice,
-                            h_->stream));
-      pend_ = off_;
-    }
-  }
-  template <class T>
-  T* vec(const std::vector<T>& v) {
-    return static_cast<T*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T)));
-  }
-  template <class T>
-  T* const* ptrs(const std::vector<T*>& v) {
-    return reinterpret_cast<T* const*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
-  }
-  template <class T>
-  const T* const* cptrs(const std::vector<T*>& v) {
-    return reinterpret_cast<const T* const*>(
-        put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
-  }
-  // caller has synchronised the stream: every uploaded table has been consumed;
-  // tables still staged are uploaded (and waited for) before the ring rewinds
-  void synced() {
-    if (off_ > pend_) {
-      flush();
-      SL_HIP(hipStreamSynchronize(h_->stream));
-    }
-    off_ = pend_ = 0;
-  }
-
- private:
-  static void flush_thunk(void* self) { static_cast<Ring*>(self)->flush(); }
-  sislice_handle* h_;
-  size_t cap_;
-  char* host_;
-  char* dev_;
-  size_t off_ = 0;
-  size_t pend_ = 0;
-};
-
-struct Ctx {
-  sislice_handle* h;
-  hipStream_t st;
-  Ring* ring;
-};
-
-// Batched GEMM helper: per-batch sizes, pointer tables through the ring,
-// split-K (ordered partials) when the reduction is long and the output small.
-void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std::vector<int>& nn,
-          const std::vector<int>& k, const std::vector<const double*>& A, long lda,
-          const std::vector<const double*>& B, long ldb, const std::vector<double*>& C, long ldc,
-          double alpha, double beta) {
-  const int batch = (int)m.size();
-  if (batch == 0) return;
-  int mmax = 0, nmax = 0, kmax = 0;
-  for (int b = 0; b < batch; ++b) {
-    mmax = std::max(mmax, m[b]);
-    nmax = std::max(nmax, nn[b]);
-    kmax = std::max(kmax, k[b]);
-  }
-  if (mmax == 0 || nmax == 0) return;
-  GemmArgs g;
-  g.m = c.ring->vec(m);
-  g.n = c.ring->vec(nn);
-  g.k = c.ring->vec(k);
-  g.A = c.ring->cptrs(A);
-  g.lda = lda;
-  g.B = c.ring->cptrs(B);
-  g.ldb = ldb;
-  g.C = c.ring->ptrs(C);
-  g.ldc = ldc;
-  g.alpha = alpha;
-  g.beta = beta;
-  int splits = 1;
-  const long tiles = ceil_div(mmax, 64) * ceil_div(nmax, 64) * (long)batch;
-  if (kmax >= 1024 && tiles < 512) {
-    splits = (int)std::min<long>(std::max<long>(1, 1024 / tiles), kmax / 256);
-    splits = std::max(1, std::min(splits, 64));
-  }
-  g.splits = splits;
-  if (splits > 1)
-    g.partial = static_cast<double*>(
-        ws_get(c.h, kBufMisc, sizeof(double) * (size_t)batch * splits * mmax * nmax));
-  gemm_launch(g, batch, mmax, nmax, ta, tb, c.st);
-}
 
 struct ProbeHost {
   double sigma = 0, lo = 0, hi = 0;
@@ -257,7 +114,6 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   hipStream_t st = h->stream;
   Ring ring(h);
   Ctx c{h, st, &ring};
-  const long nblk = solve_nblk(n);
   const int m_b = std::min(bs, n);  // Lanczos steps for the bounds
   // workspace
   Sizer z;
@@ -506,6 +362,75 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
 
 // ---------------------------------------------------------------- solve
 
+DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, long lda,
+                       const double* B, long ldb, const std::vector<double>& pts, int nb) {
+  hipStream_t st = h->stream;
+  const int S1 = (int)pts.size();
+  Sizer z;
+  z.take<double>((size_t)2 * n * n);  // [Af Bf], n x 2n
+  for (int s = 0; s < S1; ++s) z.take<double>((size_t)n * n);
+  for (int s = 0; s < S1; ++s) z.take<int32_t>(n);
+  for (int s = 0; s < S1; ++s) {
+    z.take<int>(n);
+    z.take<int>(n);
+    z.take<double>(solve_linv_size(n));
+  }
+  z.take<double>(64 * 8);  // norm estimation scratch
+  z.take<double>((size_t)n * 8 * 2);
+  z.take<int>(64);
+  h->fc.id = 0;  // the driver workspace is about to be overwritten
+  Carver cv(ws_get(h, kBufDriver, z.off));
+  DriverWs w;
+  w.Af = cv.take<double>((size_t)2 * n * n);
+  w.Bf = w.Af + (size_t)n * n;
+  w.LD.resize(S1);
+  w.ipv.resize(S1);
+  for (int s = 0; s < S1; ++s) w.LD[s] = cv.take<double>((size_t)n * n);
+  for (int s = 0; s < S1; ++s) w.ipv[s] = cv.take<int32_t>(n);
+  w.perm.resize(S1);
+  w.blk.resize(S1);
+  w.Linv.resize(S1);
+  for (int s = 0; s < S1; ++s) {
+    w.perm[s] = cv.take<int>(n);
+    w.blk[s] = cv.take<int>(n);
+    w.Linv[s] = cv.take<double>(solve_linv_size(n));
+  }
+  w.nsmall = cv.take<double>(64 * 8);
+  w.nX = cv.take<double>((size_t)n * 8 * 2);
+  w.nflag = cv.take<int>(64);
+  sym_full_launch(n, A, lda, w.Af, n, st);
+  sym_full_launch(n, B, ldb, w.Bf, n, st);
+  w.fp = build_factor(h, kBufFactor, n, A, lda, B, ldb, S1, pts.data(), w.LD.data(), n, w.ipv.data(),
+                      nb, true);
+  factor_launch(w.fp, st);
+  w.inert.assign(3 * S1, 0);
+  SL_HIP(hipMemcpyAsync(w.inert.data(), w.fp.d_inertia, sizeof(int64_t) * 3 * S1,
+                        hipMemcpyDeviceToHost, st));
+  SL_HIP(hipStreamSynchronize(st));
+  ring.synced();
+  for (int s = 0; s < S1; ++s)
+    if (w.inert[3 * s + 1] != 0) return w;  // singular: nothing is cached
+  // the factorizations stay in the driver workspace for sislice_adjoint
+  auto& f = h->fc;
+  f.id = ++h->fc_counter;
+  f.n = n;
+  f.A = A;
+  f.B = B;
+  f.lda = lda;
+  f.ldb = ldb;
+  f.Af = w.Af;
+  f.pts = pts;
+  f.LD = w.LD;
+  f.ipv = w.ipv;
+  f.perm = w.perm;
+  f.blk = w.blk;
+  f.Linv = w.Linv;
+  f.inertia = w.inert;
+  f.prepped.assign(S1, 0);
+  return w;
+}
+
+
 sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                           const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
@@ -535,61 +460,32 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   Ring ring(h);
   Ctx c{h, st, &ring};
   const int S1 = P + 1;  // shifts + top boundary
-  const long nblk = solve_nblk(n);
-  // ---- factor-phase workspace
-  Sizer z;
-  z.take<double>((size_t)n * n);  // Af
-  z.take<double>((size_t)n * n);  // Bf
-  for (int s = 0; s < S1; ++s) z.take<double>((size_t)n * n);
-  for (int s = 0; s < S1; ++s) z.take<int32_t>(n);
-  for (int s = 0; s < P; ++s) {
-    z.take<int>(n);
-    z.take<int>(n);
-    z.take<double>(solve_linv_size(n));
-  }
-  z.take<double>(64 * 8);  // norm estimation scratch
-  z.take<double>((size_t)n * 8 * 2);
-  z.take<int>(64);
-  Carver cv(ws_get(h, kBufDriver, z.off));
-  double* Af = cv.take<double>((size_t)n * n);
-  double* Bf = cv.take<double>((size_t)n * n);
-  std::vector<double*> LD(S1);
-  std::vector<int32_t*> ipv(S1);
-  for (int s = 0; s < S1; ++s) LD[s] = cv.take<double>((size_t)n * n);
-  for (int s = 0; s < S1; ++s) ipv[s] = cv.take<int32_t>(n);
-  std::vector<int*> perm(P), blk(P);
-  std::vector<double*> Linv(P);
-  for (int s = 0; s < P; ++s) {
-    perm[s] = cv.take<int>(n);
-    blk[s] = cv.take<int>(n);
-    Linv[s] = cv.take<double>(solve_linv_size(n));
-  }
-  double* nsmall = cv.take<double>(64 * 8);
-  double* nX = cv.take<double>((size_t)n * 8 * 2);
-  int* nflag = cv.take<int>(64);
   // ---- 1. factorizations and inertia
   const auto t_f0 = Clock::now();
-  sym_full_launch(n, A, lda, Af, n, st);
-  sym_full_launch(n, B, ldb, Bf, n, st);
   std::vector<double> pts(sig);
   pts.push_back(top);
   const int nb = o.nb > 0 ? std::min(o.nb, kMaxNb) : default_nb(n);
-  FactorPlan fp =
-      build_factor(h, kBufFactor, n, A, lda, B, ldb, S1, pts.data(), LD.data(), n, ipv.data(), nb, true);
-  factor_launch(fp, st);
-  std::vector<int64_t> inert(3 * S1);
-  SL_HIP(hipMemcpyAsync(inert.data(), fp.d_inertia, sizeof(int64_t) * 3 * S1, hipMemcpyDeviceToHost, st));
-  SL_HIP(hipStreamSynchronize(st));
-  ring.synced();
+  DriverWs dw = driver_factor(h, ring, n, A, lda, B, ldb, pts, nb);
   const double t_factor = ms_since(t_f0);
-  for (int s = 0; s < S1; ++s)
-    if (inert[3 * s + 1] != 0) {
-      if (rep) {
-        rep->n_shifts = P;
-        rep->t_factor_ms = t_factor;
-      }
-      return SISLICE_SINGULAR_SHIFT;
+  const std::vector<int64_t>& inert = dw.inert;
+  if (h->fc.id == 0) {  // an exact zero pivot
+    if (rep) {
+      rep->n_shifts = P;
+      rep->t_factor_ms = t_factor;
     }
+    return SISLICE_SINGULAR_SHIFT;
+  }
+  double* Af = dw.Af;
+  double* Bf = dw.Bf;
+  const std::vector<double*>& LD = dw.LD;
+  const std::vector<int32_t*>& ipv = dw.ipv;
+  const std::vector<int*>& perm = dw.perm;
+  const std::vector<int*>& blk = dw.blk;
+  const std::vector<double*>& Linv = dw.Linv;
+  double* nsmall = dw.nsmall;
+  double* nX = dw.nX;
+  int* nflag = dw.nflag;
+  const FactorPlan& fp = dw.fp;
   std::vector<int64_t> nu(P);
   for (int s = 0; s < P; ++s) nu[s] = inert[3 * s];
   const int64_t nu_top = inert[3 * P];
@@ -605,8 +501,12 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   *omega_top_io = top;
   // solve preparation for the probe shifts
   solve_prep_launch(n, P, reinterpret_cast<const int* const*>(ring.ptrs(std::vector<int32_t*>(ipv.begin(), ipv.begin() + P))),
-                    ring.ptrs(perm), ring.ptrs(blk),
-                    ring.cptrs(std::vector<double*>(LD.begin(), LD.begin() + P)), n, ring.ptrs(Linv), st);
+                    ring.ptrs(std::vector<int*>(perm.begin(), perm.begin() + P)),
+                    ring.ptrs(std::vector<int*>(blk.begin(), blk.begin() + P)),
+                    ring.cptrs(std::vector<double*>(LD.begin(), LD.begin() + P)), n,
+                    ring.ptrs(std::vector<double*>(Linv.begin(), Linv.begin() + P)), st);
+  for (int s = 0; s < P; ++s) h->fc.prepped[s] = 1;
+  if (rep) rep->factor_id = h->fc.id;
   // ||A||_2 and ||B||_2 estimates
   std::vector<int> one{1};
   int* active1 = ring.vec(one);

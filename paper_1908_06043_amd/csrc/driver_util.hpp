@@ -1,0 +1,181 @@
+// Host-side helpers shared by the drivers: the pinned upload ring for per-launch
+// kernel tables and a batched GEMM front end.
+#pragma once
+
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "blas.hpp"
+#include "handle.hpp"
+#include "kernels.hpp"
+
+namespace sislice {
+
+using Clock = std::chrono::steady_clock;
+inline double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// Pinned host ring + device ring for the small per-launch tables.  put() only
+// stages a table in the host ring; the tables staged since the last launch go
+// to the device in one copy, issued by the launch macro just before the next
+// kernel (stream order then delivers them first).  The host bytes stay untouched
+// until the stream has passed that copy: the ring is rewound only after a
+// stream synchronisation.
+class Ring {
+ public:
+  explicit Ring(sislice_handle* h, size_t cap = 16u << 20) : h_(h), cap_(cap) {
+    if (h->ring_cap < cap) {
+      if (h->ring_host) {
+        SL_HIP(hipStreamSynchronize(h->stream));
+        SL_HIP(hipHostFree(h->ring_host));
+        h->ring_host = nullptr;
+        h->ring_cap = 0;
+      }
+      SL_HIP(hipHostMalloc(&h->ring_host, cap, hipHostMallocDefault));
+      h->ring_cap = cap;
+    }
+    host_ = static_cast<char*>(h->ring_host);
+    dev_ = static_cast<char*>(ws_get(h, kBufRing, cap));
+    h->flush_fn = &Ring::flush_thunk;
+    h->flush_ctx = this;
+  }
+  ~Ring() {
+    if (h_->flush_ctx == this) {
+      try {
+        flush();
+      } catch (...) {
+      }
+      h_->flush_fn = nullptr;
+      h_->flush_ctx = nullptr;
+    }
+  }
+  Ring(const Ring&) = delete;
+  Ring& operator=(const Ring&) = delete;
+  void* put(const void* src, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    const size_t b = (bytes + 255) & ~size_t(255);
+    SL_CHECK_ARG(b <= cap_, "table too large for the upload ring");
+    if (off_ + b > cap_) {
+      flush();
+      SL_HIP(hipStreamSynchronize(h_->stream));
+      off_ = pend_ = 0;
+    }
+    if (src)
+      std::memcpy(host_ + off_, src, bytes);
+    else
+      std::memset(host_ + off_, 0, bytes);
+    void* r = dev_ + off_;
+    off_ += b;
+    return r;
+  }
+  void flush() {
+    if (off_ > pend_) {
+      SL_HIP(hipMemcpyAsync(dev_ + pend_, host_ + pend_, off_ - pend_, hipMemcpyHostToDevice,
+                            h_->stream));
+      pend_ = off_;
+    }
+  }
+  template <class T>
+  T* vec(const std::vector<T>& v) {
+    return static_cast<T*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T)));
+  }
+  template <class T>
+  T* const* ptrs(const std::vector<T*>& v) {
+    return reinterpret_cast<T* const*>(put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
+  }
+  template <class T>
+  const T* const* cptrs(const std::vector<T*>& v) {
+    return reinterpret_cast<const T* const*>(
+        put(v.empty() ? nullptr : v.data(), v.size() * sizeof(T*)));
+  }
+  // caller has synchronised the stream: every uploaded table has been consumed;
+  // tables still staged are uploaded (and waited for) before the ring rewinds
+  void synced() {
+    if (off_ > pend_) {
+      flush();
+      SL_HIP(hipStreamSynchronize(h_->stream));
+    }
+    off_ = pend_ = 0;
+  }
+
+ private:
+  static void flush_thunk(void* self) { static_cast<Ring*>(self)->flush(); }
+  sislice_handle* h_;
+  size_t cap_;
+  char* host_;
+  char* dev_;
+  size_t off_ = 0;
+  size_t pend_ = 0;
+};
+
+struct Ctx {
+  sislice_handle* h;
+  hipStream_t st;
+  Ring* ring;
+};
+
+// Batched GEMM helper: per-batch sizes, pointer tables through the ring,
+// split-K (ordered partials) when the reduction is long and the output small.
+inline void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std::vector<int>& nn,
+          const std::vector<int>& k, const std::vector<const double*>& A, long lda,
+          const std::vector<const double*>& B, long ldb, const std::vector<double*>& C, long ldc,
+          double alpha, double beta) {
+  const int batch = (int)m.size();
+  if (batch == 0) return;
+  int mmax = 0, nmax = 0, kmax = 0;
+  for (int b = 0; b < batch; ++b) {
+    mmax = std::max(mmax, m[b]);
+    nmax = std::max(nmax, nn[b]);
+    kmax = std::max(kmax, k[b]);
+  }
+  if (mmax == 0 || nmax == 0) return;
+  GemmArgs g;
+  g.m = c.ring->vec(m);
+  g.n = c.ring->vec(nn);
+  g.k = c.ring->vec(k);
+  g.A = c.ring->cptrs(A);
+  g.lda = lda;
+  g.B = c.ring->cptrs(B);
+  g.ldb = ldb;
+  g.C = c.ring->ptrs(C);
+  g.ldc = ldc;
+  g.alpha = alpha;
+  g.beta = beta;
+  int splits = 1;
+  const long tiles = ceil_div(mmax, 64) * ceil_div(nmax, 64) * (long)batch;
+  if (kmax >= 1024 && tiles < 512) {
+    splits = (int)std::min<long>(std::max<long>(1, 1024 / tiles), kmax / 256);
+    splits = std::max(1, std::min(splits, 64));
+  }
+  g.splits = splits;
+  if (splits > 1)
+    g.partial = static_cast<double*>(
+        ws_get(c.h, kBufMisc, sizeof(double) * (size_t)batch * splits * mmax * nmax));
+  gemm_launch(g, batch, mmax, nmax, ta, tb, c.st);
+}
+
+// Driver workspace of one pencil: full copies of A and B (adjacent: [A B] is an
+// n x 2n matrix with leading dimension n), the factorizations of
+// A - pts[s] B (LD, ipiv) with room for their solve preparation (perm, blk,
+// Linv), and small scratch.  driver_factor carves it, factors every point in
+// lock step, reads the inertias (synchronising) and, when no pivot is an exact
+// zero, records the factorizations in the handle's cache (h->fc.id != 0).
+struct DriverWs {
+  double* Af = nullptr;
+  double* Bf = nullptr;
+  std::vector<double*> LD;
+  std::vector<int32_t*> ipv;
+  std::vector<int*> perm, blk;
+  std::vector<double*> Linv;
+  double* nsmall = nullptr;
+  double* nX = nullptr;
+  int* nflag = nullptr;
+  FactorPlan fp;
+  std::vector<int64_t> inert;
+};
+DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, long lda,
+                       const double* B, long ldb, const std::vector<double>& pts, int nb);
+
+}  // namespace sislice

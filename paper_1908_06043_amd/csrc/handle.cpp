@@ -24,6 +24,7 @@ void* ws_get(sislice_handle* h, int id, size_t bytes) {
   auto& b = h->bufs[id];
   if (bytes == 0) bytes = 256;
   if (b.cap < bytes) {
+    if (id == kBufDriver) h->fc.id = 0;  // the cached factorizations move
     if (b.ptr) {
       SL_HIP(hipStreamSynchronize(h->stream));
       SL_HIP(hipFree(b.ptr));

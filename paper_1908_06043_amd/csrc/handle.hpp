@@ -13,7 +13,7 @@ struct sislice_handle {
     void* ptr = nullptr;
     size_t cap = 0;
   };
-  Buf bufs[8];
+  Buf bufs[9];
   void* host_stage = nullptr;  // pinned staging for small host<->device records
   size_t host_cap = 0;
   unsigned* sync = nullptr;  // epoch flags and ticket counters of the persistent solves
@@ -33,6 +33,24 @@ struct sislice_handle {
     hipEvent_t a, b;
   };
   std::vector<ProfRec> recs;
+  // Factorizations of the last sislice_solve (its shifts, then the top boundary),
+  // which stay in the driver workspace for sislice_adjoint.  id 0: none valid.
+  struct FactorCache {
+    uint64_t id = 0;
+    int n = 0;
+    const double* A = nullptr;
+    const double* B = nullptr;
+    long lda = 0, ldb = 0;
+    double* Af = nullptr;  // full A, followed by full B (an n x 2n matrix)
+    std::vector<double> pts;
+    std::vector<double*> LD;
+    std::vector<int32_t*> ipv;
+    std::vector<int*> perm, blk;
+    std::vector<double*> Linv;
+    std::vector<int64_t> inertia;  // 3 per point
+    std::vector<char> prepped;     // solve preparation done for the point
+  } fc;
+  uint64_t fc_counter = 0;
 };
 
 namespace sislice {
@@ -45,7 +63,8 @@ enum BufId {
   kBufEig = 4,
   kBufMisc = 5,
   kBufLanczos = 6,
-  kBufRing = 7
+  kBufRing = 7,
+  kBufAdjoint = 8
 };
 
 // Returns a device buffer of at least `bytes`, reallocating (contents lost) if needed.

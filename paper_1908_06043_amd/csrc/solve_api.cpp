@@ -13,7 +13,6 @@ extern "C" sislice_status sislice_ldlt_solve(sislice_handle* h, int64_t n, const
     SL_CHECK_ARG(nrhs >= 0 && nrhs <= 64, "nrhs must be in [0, 64]");
     if (n == 0 || nrhs == 0) return SISLICE_OK;
     SL_CHECK_ARG(LD && ipiv && X && ldld >= n && ldx >= n, "bad argument");
-    const long nblk = solve_nblk(n);
     Sizer z;
     z.take<int>(n);
     z.take<int>(n);
