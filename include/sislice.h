@@ -231,6 +231,51 @@ sislice_status sislice_adjoint(sislice_handle *h, int64_t n, const double *A, in
                                double tol, int32_t max_iter, double *GA, int64_t ldga, double *GB,
                                int64_t ldgb, sislice_adjoint_report *report);
 
+/* One pencil of a batched solve: inputs and outputs as in sislice_solve (all
+ * device pointers); its n_s shifts and top boundary are planned by KPM. */
+typedef struct {
+  int64_t n;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  int64_t n_e;
+  int64_t n_s;
+  double *evals;   /* device double[n_e] out, ascending            */
+  double *evecs;   /* device n x n_e (ldx >= n) out, B-orthonormal */
+  int64_t ldx;
+  double *resid;   /* device double[n_e] out                       */
+} sislice_problem;
+
+typedef struct {
+  int32_t workers;       /* pencils in flight at a time                          */
+  int32_t n_ok;          /* problems that returned SISLICE_OK                    */
+  int32_t n_tuned;       /* orders autotuned by this call (0: all were cached)   */
+  int64_t n_converged;   /* returned eigenpairs meeting opts->tol, summed        */
+  double t_total_ms;
+  double t_tune_ms;      /* autotuning time inside t_total_ms                    */
+} sislice_batch_report;
+
+/* Many independent pencils of possibly different orders (the paper's probes
+ * are independent, Sec. 4.1; so are whole pencils): each problem is planned
+ * (sislice_plan_shifts_kpm) and solved (sislice_solve) exactly as alone, with
+ * `workers` pencils in flight at a time (<= 0: 4; at most 16), each on a
+ * worker handle with its own stream and workspaces that the handle keeps, the
+ * largest orders first.  Unless opts->nb fixes it, the factorization panel
+ * width is autotuned per order on the first pencil of that order (the
+ * lock-step factorization of its planned points timed for widths 32, 48, 64)
+ * and cached in the handle.  status: host int32[count] out, one sislice_status
+ * per problem.  Returns SISLICE_OK when every problem did, else the most
+ * severe status (negative before positive).  Synchronises; inputs must be
+ * complete on the handle's stream. */
+sislice_status sislice_solve_batched(sislice_handle *h, int64_t count,
+                                     const sislice_problem *problems, const sislice_opts *opts,
+                                     int32_t workers, int32_t *status,
+                                     sislice_batch_report *report);
+
+/* Panel width the autotuner cached for order n on this handle (0: none). */
+int32_t sislice_tuned_nb(sislice_handle *h, int64_t n);
+
 /* Shift migration by k-means (Sec. 3.2), host only: Lloyd iterations on the 1-D
  * set `ritz` (host double[n]) from the initial centroids `prev_shifts` (host
  * double[n_s]) or, if use_kmeanspp, from k-means++ seeding drawn from the

@@ -44,6 +44,17 @@ class AdjointReport(C.Structure):
                 ("flops_outer", C.c_double), ("t_outer_ms", C.c_double)]
 
 
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("A", C.c_void_p), ("lda", C.c_int64), ("B", C.c_void_p),
+                ("ldb", C.c_int64), ("n_e", C.c_int64), ("n_s", C.c_int64), ("evals", C.c_void_p),
+                ("evecs", C.c_void_p), ("ldx", C.c_int64), ("resid", C.c_void_p)]
+
+
+class BatchReport(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("n_ok", C.c_int32), ("n_tuned", C.c_int32),
+                ("n_converged", C.c_int64), ("t_total_ms", C.c_double), ("t_tune_ms", C.c_double)]
+
+
 _SIGS = {
     "sislice_default_opts": (None, [C.POINTER(Opts)]),
     "sislice_status_string": (C.c_char_p, [C.c_int]),
@@ -71,6 +82,9 @@ _SIGS = {
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, c_double_p,
                                   C.c_double, C.c_uint64, C.c_double, C.c_int32, C.c_void_p,
                                   C.c_int64, C.c_void_p, C.c_int64, C.POINTER(AdjointReport)]),
+    "sislice_solve_batched": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Problem), C.POINTER(Opts),
+                                        C.c_int32, c_int32_p, C.POINTER(BatchReport)]),
+    "sislice_tuned_nb": (C.c_int32, [C.c_void_p, C.c_int64]),
     "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
                                         C.c_uint64, c_double_p, c_int32_p]),
     "sislice_validate": (C.c_int64, [C.c_int64, c_double_p, c_int64_p, C.c_double, C.c_int64,

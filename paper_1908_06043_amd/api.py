@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import AdjointReport, Opts, Report, SisliceError
+from ._lib import AdjointReport, BatchReport, Opts, Problem, Report, SisliceError
 
 _handles = {}
 
@@ -224,6 +224,46 @@ def adjoint(A, B, evals, evecs, g_evals, g_evecs, sigmas, omega_top, factor_id=0
     report = {f: getattr(rep, f) for f, _ in AdjointReport._fields_}
     report["status"] = st
     return GA, GB, report
+
+
+def solve_batched(pencils, opts=None, workers=0, check=True):
+    """Many independent pencils: ``pencils`` is a list of (A, B, n_e, n_s); each is
+    planned and solved as by ``solve`` (shifts from KPM), several at a time on
+    worker streams.  Returns (results, report): per pencil a dict with evals,
+    evecs (n x n_e view), resid and status."""
+    o = opts or default_opts()
+    count = len(pencils)
+    probs = (Problem * max(count, 1))()
+    outs = []
+    dev_index = None
+    for i, (A, B, n_e, n_s) in enumerate(pencils):
+        A = _mat(A, "A")
+        B = _mat(B, "B")
+        n = A.shape[0]
+        dev_index = A.device.index
+        ev = torch.empty(n_e, dtype=torch.float64, device=A.device)
+        Xt = torch.empty((n_e, n), dtype=torch.float64, device=A.device)
+        rs = torch.empty(n_e, dtype=torch.float64, device=A.device)
+        probs[i] = Problem(n, A.data_ptr(), n, B.data_ptr(), n, n_e, n_s, ev.data_ptr(),
+                           Xt.data_ptr(), n, rs.data_ptr())
+        outs.append(dict(evals=ev, evecs=Xt.t(), resid=rs, _keep=(A, B, Xt)))
+    status = np.zeros(max(count, 1), dtype=np.int32)
+    rep = BatchReport()
+    st = _lib.load().sislice_solve_batched(handle(dev_index), count, probs, C.byref(o), int(workers),
+                                          status.ctypes.data_as(_lib.c_int32_p), C.byref(rep))
+    if check:
+        _check(st, "sislice_solve_batched")
+    for i, d in enumerate(outs):
+        d["status"] = int(status[i])
+        d.pop("_keep")
+    report = {f: getattr(rep, f) for f, _ in BatchReport._fields_}
+    report["status"] = st
+    return outs, report
+
+
+def tuned_nb(n, device=None):
+    """Panel width the batch autotuner cached for order n (0: none yet)."""
+    return int(_lib.load().sislice_tuned_nb(handle(device), int(n)))
 
 
 class _PencilEig(torch.autograd.Function):

@@ -451,12 +451,11 @@ void tsmm_launch(TsArgs a, int batch, int mtot_max, hipStream_t st) {
   if (batch <= 0) return;
   const size_t lds = (size_t)std::max(mtot_max, 1) * 8 * sizeof(double);
   SL_CHECK_ARG(lds <= kTsmmMaxLds, "tall-skinny product: too many basis columns");
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     SL_HIP(hipFuncSetAttribute((const void*)k_tsmm, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)kTsmmMaxLds));
-    attr = true;
-  }
+  });
   sislice_handle* ph = current_handle();
   const int tk = prof_begin(ph, kProfGemm);
   SL_LAUNCH(k_tsmm, dim3((unsigned)ceil_div(a.n, 64), batch), dim3(256), lds, st, a);

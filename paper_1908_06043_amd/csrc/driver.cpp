@@ -46,16 +46,6 @@ struct ProbeHost {
   std::vector<double> lock_lam;
 };
 
-void check_opts(const sislice_opts& o) {
-  SL_CHECK_ARG(o.block == kLanczosBlock, "only block size 8 is built");
-  SL_CHECK_ARG(o.max_basis >= 32 && o.max_basis <= kEigMax && o.max_basis % kLanczosBlock == 0,
-               "max_basis must be a multiple of 8 in [32, 112]");
-  SL_CHECK_ARG(o.max_cycles >= 1, "max_cycles must be positive");
-  SL_CHECK_ARG(o.kpm_moments >= 4 && o.kpm_moments <= 4096, "kpm_moments out of range");
-  SL_CHECK_ARG(o.kpm_vectors >= 1 && o.kpm_vectors <= kSolveMaxRhs, "kpm_vectors in [1, 32]");
-  SL_CHECK_ARG(o.bounds_steps >= 2 && o.bounds_steps <= 100, "bounds_steps in [2, 100]");
-  SL_CHECK_ARG(o.tol > 0 && o.tol < 1, "tol in (0, 1)");
-}
 
 // ||M||_2 of a symmetric full matrix by block power iteration with a final
 // Rayleigh-Ritz on 8 vectors (a lower bound that converges quickly; only a
@@ -102,6 +92,17 @@ double sym_norm2(Ctx& c, int n, const double* M, double* X, double* Y, double* G
 }
 
 }  // namespace
+
+void check_opts(const sislice_opts& o) {
+  SL_CHECK_ARG(o.block == kLanczosBlock, "only block size 8 is built");
+  SL_CHECK_ARG(o.max_basis >= 32 && o.max_basis <= kEigMax && o.max_basis % kLanczosBlock == 0,
+               "max_basis must be a multiple of 8 in [32, 112]");
+  SL_CHECK_ARG(o.max_cycles >= 1, "max_cycles must be positive");
+  SL_CHECK_ARG(o.kpm_moments >= 4 && o.kpm_moments <= 4096, "kpm_moments out of range");
+  SL_CHECK_ARG(o.kpm_vectors >= 1 && o.kpm_vectors <= kSolveMaxRhs, "kpm_vectors in [1, 32]");
+  SL_CHECK_ARG(o.bounds_steps >= 2 && o.bounds_steps <= 100, "bounds_steps in [2, 100]");
+  SL_CHECK_ARG(o.tol > 0 && o.tol < 1, "tol in (0, 1)");
+}
 
 // ---------------------------------------------------------------- planner
 
@@ -466,8 +467,31 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   pts.push_back(top);
   const int nb = o.nb > 0 ? std::min(o.nb, kMaxNb) : default_nb(n);
   DriverWs dw = driver_factor(h, ring, n, A, lda, B, ldb, pts, nb);
+  std::vector<int64_t> inert = dw.inert;
+  // Top boundary recovery: fewer than n_e eigenvalues below omega_top (the planner's
+  // estimate fell short).  Move the boundary up in doubling steps, refactoring only
+  // that point, until the count reaches n_e; the last probe's slice grows with it.
+  if (h->fc.id != 0 && inert[3 * P] < n_e) {
+    double step = std::max(top - sig[P - 1], 1e-6 * (std::fabs(top) + 1.0));
+    for (int tries = 0; tries < 40 && inert[3 * P] < n_e; ++tries) {
+      top += step;
+      step *= 2.0;
+      double* ldp = dw.LD[P];
+      int32_t* ipp = dw.ipv[P];
+      FactorPlan f1 = build_factor(h, kBufFactor, n, A, lda, B, ldb, 1, &top, &ldp, n, &ipp, nb, true);
+      factor_launch(f1, st);
+      SL_HIP(hipMemcpyAsync(&inert[3 * P], f1.d_inertia, sizeof(int64_t) * 3, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipStreamSynchronize(st));
+      ring.synced();
+      if (inert[3 * P + 1] != 0) inert[3 * P] = -1;  // exactly singular: step on
+    }
+    SL_CHECK_ARG(inert[3 * P] >= n_e, "no top boundary with n_e eigenvalues below it");
+    pts[P] = top;
+    h->fc.pts[P] = top;
+    for (int q = 0; q < 3; ++q) h->fc.inertia[3 * P + q] = inert[3 * P + q];
+    h->fc.prepped[P] = 0;
+  }
   const double t_factor = ms_since(t_f0);
-  const std::vector<int64_t>& inert = dw.inert;
   if (h->fc.id == 0) {  // an exact zero pivot
     if (rep) {
       rep->n_shifts = P;
@@ -709,7 +733,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     while (true) {
       std::vector<int> js;
       for (int j : act)
-        if (pr[j].mq - b < MB) js.push_back(j);
+        if (pr[j].mq <= MB) js.push_back(j);  // the projected order mq - b stays <= MB
       if (js.empty()) break;
       const int na = (int)js.size();
       block_steps += na;

@@ -178,4 +178,17 @@ struct DriverWs {
 DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, long lda,
                        const double* B, long ldb, const std::vector<double>& pts, int nb);
 
+// The KPM shift planner and the plain per-pencil path (argument checks done by
+// the entry points).
+sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                         const sislice_opts& o, double* sig, double* top, double* mom_out,
+                         double* bounds_out);
+sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
+                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
+                          const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
+                          double* evals, double* evecs, int64_t ldx, double* resid_out,
+                          sislice_report* rep);
+void check_opts(const sislice_opts& o);
+
 }  // namespace sislice

@@ -200,12 +200,11 @@ size_t eig_lds_bytes(int mmax) {
 }
 
 void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
     SL_HIP(hipFuncSetAttribute((const void*)k_syevj, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024));
-    attr = true;
-  }
+  });
   const size_t lds = eig_lds_bytes(mmax);
   SL_CHECK_ARG(lds <= 160 * 1024, "projected problem too large for the LDS eigensolver");
   const int tk = prof_begin(current_handle(), kProfEig);

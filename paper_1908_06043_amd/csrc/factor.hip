@@ -875,14 +875,13 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
   }
   SL_CHECK_ARG(kmin >= n, "factorization did not complete");
   if (fp.pivot) {
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::once_flag attr_set;
+    std::call_once(attr_set, [] {
       SL_HIP(hipFuncSetAttribute((const void*)k_left_gather,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
       SL_HIP(hipFuncSetAttribute((const void*)k_perm_suffix,
                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      attr_set = true;
-    }
+    });
     SL_LAUNCH(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
                        fp.d_pstart, fp.d_state, fp.d_snap);
     SL_LAUNCH_CHECK();

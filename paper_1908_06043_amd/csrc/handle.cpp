@@ -266,6 +266,11 @@ sislice_status sislice_create(sislice_handle** out, int device, void* stream) {
 
 sislice_status sislice_destroy(sislice_handle* h) {
   if (!h) return SISLICE_OK;
+  for (auto* w : h->workers) sislice_destroy(w);
+  for (auto s : h->worker_streams) {
+    hipStreamSynchronize(s);
+    hipStreamDestroy(s);
+  }
   hipSetDevice(h->device);
   hipStreamSynchronize(h->stream);
   for (auto& b : h->bufs)

@@ -1,6 +1,7 @@
 // Library handle: device, stream and growable device workspaces.
 #pragma once
 
+#include <map>
 #include <vector>
 
 #include "common.hpp"
@@ -51,6 +52,11 @@ struct sislice_handle {
     std::vector<char> prepped;     // solve preparation done for the point
   } fc;
   uint64_t fc_counter = 0;
+  // Batched solves: worker handles (each with its own stream and workspaces)
+  // and the factorization panel width chosen by the autotuner per order n.
+  std::vector<sislice_handle*> workers;
+  std::vector<hipStream_t> worker_streams;  // created by the library, owned
+  std::map<int, int> tuned_nb;
 };
 
 namespace sislice {

@@ -240,3 +240,37 @@ def sym_directions(n, k, seed):
         e = 0.5 * (g + g.T)
         out[t] = e / np.linalg.norm(e)
     return out
+
+
+def batched_sizes(count=64, seed=7):
+    """Orders of the batched workload: N_p = 512 + 256 * U{0..10}, seeded; pencil p uses
+    seed 1000 + p, n_e = N_p // 10 and the SCF-shaped spectrum scaled to N_p."""
+    rng = np.random.default_rng(seed)
+    return [int(512 + 256 * k) for k in rng.integers(0, 11, count)]
+
+
+def make_pencil_device(n, lam_fn, seed, device, scale=0.05, decay=5.0):
+    """The ``make_pencil`` construction with its Gaussian draws (L, Q) taken from torch's
+    generator on ``device`` and the products formed there: the same recipe, shapes
+    and spectrum (``lam_fn`` draws from numpy's generator), a different random stream.
+    For large benchmark inputs that the host would take minutes to build.
+    Returns (A, B, lam) with A, B float64 device tensors."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    z = torch.randn((n, n), generator=g, **f64)
+    i = torch.arange(n, **f64)
+    L = torch.tril(z * scale * torch.exp(-(i[:, None] - i[None, :]).abs() / decay), -1)
+    L += torch.eye(n, **f64)
+    G = torch.randn((n, n), generator=g, **f64)
+    Q, R = torch.linalg.qr(G)
+    Q = Q * torch.sign(torch.diagonal(R))[None, :]
+    got = lam_fn(np.random.default_rng(seed), n)
+    lam = np.sort(np.asarray(got[0] if isinstance(got, tuple) else got, dtype=np.float64))
+    M = (Q * torch.from_numpy(lam).to(device)[None, :]) @ Q.T
+    A = L @ M @ L.T
+    A = 0.5 * (A + A.T)
+    B = L @ L.T
+    B = 0.5 * (B + B.T)
+    return A.contiguous(), B.contiguous(), lam

@@ -1,0 +1,106 @@
+"""GPU parity of the batched form (sislice_solve_batched) and of two cases the
+batched workload exposed in the plain path.
+
+Bar (per pencil): status OK; eigenvalues within 1e-10 max|lambda| of the
+construction's spectrum (the definition-level oracle: A = B X Lam X^T B);
+normalised residuals <= 1e-10; X^T B X = I to 1e-10; the same eigenvalues as
+the plain path on the same pencil to 1e-12 max|lambda|.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1908_06043_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(M):
+    return torch.from_numpy(np.ascontiguousarray(M)).cuda()
+
+
+def scf_lam(m):
+    return lambda r, k: inputs.spectrum_scf(r, k, m)
+
+
+def check(out, lam, n_e, B=None):
+    ev = out["evals"].cpu().numpy()
+    scale = float(np.max(np.abs(lam)))
+    assert out["status"] == 0, out["status"]
+    assert np.max(np.abs(ev - lam[:n_e])) <= 1e-10 * scale
+    assert float(out["resid"].max()) <= 1e-10
+    if B is not None:
+        X = out["evecs"]
+        G = (X.T @ (B @ X)).cpu().numpy()
+        assert np.max(np.abs(G - np.eye(n_e))) <= 1e-10
+    return ev
+
+
+def test_small_batch_matches_construction_and_plain(gpu_lib):
+    api = gpu_lib
+    sizes = [256, 320, 384, 448, 512, 576]
+    pens = []
+    for p, n in enumerate(sizes):
+        P = inputs.pencil_scf(n, n // 10, seed=2000 + p)
+        pens.append((P, dev(P.A), dev(P.B), n // 10))
+    print(f"batched small: sizes {sizes}", flush=True)
+    outs, rep = api.solve_batched([(A, B, ne, 8) for _, A, B, ne in pens], workers=3)
+    assert rep["status"] == 0 and rep["n_ok"] == len(sizes) and rep["workers"] == 3
+    assert rep["n_converged"] == sum(ne for *_, ne in pens)
+    for (P, A, B, ne), o in zip(pens, outs):
+        ev = check(o, P.lam, ne, B)
+        # host residual check with the library's own ||A||_2 scale
+        X = o["evecs"].cpu().numpy()
+        R = P.A @ X - (P.B @ X) * ev[None, :]
+        anorm = float(np.max(np.abs(P.lam))) * 1.1
+        assert np.max(np.linalg.norm(R, axis=0) / (anorm * np.linalg.norm(X, axis=0))) <= 1e-10
+        plain = api.solve(A, B, ne, 8)
+        assert np.max(np.abs(plain["evals"].cpu().numpy() - ev)) <= 1e-12 * np.max(np.abs(P.lam))
+    # the autotuner cached one width per order; a second call tunes nothing
+    for n in sizes:
+        assert api.tuned_nb(n) in (32, 48, 64)
+    _, rep2 = api.solve_batched([(A, B, ne, 8) for _, A, B, ne in pens], workers=2)
+    assert rep2["n_tuned"] == 0 and rep2["status"] == 0
+
+
+def test_restart_keeps_projected_order_bounded(gpu_lib):
+    # N = 1536 pencil whose thick restarts keep a number of vectors that is not a
+    # multiple of the block: the projected problems must stay within the
+    # eigensolver's order (regression of the batched workload's pencil 58)
+    api = gpu_lib
+    A, B, lam = inputs.make_pencil_device(1536, scf_lam(153), 1058, "cuda")
+    out = api.solve(A, B, 153, 8, check=False)
+    check(out, lam, 153, B)
+
+
+def test_top_boundary_recovery(gpu_lib):
+    # N = 2048 pencil whose planned top boundary has only 198 of the 204 wanted
+    # eigenvalues below it (a cluster just above): the boundary is moved up until
+    # it holds n_e (regression of the batched workload's pencil 4)
+    api = gpu_lib
+    A, B, lam = inputs.make_pencil_device(2048, scf_lam(204), 1004, "cuda")
+    plan = api.plan_shifts_kpm(A, B, 204, 8)
+    out = api.solve(A, B, 204, 8, sigmas=plan["sigmas"], omega_top=plan["omega_top"], check=False)
+    check(out, lam, 204)
+    assert out["omega_top"] > plan["omega_top"]
+    nu_top = int(out["report"]["nu_top"])
+    assert nu_top >= 204 and nu_top == int(np.sum(lam < out["omega_top"]))
+
+
+def test_full_batched_workload(gpu_lib):
+    # 64 pencils, N = 512 + 256 U{0..10}, n_e = N/10, 8 KPM shifts each
+    api = gpu_lib
+    sizes = inputs.batched_sizes(64, 7)
+    pens = []
+    for p, n in enumerate(sizes):
+        A, B, lam = inputs.make_pencil_device(n, scf_lam(n // 10), 1000 + p, "cuda")
+        pens.append((A, B, n // 10, lam))
+    print(f"batched full: {len(sizes)} pencils, sum N = {sum(sizes)}", flush=True)
+    outs, rep = api.solve_batched([(A, B, ne, 8) for A, B, ne, _ in pens], workers=8)
+    assert rep["status"] == 0 and rep["n_ok"] == 64
+    for (A, B, ne, lam), o in zip(pens, outs):
+        check(o, lam, ne)
+    # B-orthonormality on a sample
+    for k in (0, 13, 40):
+        A, B, ne, lam = pens[k]
+        check(outs[k], lam, ne, B)
