@@ -12,7 +12,9 @@ The pencil is generated once (seeded) and is resident in HBM before timing.
 
 The ``adjoint`` object reports the differentiated form on its own workload
 (N=2048, n_e=200, 8 shifts): forward + backward eigenpairs/s against forward
-only on the same pencil and GPU.
+only on the same pencil and GPU.  The ``batched`` object reports 64 pencils of
+uneven order (512..3072) solved by the batch scheduler against the plain path
+looping over the same pencils.
 
 Prints one JSON line.  ``value`` = converged eigenpairs (validated, residual
 <= 1e-10) per second.  ``roofline`` describes the dominant kernel class,
@@ -143,6 +145,50 @@ def adjoint_leg(api, inputs, torch, steps=3, warmup=1):
     }
 
 
+def batched_leg(api, inputs, torch, workers=8, reps=2):
+    """Batched workload (64 pencils, N = 512 + 256 U{0..10}, n_e = N/10, 8 KPM shifts
+    each): the plain path looping over the pencils against sislice_solve_batched on
+    the same pencils and GPU.  The first batched call (autotuning and worker
+    workspaces) is untimed warm-up."""
+    sizes = inputs.batched_sizes(64, 7)
+    pens = []
+    for p, n in enumerate(sizes):
+        A, B, _ = inputs.make_pencil_device(
+            n, lambda r, m, k=n // 10: inputs.spectrum_scf(r, m, k), 1000 + p, "cuda")
+        pens.append((A, B, n // 10, 8))
+    opts = api.default_opts()
+    big = max(range(len(sizes)), key=lambda i: sizes[i])
+    api.solve(*pens[big], opts=opts, check=False)          # plain warm-up at the largest order
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv_plain = 0
+    for A, B, ne, ns in pens:
+        o = api.solve(A, B, ne, ns, opts=opts, check=False)
+        conv_plain += int(o["report"]["n_converged"]) if o["status"] in (0, 2) else 0
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    _, rep0 = api.solve_batched(pens, opts=opts, workers=workers, check=False)  # tunes
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs, rep = api.solve_batched(pens, opts=opts, workers=workers, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if best is None or dt < best[0]:
+            best = (dt, rep)
+    dt, rep = best
+    return {
+        "workload": f"batched: {len(sizes)} pencils, N = 512 + 256 U{{0..10}} (sum N = {sum(sizes)}), "
+                    f"n_e = N/10, 8 KPM shifts each, SCF-shaped spectra",
+        "value": rep["n_converged"] / dt, "plain_value": conv_plain / t_plain, "unit": "eigenpairs/s",
+        "ratio_vs_plain": (rep["n_converged"] / dt) / (conv_plain / t_plain),
+        "ms_batched": 1e3 * dt, "ms_plain_loop": 1e3 * t_plain, "workers": rep["workers"],
+        "pencils_ok": rep["n_ok"], "tune_ms_first_call": rep0["t_tune_ms"],
+        "tuned_nb": {str(n): api.tuned_nb(n) for n in sorted(set(sizes))},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +199,7 @@ def main():
     ap.add_argument("--ns", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-plain leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the steps, fill a 2 GiB buffer and copy it with one elementwise kernel "
                          "(reads and writes 2 GiB, beyond the last-level cache): the reference that "
@@ -255,6 +302,8 @@ def main():
     }
     if not args.no_adjoint:
         line["adjoint"] = adjoint_leg(api, inputs, torch)
+    if not args.no_batched:
+        line["batched"] = batched_leg(api, inputs, torch)
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)
