@@ -77,13 +77,14 @@ __global__ __launch_bounds__(64) void k_diag_inv_blk(int n, const double* const*
   for (int k = 0; k < SB; ++k) Linv[t + k * SB] = sX[k][t];
 }
 
-// Look-ahead blocks (per shift, after the nblk diagonal inverses):
-//   Mf_b = Linv_b L_{b,b-1}           (forward sweep, b >= 1)
-//   Mb_b = Linv_b^T L_{b+1,b}^T       (backward sweep, b <= nblk - 2)
-// so that a block's result is P_b - M_b x (previous block) with P_b formed before
-// the previous block is available.  L's structural zeros inside 2x2 pivots are
-// applied here (lval), so the sweeps read these blocks as plain matrices.
-// Layout: column-major 64x64, Mf at nblk*SB*SB, Mb at 2*nblk*SB*SB of the Linv buffer.
+// Look-ahead blocks of depth d = 1, 2 (per shift, after the nblk diagonal inverses):
+//   Mf^d_b = Linv_b L_{b,b-d}           (forward sweep, b >= d)
+//   Mb^d_b = Linv_b^T L_{b+d,b}^T       (backward sweep, b + d <= nblk - 1)
+// so that a block's result is P_b - sum_d M^d_b x (block b -+ d), with P_b (the
+// contributions of blocks further away) formed before the nearest two blocks are
+// available.  L's structural zeros inside 2x2 pivots are applied here (lval), so
+// the sweeps read these blocks as plain matrices.  Layout: column-major 64x64,
+// Mf^d at (2d - 1)*nblk*SB*SB and Mb^d at 2d*nblk*SB*SB of the Linv buffer.
 __global__ __launch_bounds__(256) void k_lookahead(int n, const double* const* LDs, long ldld,
                                                    const int* const* blks, double* const* Linvs) {
   __shared__ double sA[SB][SB + 1];  // Linv_b(i, k)
@@ -96,35 +97,38 @@ __global__ __launch_bounds__(256) void k_lookahead(int n, const double* const* L
   const double* Li = base + (long)b * SB * SB;
   const int r0 = b * SB;
   for (int e = tid; e < SB * SB; e += 256) sA[e & 63][e >> 6] = Li[e];
-  // forward: sB[j][k] = L(r0 + j, r0 - 64 + k)
-  if (b >= 1) {
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int j = e & 63, k = e >> 6, row = r0 + j;
-      sB[j][k] = (row < n) ? lval(LD, ldld, blk, row, r0 - SB + k) : 0.0;
+  for (int d = 1; d <= kSolveLook; ++d) {
+    // forward: sB[j][k] = L(r0 + j, r0 - d*64 + k)
+    if (b >= d) {
+      __syncthreads();
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int j = e & 63, k = e >> 6, row = r0 + j;
+        sB[j][k] = (row < n) ? lval(LD, ldld, blk, row, r0 - d * SB + k) : 0.0;
+      }
+      __syncthreads();
+      double* Mf = base + (long)(2 * d - 1) * nblk * SB * SB + (long)b * SB * SB;
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int i = e & 63, k = e >> 6;
+        double v = 0.0;
+        for (int j = 0; j <= i; ++j) v += sA[i][j] * sB[j][k];
+        Mf[e] = v;
+      }
     }
-    __syncthreads();
-    double* Mf = base + (long)nblk * SB * SB + (long)b * SB * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int i = e & 63, k = e >> 6;
-      double v = 0.0;
-      for (int j = 0; j <= i; ++j) v += sA[i][j] * sB[j][k];
-      Mf[e] = v;
-    }
-    __syncthreads();
-  }
-  // backward: G = L_{b+1,b} Linv_b, sB[i][j] = L(r0 + 64 + i, r0 + j); Mb = G^T
-  if (b + 1 < nblk) {
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int ii = e & 63, j = e >> 6, row = r0 + SB + ii;
-      sB[ii][j] = (row < n) ? lval(LD, ldld, blk, row, r0 + j) : 0.0;
-    }
-    __syncthreads();
-    double* Mb = base + 2L * nblk * SB * SB + (long)b * SB * SB;
-    for (int e = tid; e < SB * SB; e += 256) {
-      const int i = e & 63, k = e >> 6;  // Mb(i, k) = G(k, i) = sum_j L(k, j) Linv(j, i)
-      double v = 0.0;
-      for (int j = i; j < SB; ++j) v += sB[k][j] * sA[j][i];
-      Mb[e] = v;
+    // backward: G = L_{b+d,b} Linv_b, sB[i][j] = L(r0 + d*64 + i, r0 + j); Mb = G^T
+    if (b + d < nblk) {
+      __syncthreads();
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int ii = e & 63, j = e >> 6, row = r0 + d * SB + ii;
+        sB[ii][j] = (row < n) ? lval(LD, ldld, blk, row, r0 + j) : 0.0;
+      }
+      __syncthreads();
+      double* Mb = base + (long)(2 * d) * nblk * SB * SB + (long)b * SB * SB;
+      for (int e = tid; e < SB * SB; e += 256) {
+        const int i = e & 63, k = e >> 6;  // Mb(i, k) = G(k, i) = sum_j L(k, j) Linv(j, i)
+        double v = 0.0;
+        for (int j = i; j < SB; ++j) v += sB[k][j] * sA[j][i];
+        Mb[e] = v;
+      }
     }
   }
 }
@@ -163,12 +167,27 @@ __device__ __forceinline__ bool is_sentinel(double v) {
 }
 
 // sX[c][rr] = block rows rr < rows of column c of B (ld ldb), once none is the
-// sentinel; rows past `rows` read as zero.  One lane waits on a single element
-// first (the last one of the block), so the waiting workgroups do not stream the
-// whole block from the coherence point on every poll; the block is then loaded
-// and checked in full (other lanes' stores may still be on their way).
+// sentinel; rows past `rows` read as zero.  A block that is already complete (the
+// common case for a workgroup that started after its predecessors) is read in one
+// round trip.  Otherwise one lane waits on a single element first (the last one of
+// the block), so the waiting workgroups do not stream the whole block from the
+// coherence point on every poll; the block is then loaded and checked in full
+// (other lanes' stores may still be on their way).
 __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, long ldb, int nrhs,
                                            int rows) {
+  {
+    int ok = 1;
+    for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
+      const int rr = e & 63, c = e >> 6;
+      double v = 0.0;
+      if (rr < rows) {
+        v = ld_shared_blk(B + rr + (long)c * ldb);
+        if (is_sentinel(v)) ok = 0;
+      }
+      sX[c][rr] = v;
+    }
+    if (__syncthreads_and(ok)) return;
+  }
   if (threadIdx.x == 0) {
     const double* last = B + (rows - 1) + (long)(nrhs - 1) * ldb;
     while (is_sentinel(ld_shared_blk(last))) __builtin_amdgcn_s_sleep(1);
@@ -188,6 +207,28 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
     if (__syncthreads_and(ok)) return;
     __builtin_amdgcn_s_sleep(2);
   }
+}
+
+// The critical hand-off (a block waiting for its immediate predecessor): at most
+// one or two workgroups per shift wait here at a time, so every lane spins on its
+// own elements and the block is complete one round trip after it lands, instead
+// of one round trip for the probe element and another for the block.
+__device__ __forceinline__ void poll_block_spin(double (*sX)[SB], const double* B, long ldb,
+                                                int nrhs, int rows) {
+  for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
+    const int rr = e & 63, c = e >> 6;
+    double v = 0.0;
+    if (rr < rows) {
+      const double* p = B + rr + (long)c * ldb;
+      v = ld_shared_blk(p);
+      while (is_sentinel(v)) {
+        __builtin_amdgcn_s_sleep(1);
+        v = ld_shared_blk(p);
+      }
+    }
+    sX[c][rr] = v;
+  }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(256) void k_fill_sentinel(int n, int nrhs, int nshift,
@@ -264,14 +305,14 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       lnext[q] = (r0 + rr < n) ? LD[r0 + rr + (long)(c0 + kk) * a.ldld] : 0.0;
     }
   };
-  if (b > 1) load_L(0);
-  for (int cb = 0; cb + 1 < b; ++cb) {
+  if (b > 2) load_L(0);
+  for (int cb = 0; cb + 2 < b; ++cb) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = lnext[q];
     }
-    if (cb + 2 < b) load_L(cb + 1);
+    if (cb + 3 < b) load_L(cb + 1);
     poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
@@ -285,7 +326,11 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
     }
     __syncthreads();
   }
-  // P_b = Linv_b acc
+  // the depth-2 block is loaded while P_b = Linv_b acc is formed
+  if (b >= 2) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lnext[q] = Lbase[(3L * nblk + b) * SB * SB + tid + 256 * q];
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int e = tid + 256 * q;
@@ -306,6 +351,25 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
     pb[m] = t;
   }
+  if (b >= 2) {  // P_b -= Mf^2_b Z_{b-2}
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      sM[e & 63][e >> 6] = lnext[q];
+    }
+    poll_block_spin(sZ, Z + (b - 2) * SB, a.ldz, nrhs, SB);
+#pragma unroll
+    for (int m = 0; m < NR / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double t = pb[m];
+#pragma unroll 16
+        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
+        pb[m] = t;
+      }
+    }
+  }
   if (b > 0) {
     __syncthreads();
 #pragma unroll
@@ -313,7 +377,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = mf[q];
     }
-    poll_block(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB);
+    poll_block_spin(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -414,15 +478,15 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       lnext[q] = (c0 + kk < n) ? LD[c0 + kk + (long)(r0 + rr) * a.ldld] : 0.0;
     }
   };
-  if (b + 2 < nblk) load_L(nblk - 1);
-  for (int cb = nblk - 1; cb > b + 1; --cb) {
+  if (b + 3 < nblk) load_L(nblk - 1);
+  for (int cb = nblk - 1; cb > b + 2; --cb) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
       // sM[kk][rr] = L(c0 + kk, r0 + rr)
       sM[e & 63][e >> 6] = lnext[q];
     }
-    if (cb - 1 > b + 1) load_L(cb - 1);
+    if (cb - 1 > b + 2) load_L(cb - 1);
     poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB));
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
@@ -436,7 +500,11 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
     }
     __syncthreads();
   }
-  // P_b = Linv_b^T acc
+  // the depth-2 block is loaded while P_b = Linv_b^T acc is formed
+  if (b + 2 < nblk) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) lnext[q] = Lbase[(4L * nblk + b) * SB * SB + tid + 256 * q];
+  }
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int e = tid + 256 * q;
@@ -457,6 +525,25 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
     pb[m] = tt;
   }
+  if (b + 2 < nblk) {  // P_b -= Mb^2_b V_{b+2}
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int e = tid + 256 * q;
+      sM[e & 63][e >> 6] = lnext[q];
+    }
+    poll_block_spin(sV, V + (b + 2) * SB, a.ldz, nrhs, min(SB, n - (b + 2) * SB));
+#pragma unroll
+    for (int m = 0; m < NR / 4; ++m) {
+      const int c = q0 + 4 * m;
+      if (c < nrhs) {
+        double tt = pb[m];
+#pragma unroll 16
+        for (int k = 0; k < SB; ++k) tt -= sM[i][k] * sV[c][k];
+        pb[m] = tt;
+      }
+    }
+  }
   if (b + 1 < nblk) {
     __syncthreads();
 #pragma unroll
@@ -464,7 +551,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = mb[q];
     }
-    poll_block(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB));
+    poll_block_spin(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB));
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;

@@ -40,10 +40,14 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode = 0);
 void diag_inv_scatter_launch(int n, const double* Linv, double* Li, long ldli, hipStream_t st);
 
 inline long solve_nblk(long n) { return ceil_div(n, kSolveBlock); }
+// Depth of the sweeps' look-ahead: the nearest kSolveLook blocks enter a block's
+// result through precomputed products, the rest through P_b.
+constexpr int kSolveLook = 2;
 // per shift: the 64x64 diagonal-block inverses of L, then the forward and the
-// backward look-ahead blocks (3 * nblk column-major 64x64 blocks)
+// backward look-ahead blocks of each depth ((1 + 2 kSolveLook) * nblk column-major
+// 64x64 blocks)
 inline size_t solve_linv_size(long n) {
-  return 3 * (size_t)solve_nblk(n) * kSolveBlock * kSolveBlock;
+  return (1 + 2 * (size_t)kSolveLook) * (size_t)solve_nblk(n) * kSolveBlock * kSolveBlock;
 }
 
 
