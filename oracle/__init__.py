@@ -23,6 +23,9 @@ in the paper's order and notation, sharing no code with the HIP library:
 * ``prng``     -- SplitMix64, the counter-based generator both sides implement;
 * ``sislice``  -- the per-pencil driver: factor every shift, run Algorithm 2 per
                   probe until its window converges, validate, return the lowest n_e;
+* ``scf``      -- probe migration between SCF steps (k-means clusters mapped to
+                  probes by overlap, merge, delete, insert by 2-means; Section 3.2)
+                  and the partial-trace monitor (Section 3.3);
 * ``adjoint``  -- gradients of a loss of the lowest eigenpairs with respect to A
                   and B (first-order perturbation theory of the pencil of Section 1;
                   not a step of the paper): the sum-over-states definition and the
