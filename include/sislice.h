@@ -286,6 +286,26 @@ sislice_status sislice_kmeans_shifts(const double *ritz, int64_t n, const double
                                      int64_t n_s, int32_t use_kmeanspp, uint64_t seed,
                                      double *new_shifts, int32_t *labels);
 
+/* Probe migration between SCF steps (Sec. 3.2), host only.  The validated values
+ * `ritz` (host double[n]) with the probe that validated each (probe_of, host
+ * int32[n], in [0, n_s)) are clustered by k-means (Lloyd as in
+ * sislice_kmeans_shifts, seeded with prev_shifts or by k-means++); each cluster is
+ * mapped to the probe that validated most of its members (ties: the probe whose
+ * previous shift is nearest the centroid, then the lower index); clusters mapped
+ * to one probe are merged; probes without a cluster are deleted; while fewer than
+ * n_s probes remain, the probe holding the most values is split by 2-means (Lloyd
+ * from its smallest and largest value) and the half whose centroid is nearer that
+ * probe's previous shift stays with it while the other half seeds an inserted
+ * probe.  Outputs: new_shifts host double[n_s] (ascending; the first *n_new are
+ * set, *n_new < n_s only when no probe holds two values), value_probe host
+ * int32[n] (the new probe each value seeds; may be NULL), origin host
+ * int32[n_s] (the previous probe each new probe continues, -1 if inserted; may
+ * be NULL), stats host int32[3] (merged, deleted, inserted; may be NULL). */
+sislice_status sislice_scf_migrate(const double *ritz, const int32_t *probe_of, int64_t n,
+                                   const double *prev_shifts, int64_t n_s, int32_t use_kmeanspp,
+                                   uint64_t seed, double *new_shifts, int32_t *value_probe,
+                                   int32_t *origin, int32_t *n_new, int32_t *stats);
+
 /* Slice validation (Sec. 2.2), host only.  Probe j (shift sigmas[j]) reports
  * counts[j] Ritz values and residual norms stored contiguously from
  * offsets[j] in `thetas` / `resids`.  Slices: (-inf, s_1), [s_j, s_{j+1}) split

@@ -87,6 +87,9 @@ _SIGS = {
     "sislice_tuned_nb": (C.c_int32, [C.c_void_p, C.c_int64]),
     "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
                                         C.c_uint64, c_double_p, c_int32_p]),
+    "sislice_scf_migrate": (C.c_int, [c_double_p, c_int32_p, C.c_int64, c_double_p, C.c_int64,
+                                      C.c_int32, C.c_uint64, c_double_p, c_int32_p, c_int32_p,
+                                      c_int32_p, c_int32_p]),
     "sislice_validate": (C.c_int64, [C.c_int64, c_double_p, c_int64_p, C.c_double, C.c_int64,
                                      c_int64_p, c_int64_p, c_double_p, c_double_p, c_int32_p,
                                      c_int32_p, c_int32_p, c_int32_p]),

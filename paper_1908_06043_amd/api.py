@@ -321,6 +321,30 @@ def kmeans_shifts(ritz, prev_shifts=None, n_s=None, use_kmeanspp=False, seed=0):
     return out, lab
 
 
+def scf_migrate(ritz, probe_of, prev_shifts, use_kmeanspp=False, seed=0):
+    """Probe migration between SCF steps (host): new shifts, the new probe each value
+    seeds, the previous probe each new probe continues (-1: inserted) and the
+    counts (merged, deleted, inserted)."""
+    x = np.ascontiguousarray(np.asarray(ritz, dtype=np.float64))
+    po = np.ascontiguousarray(np.asarray(probe_of, dtype=np.int32))
+    prev = np.ascontiguousarray(np.asarray(prev_shifts, dtype=np.float64))
+    k = prev.size
+    sh = np.zeros(k)
+    vp = np.zeros(x.size, dtype=np.int32)
+    org = np.zeros(k, dtype=np.int32)
+    nn = C.c_int32()
+    stats = np.zeros(3, dtype=np.int32)
+    st = _lib.load().sislice_scf_migrate(x.ctypes.data_as(_lib.c_double_p), po.ctypes.data_as(_lib.c_int32_p),
+                                        x.size, prev.ctypes.data_as(_lib.c_double_p), k,
+                                        int(use_kmeanspp), seed, sh.ctypes.data_as(_lib.c_double_p),
+                                        vp.ctypes.data_as(_lib.c_int32_p), org.ctypes.data_as(_lib.c_int32_p),
+                                        C.byref(nn), stats.ctypes.data_as(_lib.c_int32_p))
+    _check(st, "sislice_scf_migrate")
+    m = nn.value
+    return dict(shifts=sh[:m], value_probe=vp, origin=org[:m], merged=int(stats[0]),
+                deleted=int(stats[1]), inserted=int(stats[2]))
+
+
 def validate(sigmas, nus, thetas, resids, omega_top, nu_top):
     sig = np.ascontiguousarray(np.asarray(sigmas, dtype=np.float64))
     ns = sig.size

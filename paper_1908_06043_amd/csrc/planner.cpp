@@ -147,6 +147,98 @@ void lloyd(const double* x, int64_t n, int k, double* c, int32_t* lab_out, int m
     for (int64_t i = 0; i < n; ++i) lab_out[i] = lab[i];
 }
 
+// ------------------------------------------------------------------ SCF probe migration
+
+static double mean_of(const double* x, const std::vector<int>& idx) {
+  double t = 0.0;
+  for (int i : idx) t += x[i];  // left to right, ascending index
+  return t / (double)idx.size();
+}
+
+ScfMigration scf_migrate(const double* x, const int32_t* probe_of, int64_t n,
+                         const double* prev, int n_s, bool use_kmeanspp, uint64_t seed) {
+  std::vector<double> c(n_s);
+  if (use_kmeanspp)
+    kmeanspp(x, n, n_s, seed, c.data());
+  else
+    for (int j = 0; j < n_s; ++j) c[j] = prev[j];
+  std::sort(c.begin(), c.end());
+  std::vector<int32_t> lab(n);
+  lloyd(x, n, n_s, c.data(), lab.data(), 300);
+  // cluster -> probe of maximal overlap (ties: previous shift nearest the centroid,
+  // then the lower probe); empty clusters map nowhere
+  std::vector<int> cmap(n_s, -1);
+  for (int k = 0; k < n_s; ++k) {
+    std::vector<int64_t> cnt(n_s, 0);
+    int64_t members = 0;
+    for (int64_t i = 0; i < n; ++i)
+      if (lab[i] == k) {
+        ++cnt[probe_of[i]];
+        ++members;
+      }
+    if (members == 0) continue;
+    int best = -1;
+    for (int p = 0; p < n_s; ++p)
+      if (best < 0 || cnt[p] > cnt[best] ||
+          (cnt[p] == cnt[best] && std::fabs(prev[p] - c[k]) < std::fabs(prev[best] - c[k])))
+        best = p;
+    cmap[k] = best;
+  }
+  struct Pr {
+    int origin;
+    double ref;
+    std::vector<int> m;
+  };
+  std::vector<Pr> pr;
+  ScfMigration out;
+  for (int p = 0; p < n_s; ++p) {
+    int nk = 0;
+    for (int k = 0; k < n_s; ++k) nk += cmap[k] == p;
+    if (nk == 0) continue;
+    out.merged += nk - 1;
+    Pr q{p, prev[p], {}};
+    for (int64_t i = 0; i < n; ++i)
+      if (lab[i] >= 0 && cmap[lab[i]] == p) q.m.push_back((int)i);
+    pr.push_back(std::move(q));
+  }
+  out.deleted = n_s - (int)pr.size();
+  while ((int)pr.size() < n_s) {
+    int big = 0;
+    for (int q = 1; q < (int)pr.size(); ++q)
+      if (pr[q].m.size() > pr[big].m.size()) big = q;
+    if (pr[big].m.size() < 2) break;
+    // 2-means of the probe's values from their smallest and largest
+    std::vector<double> v;
+    for (int i : pr[big].m) v.push_back(x[i]);
+    double c2[2] = {*std::min_element(v.begin(), v.end()), *std::max_element(v.begin(), v.end())};
+    std::vector<int32_t> l2(v.size());
+    lloyd(v.data(), (int64_t)v.size(), 2, c2, l2.data(), 300);
+    std::vector<int> lo, hi;
+    for (size_t t = 0; t < v.size(); ++t) (l2[t] == 0 ? lo : hi).push_back(pr[big].m[t]);
+    if (lo.empty() || hi.empty()) break;
+    const double ref = pr[big].ref;
+    const bool keep_lo = std::fabs(mean_of(x, lo) - ref) <= std::fabs(mean_of(x, hi) - ref);
+    std::vector<int> go = keep_lo ? hi : lo;
+    pr[big].m = keep_lo ? lo : hi;
+    Pr nw{-1, mean_of(x, go), go};
+    pr.push_back(std::move(nw));
+    ++out.inserted;
+  }
+  std::vector<double> sh(pr.size());
+  for (size_t q = 0; q < pr.size(); ++q) sh[q] = mean_of(x, pr[q].m);
+  std::vector<int> order(pr.size());
+  for (size_t q = 0; q < pr.size(); ++q) order[q] = (int)q;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sh[a] < sh[b]; });
+  out.value_probe.assign(n, -1);
+  for (size_t r = 0; r < order.size(); ++r) {
+    const Pr& q = pr[order[r]];
+    out.shifts.push_back(sh[order[r]]);
+    out.origin.push_back(q.origin);
+    for (int i : q.m) out.value_probe[i] = (int)r;
+  }
+  return out;
+}
+
 // ------------------------------------------------------------------ validation
 
 int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
@@ -257,6 +349,31 @@ sislice_status sislice_kmeans_shifts(const double* ritz, int64_t n, const double
   }
   if (labels)
     for (int64_t i = 0; i < n; ++i) labels[i] = rank[labels[i]];
+  return SISLICE_OK;
+}
+
+sislice_status sislice_scf_migrate(const double* ritz, const int32_t* probe_of, int64_t n,
+                                   const double* prev_shifts, int64_t n_s, int32_t use_kmeanspp,
+                                   uint64_t seed, double* new_shifts, int32_t* value_probe,
+                                   int32_t* origin, int32_t* n_new, int32_t* stats) {
+  if (!ritz || !probe_of || !prev_shifts || !new_shifts || !n_new || n <= 0 || n_s <= 0 ||
+      n_s > n)
+    return SISLICE_ERR_ARG;
+  for (int64_t i = 0; i < n; ++i)
+    if (probe_of[i] < 0 || probe_of[i] >= n_s) return SISLICE_ERR_ARG;
+  const ScfMigration m = scf_migrate(ritz, probe_of, n, prev_shifts, (int)n_s, use_kmeanspp != 0, seed);
+  *n_new = (int32_t)m.shifts.size();
+  for (size_t r = 0; r < m.shifts.size(); ++r) {
+    new_shifts[r] = m.shifts[r];
+    if (origin) origin[r] = m.origin[r];
+  }
+  if (value_probe)
+    for (int64_t i = 0; i < n; ++i) value_probe[i] = m.value_probe[i];
+  if (stats) {
+    stats[0] = m.merged;
+    stats[1] = m.deleted;
+    stats[2] = m.inserted;
+  }
   return SISLICE_OK;
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <vector>
 
 #include "sislice.h"
 
@@ -24,6 +25,20 @@ void kpm_place(const double* mu, int M, double a, double b, int64_t n, int64_t n
                double top_margin, double* sigmas, double* omega_top);
 void kmeanspp(const double* x, int64_t n, int k, uint64_t seed, double* out);
 void lloyd(const double* x, int64_t n, int k, double* c, int32_t* lab, int max_iter);
+// Probe migration between SCF steps (Section 3.2): k-means of the validated values
+// seeded with the previous shifts (or k-means++), clusters mapped to the probe of
+// maximal overlap, merged, unmapped probes deleted and the largest probe split by
+// 2-means until n_s probes exist again.  Shifts ascending; value_probe[i] = new
+// probe seeded by value i; origin[r] = previous probe continued (-1: inserted).
+struct ScfMigration {
+  std::vector<double> shifts;
+  std::vector<int> origin;
+  std::vector<int> value_probe;
+  int merged = 0, deleted = 0, inserted = 0;
+};
+ScfMigration scf_migrate(const double* x, const int32_t* probe_of, int64_t n, const double* prev,
+                         int n_s, bool use_kmeanspp, uint64_t seed);
+
 int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
                  const int64_t* off, const int64_t* cnt, const double* th, const double* rs,
                  int32_t* scase, int32_t* sexact, int32_t* scand, int32_t* chosen);

@@ -98,3 +98,32 @@ def test_gpu_entry_points_refuse_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         api.handle()
+
+
+def test_scf_migrate_matches_oracle():
+    from oracle import scf as oscf
+    import os
+    gold = {}
+    path = os.path.join(HERE, "golden", "clustermap_example.txt")
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        k, *v = line.split()
+        gold[k] = [float(t) for t in v]
+    out = api.scf_migrate(gold["values"], [int(v) for v in gold["probe_of"]], gold["prev_shifts"])
+    assert list(out["shifts"]) == gold["new_shifts"]
+    assert (out["merged"], out["deleted"], out["inserted"]) == (1, 1, 1)
+    rng = np.random.default_rng(11)
+    for trial in range(40):
+        n_s = int(rng.integers(2, 9))
+        x = rng.uniform(-5, 5, int(rng.integers(3 * n_s, 60)))
+        prev = np.sort(rng.uniform(-6, 6, n_s))
+        po = rng.integers(0, n_s, x.size).astype(np.int32)
+        ref = oscf.migrate_probes(x, po, prev, use_kmeanspp=bool(trial % 3 == 0), seed=trial)
+        got = api.scf_migrate(x, po, prev, use_kmeanspp=bool(trial % 3 == 0), seed=trial)
+        assert np.array_equal(got["shifts"], ref["shifts"])         # bit-exact
+        assert list(got["origin"]) == list(ref["origin"])
+        for r, members in enumerate(ref["members"]):
+            assert all(got["value_probe"][i] == r for i in members)
+        assert (got["merged"], got["deleted"], got["inserted"]) == (
+            ref["merged"], ref["deleted"], ref["inserted"])
