@@ -306,6 +306,49 @@ sislice_status sislice_scf_migrate(const double *ritz, const int32_t *probe_of, 
                                    uint64_t seed, double *new_shifts, int32_t *value_probe,
                                    int32_t *origin, int32_t *n_new, int32_t *stats);
 
+/* SCF sequence (Algorithm 1 over successive pencils; shift migration of
+ * Sec. 3.2, missing eigenvalues and the partial-trace monitor of Sec. 3.3).  The
+ * state keeps the shifts, top boundary, validated eigenvalues, the probe that
+ * validated each, and the eigenvectors (device, owned) of the last step.
+ *   sislice_scf_create: for pencils of order n, the lowest n_e pairs, n_s
+ *     shifts; opts as for sislice_solve; eta_tol (<= 0: 0.05) the relative change
+ *     of the partial trace that sends a step back to the DOS planner.  The state
+ *     holds about (2 n_e + n + 8 n_s) n doubles of device memory.
+ *   sislice_scf_step: one pencil.  The first step plans the shifts by KPM and
+ *     starts every probe from a Gaussian block.  Later steps compare
+ *     eta = tr(X^T A X) of the previous eigenvectors under the previous pencil
+ *     (the sum of the previous eigenvalues) and the new one; within eta_tol the
+ *     shifts migrate (sislice_scf_migrate; k-means++ after a DOS step) and every
+ *     probe starts from the previous eigenvectors of the values that seed it (a
+ *     Gaussian combination of them, or the vectors padded with Gaussian columns
+ *     when fewer than the block size); otherwise, or when the migrated shifts
+ *     miss eigenvalues, the step uses DOS shifts and Gaussian starts.  Outputs as
+ *     for sislice_solve; sigmas host double[n_s] and omega_top host double out
+ *     (may be NULL).  The factorizations stay with the handle for
+ *     sislice_adjoint (report->factor_id).  Synchronises.
+ *   sislice_scf_destroy: frees the state (not the handle). */
+typedef struct sislice_scf sislice_scf;
+typedef struct {
+  int32_t step;          /* 0 for the first pencil                                   */
+  int32_t replanned;     /* 0 migrated shifts, 1 DOS shifts (first step or trace jump), */
+                         /* 2 DOS shifts after the migrated shifts missed eigenvalues  */
+  int32_t merged, deleted, inserted;  /* probe migration counts (sislice_scf_migrate)  */
+  int32_t status_solve;  /* status of the solve                                        */
+  double eta_prev;       /* sum of the previous eigenvalues                            */
+  double eta_new;        /* tr(X_prev^T A X_prev) with the new A                        */
+  int64_t block_steps;   /* block Lanczos steps of the step's solves                   */
+  uint64_t factor_id;
+  double t_solve_ms, t_total_ms;
+} sislice_scf_report;
+
+sislice_status sislice_scf_create(sislice_handle *h, int64_t n, int64_t n_e, int64_t n_s,
+                                  const sislice_opts *opts, double eta_tol, sislice_scf **scf);
+sislice_status sislice_scf_step(sislice_scf *scf, const double *A, int64_t lda, const double *B,
+                                int64_t ldb, double *evals, double *evecs, int64_t ldx,
+                                double *resid, double *sigmas, double *omega_top,
+                                sislice_scf_report *report);
+sislice_status sislice_scf_destroy(sislice_scf *scf);
+
 /* Slice validation (Sec. 2.2), host only.  Probe j (shift sigmas[j]) reports
  * counts[j] Ritz values and residual norms stored contiguously from
  * offsets[j] in `thetas` / `resids`.  Slices: (-inf, s_1), [s_j, s_{j+1}) split

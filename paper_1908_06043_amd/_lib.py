@@ -44,6 +44,13 @@ class AdjointReport(C.Structure):
                 ("flops_outer", C.c_double), ("t_outer_ms", C.c_double)]
 
 
+class ScfReport(C.Structure):
+    _fields_ = [("step", C.c_int32), ("replanned", C.c_int32), ("merged", C.c_int32),
+                ("deleted", C.c_int32), ("inserted", C.c_int32), ("status_solve", C.c_int32),
+                ("eta_prev", C.c_double), ("eta_new", C.c_double), ("block_steps", C.c_int64),
+                ("factor_id", C.c_uint64), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double)]
+
+
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("A", C.c_void_p), ("lda", C.c_int64), ("B", C.c_void_p),
                 ("ldb", C.c_int64), ("n_e", C.c_int64), ("n_s", C.c_int64), ("evals", C.c_void_p),
@@ -85,6 +92,12 @@ _SIGS = {
     "sislice_solve_batched": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Problem), C.POINTER(Opts),
                                         C.c_int32, c_int32_p, C.POINTER(BatchReport)]),
     "sislice_tuned_nb": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "sislice_scf_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(Opts),
+                                     C.c_double, C.POINTER(C.c_void_p)]),
+    "sislice_scf_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, c_double_p,
+                                   c_double_p, C.POINTER(ScfReport)]),
+    "sislice_scf_destroy": (C.c_int, [C.c_void_p]),
     "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
                                         C.c_uint64, c_double_p, c_int32_p]),
     "sislice_scf_migrate": (C.c_int, [c_double_p, c_int32_p, C.c_int64, c_double_p, C.c_int64,

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import AdjointReport, BatchReport, Opts, Problem, Report, SisliceError
+from ._lib import AdjointReport, BatchReport, Opts, Problem, Report, ScfReport, SisliceError
 
 _handles = {}
 
@@ -259,6 +259,55 @@ def solve_batched(pencils, opts=None, workers=0, check=True):
     report = {f: getattr(rep, f) for f, _ in BatchReport._fields_}
     report["status"] = st
     return outs, report
+
+
+class ScfSequence:
+    """A sequence of pencils of order n (the SCF iteration): shifts planned by KPM
+    on the first step and migrated afterwards, probes warm-started from the
+    previous eigenvectors, the partial-trace monitor and the missing-eigenvalue
+    fallback (sislice_scf_*)."""
+
+    def __init__(self, n, n_e, n_s, opts=None, eta_tol=0.0, device=None):
+        self.n, self.n_e, self.n_s = int(n), int(n_e), int(n_s)
+        self._opts = opts or default_opts()
+        self._dev = device
+        p = C.c_void_p()
+        _check(_lib.load().sislice_scf_create(handle(device), self.n, self.n_e, self.n_s,
+                                              C.byref(self._opts), float(eta_tol), C.byref(p)),
+               "sislice_scf_create")
+        self._p = p
+
+    def step(self, A, B, check=True):
+        A = _mat(A, "A")
+        B = _mat(B, "B")
+        n, n_e = self.n, self.n_e
+        ev = torch.empty(n_e, dtype=torch.float64, device=A.device)
+        Xt = torch.empty((n_e, n), dtype=torch.float64, device=A.device)
+        rs = torch.empty(n_e, dtype=torch.float64, device=A.device)
+        sig = np.zeros(self.n_s)
+        top = C.c_double()
+        rep = ScfReport()
+        handle(A.device.index)  # bind the current stream
+        st = _lib.load().sislice_scf_step(self._p, A.data_ptr(), n, B.data_ptr(), n, ev.data_ptr(),
+                                         Xt.data_ptr(), n, rs.data_ptr(),
+                                         sig.ctypes.data_as(_lib.c_double_p), C.byref(top),
+                                         C.byref(rep))
+        if check:
+            _check(st, "sislice_scf_step")
+        report = {f: getattr(rep, f) for f, _ in ScfReport._fields_}
+        return dict(evals=ev, evecs=Xt.t(), resid=rs, status=st, sigmas=sig, omega_top=top.value,
+                    report=report)
+
+    def close(self):
+        if self._p is not None and self._p.value:
+            _lib.load().sislice_scf_destroy(self._p)
+        self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tuned_nb(n, device=None):

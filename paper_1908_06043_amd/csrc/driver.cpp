@@ -436,7 +436,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
                           const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
                           double* evals, double* evecs, int64_t ldx, double* resid_out,
-                          sislice_report* rep) {
+                          sislice_report* rep, const double* start, int32_t* probe_of) {
   const auto t_start = Clock::now();
   const int n = (int)n64;
   const int P = (int)n_s;
@@ -625,8 +625,11 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   unsigned* sync = sync_words(h, (size_t)P + 64);  // one ticket counter per probe
   auto Wj = [&](int j) { return Wall + (size_t)j * n * b; };
   auto Zj = [&](int j) { return Zall + (size_t)j * n * b; };
-  // start blocks: Gaussian from the shared stream, B-orthonormalised (CholeskyQR2)
-  {
+  // start blocks: Gaussian from the shared stream, or the caller's (warm start),
+  // B-orthonormalised (CholeskyQR2)
+  if (start) {
+    SL_HIP(hipMemcpyAsync(Wall, start, sizeof(double) * (size_t)n * b * P, hipMemcpyDeviceToDevice, st));
+  } else {
     std::vector<unsigned long long> seeds(P);
     std::vector<double*> wp(P);
     for (int j = 0; j < P; ++j) {
@@ -1126,12 +1129,16 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     std::vector<const double*> src(nout);
     std::vector<int> scol(nout);
     std::vector<double> v(nout), r(nout);
+    std::vector<int> val_probe(std::max(NL, 1), -1);
+    for (const auto& ch : chunks)
+      for (int i = 0; i < ch.cnt; ++i) val_probe[ch.off + i] = ch.probe;
     for (int q = 0; q < nout; ++q) {
       src[q] = Xf;
       scol[q] = pick[q];
       v[q] = vals[pick[q]];
       r[q] = ress[pick[q]];
       nconv += r[q] <= o.tol;
+      if (probe_of) probe_of[q] = val_probe[pick[q]];
     }
     GatherArgs g;
     g.n = n;
@@ -1241,7 +1248,7 @@ sislice_status sislice_solve(sislice_handle* h, int64_t n, const double* A, int6
     SL_CHECK_ARG(A && B && lda >= n && ldb >= n && omega_top, "bad matrix argument");
     SL_CHECK_ARG(evals && evecs && resid && ldx >= n, "bad output argument");
     return solve_impl(h, n, A, lda, B, ldb, n_e, n_s, sigmas, omega_top, o, evals, evecs, ldx, resid,
-                      report);
+                      report, nullptr, nullptr);
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());
     return e.status;

@@ -179,7 +179,10 @@ DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, lo
                        const double* B, long ldb, const std::vector<double>& pts, int nb);
 
 // The KPM shift planner and the plain per-pencil path (argument checks done by
-// the entry points).
+// the entry points).  solve_impl's optional `start` (device n x 8 n_s, ld n) gives
+// each probe's Lanczos start block (warm start) instead of a Gaussian one, and
+// `probe_of` (host int32[n_e]) receives the probe that validated each returned
+// eigenpair.
 sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                          const sislice_opts& o, double* sig, double* top, double* mom_out,
@@ -188,7 +191,8 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
                           const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
                           double* evals, double* evecs, int64_t ldx, double* resid_out,
-                          sislice_report* rep);
+                          sislice_report* rep, const double* start = nullptr,
+                          int32_t* probe_of = nullptr);
 void check_opts(const sislice_opts& o);
 
 }  // namespace sislice

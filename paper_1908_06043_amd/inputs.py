@@ -274,3 +274,29 @@ def make_pencil_device(n, lam_fn, seed, device, scale=0.05, decay=5.0):
     B = L @ L.T
     B = 0.5 * (B + B.T)
     return A.contiguous(), B.contiguous(), lam
+
+
+def sym_perturbation(n, seed, norm2=1e-3):
+    """E = (G + G^T)/2 with G ~ N(0, 1) entries, scaled to ||E||_2 = norm2 (the SCF
+    sequence's step A_k = A_{k-1} + E_k)."""
+    rng = np.random.default_rng(seed)
+    g = rng.standard_normal((n, n))
+    e = 0.5 * (g + g.T)
+    return np.ascontiguousarray(e * (norm2 / np.max(np.abs(np.linalg.eigvalsh(e)))))
+
+
+def sym_perturbation_device(n, seed, norm2, device, iters=60):
+    """The same construction drawn from torch's generator on ``device``; ||E||_2 by
+    power iteration (for orders where a dense eigensolve on the host is slow)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    G = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+    E = 0.5 * (G + G.T)
+    v = torch.randn(n, generator=g, dtype=torch.float64, device=device)
+    lam = 0.0
+    for _ in range(iters):
+        w = E @ v
+        lam = float(torch.linalg.norm(w))
+        v = w / lam
+    return (E * (norm2 / lam)).contiguous()
