@@ -23,6 +23,10 @@ in the paper's order and notation, sharing no code with the HIP library:
 * ``prng``     -- SplitMix64, the counter-based generator both sides implement;
 * ``sislice``  -- the per-pencil driver: factor every shift, run Algorithm 2 per
                   probe until its window converges, validate, return the lowest n_e;
+* ``dos``      -- the paper's own planner: Gaussian-broadened Lanczos DOS and its
+                  closed-form CDOS (eq. dos, eq. cdos), equal-count roots, and
+                  DOSCluster with refinement, safeguards and DOS-expectation
+                  shifts (Section 3.1);
 * ``scf``      -- probe migration between SCF steps (k-means clusters mapped to
                   probes by overlap, merge, delete, insert by 2-means; Section 3.2)
                   and the partial-trace monitor (Section 3.3);
