@@ -102,7 +102,7 @@ typedef struct {
   int32_t iterations;        /* conjugate-gradient iterations (all columns together)  */
   int32_t reused_factors;    /* 1: the solve's factorizations were reused             */
   int32_t n_groups;          /* groups of at most 8 columns sharing one factorization */
-  int32_t breakdowns;        /* columns stopped by a non-positive curvature p^T K p   */
+  int32_t breakdowns;        /* columns stopped after repeated non-positive curvature */
   double max_rel_residual;   /* max_i ||r_i|| / ||b_i|| of the projected solves        */
   double t_factor_ms;        /* refactorization (0 when reused)                       */
   double t_solve_ms;         /* preconditioned conjugate gradients                    */
@@ -201,7 +201,8 @@ sislice_status sislice_solve(sislice_handle *h, int64_t n, const double *A, int6
  *   M_A = diag(g_evals) + T o F
  *   M_B = -diag(lambda g_evals) - S / 2 - (lambda_i + lambda_j) (T o F) / 2,
  * and column z_i of Z solves (A - lambda_i B) z_i = -(I - B X X^T) g_i with
- * X^T B z_i = 0.  Those solves run as conjugate gradients on the B-orthogonal
+ * X^T B z_i = 0.  Those solves run as flexible (Polak-Ribiere) conjugate
+ * gradients, restarted on a non-positive curvature, on the B-orthogonal
  * complement of X (where A - lambda_i B is positive definite), preconditioned
  * by (A - sigma B)^{-1} for the point sigma nearest lambda_i among those shifts
  * and top boundary that lie below lambda_{n_e+1} (inertia <= n_e: positive
@@ -217,7 +218,7 @@ sislice_status sislice_solve(sislice_handle *h, int64_t n, const double *A, int6
  *                    solve; at least one point must have inertia <= n_e
  *                    (SISLICE_ERR_ARG otherwise).
  *   factor_id        sislice_report.factor_id of that solve, or 0.
- *   tol, max_iter    relative residual target of the solves (<= 0: 1e-11) and
+ *   tol, max_iter    relative residual target of the solves (<= 0: 1e-10) and
  *                    iteration cap (<= 0: 500).
  *   GA, GB           device n x n out (ldga, ldgb >= n), both triangles written.
  *   report           host, may be NULL.
@@ -339,6 +340,7 @@ typedef struct {
   int64_t block_steps;   /* block Lanczos steps of the step's solves                   */
   uint64_t factor_id;
   double t_solve_ms, t_total_ms;
+  int32_t cycles_max;    /* largest number of Lanczos restart cycles of a probe        */
 } sislice_scf_report;
 
 sislice_status sislice_scf_create(sislice_handle *h, int64_t n, int64_t n_e, int64_t n_s,
@@ -368,6 +370,22 @@ double sislice_kpm_cdos(const double *mu, int32_t M, double a, double b, int64_t
 sislice_status sislice_kpm_place(const double *mu, int32_t M, double a, double b, int64_t n,
                                  int64_t n_e, int64_t n_s, double top_margin, double *sigmas,
                                  double *omega_top);
+
+/* The paper's DOS shift selection (Sec. 3.1), host part: from n_v runs of
+ * k-step Lanczos (host theta[r*k + j] Ritz values ascending per run, zeta2 the
+ * squared first components of their eigenvectors), the Gaussian-broadened DOS
+ * phi and its closed-form CDOS Phi (eq. dos, eq. cdos; averaged over the runs;
+ * widths nu_j = d_j / 3 with d_j the larger neighbour gap, floored at
+ * 1e-3 (b - a) / k), the window [a, omega_top] with Phi(omega_top) =
+ * n_e + top_margin n_e / n_s, and n_s shifts: mode 0 equal-count roots and
+ * interval midpoints (eq. cdos_root); mode 1 DOSCluster on 10 k grid points,
+ * merging of intervals with fewer than 2 estimated eigenvalues, refinement of
+ * intervals with more than 50, the safeguards that split or merge to exactly n_s
+ * intervals, and each shift the DOS expectation over its interval.  sigmas host
+ * double[n_s] out ascending, omega_top host double out. */
+sislice_status sislice_dos_plan(const double *theta, const double *zeta2, int32_t k, int32_t nv,
+                                int64_t n, int64_t n_e, int64_t n_s, int32_t mode,
+                                double top_margin, double *sigmas, double *omega_top);
 
 /* SplitMix64 output i of `seed` (counter form): the generator behind every
  * random draw of the library. */

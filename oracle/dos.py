@@ -223,7 +223,7 @@ def plan_cluster(dos, ritz, n_e, n_s, k, top_margin=2.0, big=50.0):
         for iv in I:
             g = _gamma(dos, iv)
             if g > big:
-                nw = max(10, int(round(2.0 * g / total * n_omega)))
+                nw = max(10, int(math.floor(2.0 * g / total * n_omega + 0.5)))
                 sub = dos_cluster(dos, iv[0], iv[1], nw, ritz)
                 if len(sub) >= 2:
                     new.extend(sub)

@@ -48,7 +48,8 @@ class ScfReport(C.Structure):
     _fields_ = [("step", C.c_int32), ("replanned", C.c_int32), ("merged", C.c_int32),
                 ("deleted", C.c_int32), ("inserted", C.c_int32), ("status_solve", C.c_int32),
                 ("eta_prev", C.c_double), ("eta_new", C.c_double), ("block_steps", C.c_int64),
-                ("factor_id", C.c_uint64), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double)]
+                ("factor_id", C.c_uint64), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double),
+                ("cycles_max", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -100,6 +101,9 @@ _SIGS = {
     "sislice_scf_destroy": (C.c_int, [C.c_void_p]),
     "sislice_kmeans_shifts": (C.c_int, [c_double_p, C.c_int64, c_double_p, C.c_int64, C.c_int32,
                                         C.c_uint64, c_double_p, c_int32_p]),
+    "sislice_dos_plan": (C.c_int, [c_double_p, c_double_p, C.c_int32, C.c_int32, C.c_int64,
+                                   C.c_int64, C.c_int64, C.c_int32, C.c_double, c_double_p,
+                                   c_double_p]),
     "sislice_scf_migrate": (C.c_int, [c_double_p, c_int32_p, C.c_int64, c_double_p, C.c_int64,
                                       C.c_int32, C.c_uint64, c_double_p, c_int32_p, c_int32_p,
                                       c_int32_p, c_int32_p]),

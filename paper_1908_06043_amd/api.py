@@ -370,6 +370,21 @@ def kmeans_shifts(ritz, prev_shifts=None, n_s=None, use_kmeanspp=False, seed=0):
     return out, lab
 
 
+def dos_plan(theta, zeta2, n, n_e, n_s, mode=1, top_margin=2.0):
+    """The paper's DOS shift selection from Lanczos Ritz data (host): theta and zeta2
+    of shape (n_v, k).  mode 0: equal-count roots; mode 1: DOSCluster."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    z2 = np.ascontiguousarray(np.asarray(zeta2, dtype=np.float64))
+    nv, k = th.shape
+    sig = np.zeros(n_s)
+    top = C.c_double()
+    st = _lib.load().sislice_dos_plan(th.ctypes.data_as(_lib.c_double_p), z2.ctypes.data_as(_lib.c_double_p),
+                                     k, nv, n, n_e, n_s, mode, top_margin,
+                                     sig.ctypes.data_as(_lib.c_double_p), C.byref(top))
+    _check(st, "sislice_dos_plan")
+    return sig, top.value
+
+
 def scf_migrate(ritz, probe_of, prev_shifts, use_kmeanspp=False, seed=0):
     """Probe migration between SCF steps (host): new shifts, the new probe each value
     seeds, the previous probe each new probe continues (-1: inserted) and the

@@ -239,6 +239,228 @@ ScfMigration scf_migrate(const double* x, const int32_t* probe_of, int64_t n,
   return out;
 }
 
+// ------------------------------------------------------------------ Lanczos DOS
+
+LanczosDos::LanczosDos(const double* theta, const double* zeta2, int k_, int nv_, int64_t n_)
+    : n(n_), k(k_), nv(nv_) {
+  th.assign(theta, theta + (size_t)k * nv);
+  z2.assign(zeta2, zeta2 + (size_t)k * nv);
+  a = *std::min_element(th.begin(), th.end());
+  b = *std::max_element(th.begin(), th.end());
+  const double floor = 1e-3 * (b - a) / k;
+  nu.resize(th.size());
+  for (int r = 0; r < nv; ++r)
+    for (int j = 0; j < k; ++j) {
+      const double* t = th.data() + (size_t)r * k;
+      const double left = j > 0 ? t[j] - t[j - 1] : -1e300;
+      const double right = j + 1 < k ? t[j + 1] - t[j] : -1e300;
+      nu[(size_t)r * k + j] = std::max(std::max(left, right), floor) / 3.0;
+    }
+}
+
+double LanczosDos::phi(double w) const {
+  double tot = 0.0;
+  for (int r = 0; r < nv; ++r) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const size_t q = (size_t)r * k + j;
+      const double kap = (w - th[q]) / (nu[q] * std::sqrt(2.0));
+      s += z2[q] / nu[q] * std::exp(-kap * kap);
+    }
+    tot += s;
+  }
+  return (double)n / std::sqrt(2.0 * M_PI) * tot / nv;
+}
+
+double LanczosDos::cdos(double w) const {
+  double tot = 0.0;
+  for (int r = 0; r < nv; ++r) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const size_t q = (size_t)r * k + j;
+      const double kap = (w - th[q]) / (nu[q] * std::sqrt(2.0));
+      s += z2[q] * (std::erf(kap) + 1.0);
+    }
+    tot += s;
+  }
+  return (double)n / 2.0 * tot / nv;
+}
+
+double LanczosDos::expectation(double l, double u) const {
+  double tot = 0.0;
+  for (int r = 0; r < nv; ++r) {
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) {
+      const size_t q = (size_t)r * k + j;
+      auto psi = [&](double w) {
+        const double kap = (w - th[q]) / (nu[q] * std::sqrt(2.0));
+        return th[q] / 2.0 * std::erf(kap) - nu[q] / std::sqrt(2.0 * M_PI) * std::exp(-kap * kap);
+      };
+      s += z2[q] * (psi(u) - psi(l));
+    }
+    tot += s;
+  }
+  return (double)n * tot / nv / (cdos(u) - cdos(l));
+}
+
+double LanczosDos::root(double target, double lo, double hi) const {
+  if (cdos(lo) - target >= 0) return lo;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (cdos(mid) - target < 0)
+      lo = mid;
+    else
+      hi = mid;
+    if (hi - lo <= 1e-12 * (b - a)) break;
+  }
+  return 0.5 * (lo + hi);
+}
+
+namespace {
+
+using Iv = std::pair<double, double>;
+
+double gamma_of(const LanczosDos& d, const Iv& iv) { return d.cdos(iv.second) - d.cdos(iv.first); }
+
+std::vector<Iv> dos_cluster(const LanczosDos& d, double lo, double hi, int nw) {
+  std::vector<double> w(nw), f(nw);
+  for (int i = 0; i < nw; ++i) {
+    w[i] = lo + (hi - lo) / (nw - 1) * i;
+    f[i] = d.phi(w[i]);
+  }
+  std::vector<int> mx;
+  for (int i = 0; i < nw; ++i)
+    if ((i == 0 || f[i] > f[i - 1]) && (i == nw - 1 || f[i] >= f[i + 1])) mx.push_back(i);
+  if (mx.size() <= 1) return {Iv(lo, hi)};
+  std::vector<double> mu{lo};
+  for (size_t j = 0; j + 1 < mx.size(); ++j) {
+    int best = mx[j];
+    if (mx[j + 1] - mx[j] > 1) {
+      best = mx[j] + 1;
+      for (int t = mx[j] + 1; t < mx[j + 1]; ++t)
+        if (f[t] < f[best]) best = t;
+    }
+    mu.push_back(w[best]);
+  }
+  mu.push_back(hi);
+  std::vector<Iv> out;
+  for (size_t j = 0; j + 1 < mu.size(); ++j) {
+    if (!(mu[j + 1] > mu[j])) continue;
+    bool has = false;
+    for (double t : d.th) has |= t > mu[j] && t <= mu[j + 1];
+    if (has) out.emplace_back(mu[j], mu[j + 1]);
+  }
+  return out;
+}
+
+std::vector<Iv> merge_small(const LanczosDos& d, std::vector<Iv> I, double tol = 2.0) {
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (size_t j = 0; j < I.size(); ++j) {
+      if (I.size() == 1 || gamma_of(d, I[j]) >= tol) continue;
+      std::vector<size_t> cands;
+      if (j > 0 && I[j - 1].second == I[j].first) cands.push_back(j - 1);
+      if (j + 1 < I.size() && I[j + 1].first == I[j].second) cands.push_back(j + 1);
+      if (cands.empty()) continue;
+      size_t t = cands[0];
+      for (size_t q : cands)
+        if (gamma_of(d, I[q]) < gamma_of(d, I[t])) t = q;
+      const Iv m(std::min(I[t].first, I[j].first), std::max(I[t].second, I[j].second));
+      std::vector<Iv> keep;
+      for (size_t q = 0; q < I.size(); ++q)
+        if (q != j && q != t) keep.push_back(I[q]);
+      keep.push_back(m);
+      std::sort(keep.begin(), keep.end());
+      I = keep;
+      changed = true;
+      break;
+    }
+  }
+  return I;
+}
+
+}  // namespace
+
+void dos_plan(const LanczosDos& d, int64_t n_e, int64_t n_s, int mode, double top_margin,
+              double* sigmas, double* omega_top) {
+  const double span = d.b - d.a;
+  const double a = d.a - 0.01 * span;
+  const double top = d.root((double)n_e + top_margin * (double)n_e / (double)n_s, a, d.b + 0.01 * span);
+  *omega_top = top;
+  if (mode == 0) {
+    const double pa = d.cdos(a);
+    const double K = (d.cdos(top) - pa) / (double)n_s;
+    std::vector<double> pts{a};
+    for (int64_t j = 1; j < n_s; ++j) pts.push_back(d.root(pa + (double)j * K, a, top));
+    pts.push_back(top);
+    for (int64_t j = 0; j < n_s; ++j) sigmas[j] = 0.5 * (pts[j] + pts[j + 1]);
+    return;
+  }
+  const int nw = 10 * d.k;
+  const double total = gamma_of(d, Iv(a, top));
+  std::vector<Iv> I = dos_cluster(d, a, top, nw);
+  for (int round = 0; round < 20; ++round) {
+    I = merge_small(d, I);
+    std::vector<Iv> nwI;
+    bool grew = false;
+    for (const Iv& iv : I) {
+      const double g = gamma_of(d, iv);
+      if (g > 50.0) {
+        const int nw2 = std::max(10, (int)std::floor(2.0 * g / total * nw + 0.5));
+        std::vector<Iv> sub = dos_cluster(d, iv.first, iv.second, nw2);
+        if (sub.size() >= 2) {
+          nwI.insert(nwI.end(), sub.begin(), sub.end());
+          grew = true;
+          continue;
+        }
+      }
+      nwI.push_back(iv);
+    }
+    std::sort(nwI.begin(), nwI.end());
+    I = nwI;
+    if (!grew) break;
+  }
+  while ((int64_t)I.size() < n_s) {
+    size_t j = 0;
+    for (size_t q = 1; q < I.size(); ++q)
+      if (gamma_of(d, I[q]) > gamma_of(d, I[j])) j = q;
+    const double l = I[j].first, u = I[j].second;
+    const double mid = d.root(0.5 * (d.cdos(l) + d.cdos(u)), l, u);
+    std::vector<Iv> nwI(I.begin(), I.begin() + j);
+    nwI.emplace_back(l, mid);
+    nwI.emplace_back(mid, u);
+    nwI.insert(nwI.end(), I.begin() + j + 1, I.end());
+    std::sort(nwI.begin(), nwI.end());
+    I = nwI;
+  }
+  while ((int64_t)I.size() > n_s) {
+    size_t j = 0;
+    for (size_t q = 1; q < I.size(); ++q)
+      if (gamma_of(d, I[q]) < gamma_of(d, I[j])) j = q;
+    std::vector<size_t> cands, adj;
+    if (j > 0) cands.push_back(j - 1);
+    if (j + 1 < I.size()) cands.push_back(j + 1);
+    for (size_t q : cands)
+      if (I[q].second == I[j].first || I[q].first == I[j].second) adj.push_back(q);
+    const std::vector<size_t>& pool = adj.empty() ? cands : adj;
+    size_t t = pool[0];
+    for (size_t q : pool)
+      if (gamma_of(d, I[q]) < gamma_of(d, I[t])) t = q;
+    const Iv m(std::min(I[t].first, I[j].first), std::max(I[t].second, I[j].second));
+    std::vector<Iv> keep;
+    for (size_t q = 0; q < I.size(); ++q)
+      if (q != j && q != t) keep.push_back(I[q]);
+    keep.push_back(m);
+    std::sort(keep.begin(), keep.end());
+    I = keep;
+  }
+  std::vector<double> sh;
+  for (const Iv& iv : I) sh.push_back(d.expectation(iv.first, iv.second));
+  std::sort(sh.begin(), sh.end());
+  for (int64_t j = 0; j < n_s; ++j) sigmas[j] = sh[j];
+}
+
 // ------------------------------------------------------------------ validation
 
 int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
@@ -349,6 +571,17 @@ sislice_status sislice_kmeans_shifts(const double* ritz, int64_t n, const double
   }
   if (labels)
     for (int64_t i = 0; i < n; ++i) labels[i] = rank[labels[i]];
+  return SISLICE_OK;
+}
+
+sislice_status sislice_dos_plan(const double* theta, const double* zeta2, int32_t k, int32_t nv,
+                                int64_t n, int64_t n_e, int64_t n_s, int32_t mode,
+                                double top_margin, double* sigmas, double* omega_top) {
+  if (!theta || !zeta2 || !sigmas || !omega_top || k < 2 || nv < 1 || n < 1 || n_e < 1 ||
+      n_s < 1 || (mode != 0 && mode != 1))
+    return SISLICE_ERR_ARG;
+  const LanczosDos d(theta, zeta2, k, nv, n);
+  dos_plan(d, n_e, n_s, mode, top_margin, sigmas, omega_top);
   return SISLICE_OK;
 }
 

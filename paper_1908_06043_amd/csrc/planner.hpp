@@ -39,6 +39,25 @@ struct ScfMigration {
 ScfMigration scf_migrate(const double* x, const int32_t* probe_of, int64_t n, const double* prev,
                          int n_s, bool use_kmeanspp, uint64_t seed);
 
+// The paper's Lanczos DOS estimate (Section 3.1, eq. dos / cdos) from n_v runs of
+// k-step Lanczos (Ritz values theta and squared first components zeta2, run r at
+// offset r * k), with widths nu = d / 3 (d = the larger neighbour gap, floored at
+// 1e-3 (b - a) / k), and the two planners: equal-count roots (mode 0) and
+// DOSCluster with refinement, safeguards and DOS-expectation shifts (mode 1).
+struct LanczosDos {
+  int64_t n = 0;
+  int k = 0, nv = 0;
+  double a = 0, b = 0;
+  std::vector<double> th, z2, nu;  // nv * k each
+  LanczosDos(const double* theta, const double* zeta2, int k, int nv, int64_t n);
+  double phi(double w) const;
+  double cdos(double w) const;
+  double expectation(double l, double u) const;
+  double root(double target, double lo, double hi) const;
+};
+void dos_plan(const LanczosDos& d, int64_t n_e, int64_t n_s, int mode, double top_margin,
+              double* sigmas, double* omega_top);
+
 int64_t validate(int64_t ns, const double* sig, const int64_t* nu, double omega_top, int64_t nu_top,
                  const int64_t* off, const int64_t* cnt, const double* th, const double* rs,
                  int32_t* scase, int32_t* sexact, int32_t* scand, int32_t* chosen);

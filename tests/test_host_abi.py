@@ -127,3 +127,25 @@ def test_scf_migrate_matches_oracle():
             assert all(got["value_probe"][i] == r for i in members)
         assert (got["merged"], got["deleted"], got["inserted"]) == (
             ref["merged"], ref["deleted"], ref["inserted"])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_dos_plan_matches_oracle(mode):
+    from oracle import dos as odos
+    from oracle.kpm import Operator
+    from paper_1908_06043_amd import inputs
+    for P, n_e, n_s, k in ((inputs.pencil_clusters4(200, 0), 40, 4, 40),
+                           (inputs.pencil_scf(600, 60, seed=3), 60, 6, 60)):
+        runs = odos.lanczos_runs(Operator(P.A, P.B), k, 4, seed=1)
+        d = odos.LanczosDOS(runs, P.n, k)
+        if mode == 0:
+            ref, top = odos.plan_cdos(d, n_e, n_s)
+        else:
+            ritz = np.concatenate([th for th, _ in runs])
+            ref, top, _ = odos.plan_cluster(d, ritz, n_e, n_s, k)
+        th = np.stack([t for t, _ in runs])
+        z2 = np.stack([z for _, z in runs])
+        sig, top2 = api.dos_plan(th, z2, P.n, n_e, n_s, mode=mode)
+        scale = np.max(np.abs(th))
+        assert abs(top2 - top) <= 1e-12 * scale
+        assert np.max(np.abs(sig - ref)) <= 1e-12 * scale
