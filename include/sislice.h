@@ -168,6 +168,21 @@ sislice_status sislice_plan_shifts_kpm(sislice_handle *h, int64_t n, const doubl
                                        const sislice_opts *opts, double *sigmas, double *omega_top,
                                        double *moments, double *bounds);
 
+/* The paper's own shift selection (Sec. 3.1): nv runs of k-step Lanczos (full
+ * reorthogonalisation, Gaussian starts from the SplitMix64 stream of
+ * opts->seed) on L_B^{-1} A L_B^{-T}, their Ritz values and the squared first
+ * components of the Ritz vectors, then the planning of sislice_dos_plan with
+ * mode 0 (equal-count roots of the Lanczos CDOS) or 1 (DOSCluster, refinement,
+ * safeguards, DOS-expectation shifts) and opts->top_margin.
+ *   k in [2, 112], nv in [1, 32].
+ *   sigmas host double[n_s] out ascending, omega_top host double out, bounds
+ *   host double[2] out (the extreme Ritz values; may be NULL).  Synchronises. */
+sislice_status sislice_plan_shifts_lanczos(sislice_handle *h, int64_t n, const double *A,
+                                           int64_t lda, const double *B, int64_t ldb, int64_t n_e,
+                                           int64_t n_s, const sislice_opts *opts, int32_t mode,
+                                           int32_t k, int32_t nv, double *sigmas, double *omega_top,
+                                           double *bounds);
+
 /* The plain per-pencil path (Algorithm 1, one pass on a fixed pencil): factor
  * every shift and the top boundary, read the inertias, run block shift-invert
  * Lanczos in the B inner product per shift (b = opts->block, thick restart with

@@ -81,6 +81,10 @@ _SIGS = {
                                           C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                                           C.POINTER(Opts), c_double_p, c_double_p, c_double_p,
                                           c_double_p]),
+    "sislice_plan_shifts_lanczos": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                              C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
+                                              C.POINTER(Opts), C.c_int32, C.c_int32, C.c_int32,
+                                              c_double_p, c_double_p, c_double_p]),
     "sislice_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                 C.c_int64, C.c_int64, C.c_int64, c_double_p, c_double_p,
                                 C.POINTER(Opts), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,

@@ -150,6 +150,24 @@ def plan_shifts_kpm(A, B, n_e, n_s, opts=None):
     return dict(sigmas=sig, omega_top=top.value, mu=mom, a=bnd[0], b=bnd[1])
 
 
+def plan_shifts_lanczos(A, B, n_e, n_s, mode=1, k=80, nv=8, opts=None):
+    """The paper's Lanczos DOS shift selection (mode 0: equal-count roots, mode 1:
+    DOSCluster with refinement and expectation shifts)."""
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n = A.shape[0]
+    o = opts or default_opts()
+    sig = np.zeros(n_s)
+    top = C.c_double()
+    bnd = np.zeros(2)
+    st = _lib.load().sislice_plan_shifts_lanczos(handle(A.device.index), n, A.data_ptr(), n,
+                                                B.data_ptr(), n, n_e, n_s, C.byref(o), mode, k, nv,
+                                                sig.ctypes.data_as(_lib.c_double_p), C.byref(top),
+                                                bnd.ctypes.data_as(_lib.c_double_p))
+    _check(st, "sislice_plan_shifts_lanczos")
+    return dict(sigmas=sig, omega_top=top.value, a=bnd[0], b=bnd[1])
+
+
 def solve(A, B, n_e, n_s, sigmas=None, omega_top=None, opts=None, check=True):
     """Lowest n_e eigenpairs of (A, B).  Returns dict with evals, evecs (n x n_e view),
     resid, status and the report."""

@@ -137,8 +137,9 @@ sislice_status adjoint_impl(sislice_handle* h, int n, const double* A, long lda,
   for (int q = 0; q < 4; ++q) z.take<double>((size_t)n * NP);  // R, Y, Z, Q
   z.take<double>((size_t)2 * n * NP);                          // Pst
   z.take<double>((size_t)m * NP);                              // projection coefficients
-  for (int q = 0; q < 4; ++q) z.take<double>(NP);              // lamc, rho, bn2, rrel
+  for (int q = 0; q < 5; ++q) z.take<double>(NP);              // lamc, rho, bn2, rrel, ryo
   z.take<int>(NP);                                             // act
+  z.take<int>(NP);                                             // restarts
   z.take<int>(NP);                                             // col_of
   z.take<int>(m);                                              // slot
   z.take<double>((size_t)G * n * kAdjGroup);                   // sweep scratch Z
@@ -161,7 +162,9 @@ sislice_status adjoint_impl(sislice_handle* h, int n, const double* A, long lda,
   double* rho = cv.take<double>(NP);
   double* bn2 = cv.take<double>(NP);
   double* rrel = cv.take<double>(NP);
+  double* ryo = cv.take<double>(NP);
   int* act = cv.take<int>(NP);
+  int* nrest = cv.take<int>(NP);
   int* d_col = cv.take<int>(NP);
   int* d_slot = cv.take<int>(m);
   double* Zs = cv.take<double>((size_t)G * n * kAdjGroup);
@@ -235,6 +238,8 @@ sislice_status adjoint_impl(sislice_handle* h, int n, const double* A, long lda,
     pa.rho = rho;
     pa.bn2 = bn2;
     pa.rrel = rrel;
+    pa.ryo = ryo;
+    pa.nrest = nrest;
     pa.act = act;
     pa.tol2 = tol * tol;
     precondition();
@@ -249,7 +254,7 @@ sislice_status adjoint_impl(sislice_handle* h, int n, const double* A, long lda,
       if (it % kAdjCheck == 0 || it == max_iter) {
         SL_HIP(hipMemcpyAsync(hact.data(), act, sizeof(int) * NP, hipMemcpyDeviceToHost, st));
         SL_HIP(hipStreamSynchronize(st));
-        if (std::none_of(hact.begin(), hact.end(), [](int v) { return v == 1; })) break;
+        if (std::none_of(hact.begin(), hact.end(), [](int v) { return v == 1 || v == 3; })) break;
       }
     }
     // Z on the complement (removes the rounding drift along X)
@@ -263,7 +268,7 @@ sislice_status adjoint_impl(sislice_handle* h, int n, const double* A, long lda,
     for (int t = 0; t < NP; ++t) {
       if (col_of[t] < 0) continue;
       breakdowns += hact[t] == 2;
-      still += hact[t] == 1;
+      still += hact[t] == 1 || hact[t] == 3;
       maxrel = std::max(maxrel, std::sqrt(std::max(hrel[t], 0.0)));
     }
     t_solve = ms_since(t0);
@@ -316,7 +321,7 @@ extern "C" sislice_status sislice_adjoint(sislice_handle* h, int64_t n, const do
     SL_CHECK_ARG(!g_evecs || ldg >= n, "ldg must be >= n");
     SL_CHECK_ARG(GA && GB && ldga >= n && ldgb >= n, "bad gradient argument");
     SL_CHECK_ARG(std::isfinite(omega_top), "omega_top must be finite");
-    if (!(tol > 0.0)) tol = 1e-11;
+    if (!(tol > 0.0)) tol = 1e-10;
     if (max_iter <= 0) max_iter = 500;
     return adjoint_impl(h, (int)n, A, lda, B, ldb, (int)n_e, evals, evecs, ldx, g_evals, g_evecs,
                         ldg, (int)n_s, sigmas, omega_top, factor_id, tol, max_iter, GA, ldga, GB,

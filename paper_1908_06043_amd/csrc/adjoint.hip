@@ -117,6 +117,7 @@ __global__ __launch_bounds__(256) void k_pcg_init(PcgArgs a) {
     a.bn2[t] = rr;
     a.rrel[t] = rr > 0.0 ? 1.0 : 0.0;
     a.act[t] = rr > 0.0 ? 1 : 0;
+    a.nrest[t] = 0;
   }
 }
 
@@ -135,18 +136,24 @@ __global__ __launch_bounds__(256) void k_pcg_alpha(PcgArgs a) {
   const double* Q = a.Q + t * a.ldq;
   double* Z = a.Z + t * a.ld;
   double* R = a.R + t * a.ld;
+  const double* Y = a.Y + t * a.ld;
   double pq = 0.0;
   for (long i = threadIdx.x; i < n; i += 256) pq += P[i] * Q[i];
   pq = block_sum(pq, red);
-  if (!(pq > 0.0)) {  // the operator is positive definite on the search space
-    if (threadIdx.x == 0) a.act[t] = 2;
+  if (!(pq > 0.0)) {  // positive definite in exact arithmetic: restart the direction
+    if (threadIdx.x == 0) a.act[t] = 3;
     return;
   }
   const double al = a.rho[t] / pq;
+  double ryo = 0.0;
   for (long i = threadIdx.x; i < n; i += 256) {
     Z[i] += al * P[i];
-    R[i] -= al * Q[i];
+    const double r = R[i] - al * Q[i];
+    R[i] = r;
+    ryo += r * Y[i];
   }
+  ryo = block_sum(ryo, red);
+  if (threadIdx.x == 0) a.ryo[t] = ryo;
 }
 
 void pcg_alpha_launch(const PcgArgs& a, hipStream_t st) {
@@ -158,7 +165,8 @@ void pcg_alpha_launch(const PcgArgs& a, hipStream_t st) {
 __global__ __launch_bounds__(256) void k_pcg_beta(PcgArgs a) {
   __shared__ double red[4];
   const int t = blockIdx.x;
-  if (a.act[t] != 1) return;
+  const int st = a.act[t];
+  if (st != 1 && st != 3) return;
   const long n = a.n;
   double* P = a.Pst + t * a.ldp;
   const double* R = a.R + t * a.ld;
@@ -180,7 +188,17 @@ __global__ __launch_bounds__(256) void k_pcg_beta(PcgArgs a) {
     }
     return;
   }
-  const double be = ry / a.rho[t];
+  double be = 0.0;
+  if (st == 1) {
+    be = (ry - a.ryo[t]) / a.rho[t];  // Polak-Ribiere
+    if (!(be > 0.0)) be = 0.0;
+  } else if (a.nrest[t] >= kPcgMaxRestarts) {
+    if (threadIdx.x == 0) {
+      a.act[t] = 2;
+      a.rrel[t] = rr / b2;
+    }
+    return;
+  }
   for (long i = threadIdx.x; i < n; i += 256) {
     const double p = Y[i] + be * P[i];
     P[i] = p;
@@ -189,6 +207,10 @@ __global__ __launch_bounds__(256) void k_pcg_beta(PcgArgs a) {
   if (threadIdx.x == 0) {
     a.rho[t] = ry;
     a.rrel[t] = rr / b2;
+    if (st == 3) {
+      a.act[t] = 1;
+      ++a.nrest[t];
+    }
   }
 }
 

@@ -18,11 +18,14 @@ void adj_mid_launch(int m, const double* lam, const double* glam, const double* 
 void adj_rhs_launch(int n, int np, const int* col_of, const double* E, long lde, const double* G,
                     long ldg, const double* lam, double* R, long ldr, double* lamc, hipStream_t st);
 
-// Column-wise preconditioned conjugate gradients, one workgroup per column.
-// Pst (2n x np, ldp) holds the search directions P on rows [0, n) and -lam_t P
-// on rows [n, 2n), so that Q = [A B] Pst is (A - lam_t B) P in one product.
-// act[t]: 1 iterating, 0 converged (or zero right-hand side), 2 stopped by a
-// non-positive curvature.
+// Column-wise flexible preconditioned conjugate gradients (Polak-Ribiere beta,
+// which tolerates the rounding of the shift-invert preconditioner), one
+// workgroup per column.  Pst (2n x np, ldp) holds the search directions P on rows
+// [0, n) and -lam_t P on rows [n, 2n), so that Q = [A B] Pst is (A - lam_t B) P
+// in one product.  act[t]: 1 iterating, 0 converged (or zero right-hand side),
+// 3 restart requested (a non-positive curvature p^T Q: the direction restarts
+// from the preconditioned residual), 2 stopped after kPcgMaxRestarts restarts.
+constexpr int kPcgMaxRestarts = 8;
 struct PcgArgs {
   int n = 0, np = 0;
   double* Pst = nullptr;
@@ -37,6 +40,8 @@ struct PcgArgs {
   double* rho = nullptr;   // r^T y
   double* bn2 = nullptr;   // ||b||^2
   double* rrel = nullptr;  // ||r||^2 / ||b||^2
+  double* ryo = nullptr;   // r_{k+1}^T y_k (the Polak-Ribiere correction)
+  int* nrest = nullptr;    // restarts taken
   int* act = nullptr;
   double tol2 = 0.0;       // converged when ||r||^2 <= tol2 ||b||^2
 };

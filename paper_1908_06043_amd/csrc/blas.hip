@@ -503,6 +503,27 @@ void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, d
   SL_LAUNCH_CHECK();
 }
 
+// Y[:, c] = X[:, c] / sqrt(s2[c]) for ncol columns (zero when s2 <= 0), rec[c] = sqrt(s2[c]).
+__global__ __launch_bounds__(256) void k_scale_cols(int n, const double* __restrict__ s2,
+                                                    const double* __restrict__ X, long ldx,
+                                                    double* __restrict__ Y, long ldy,
+                                                    double* __restrict__ rec) {
+  const int c = blockIdx.y;
+  const double nr = sqrt(fmax(s2[c], 0.0));
+  const double f = nr > 0.0 ? 1.0 / nr : 0.0;
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
+    Y[i + (long)c * ldy] = X[i + (long)c * ldx] * f;
+  if (rec && blockIdx.x == 0 && threadIdx.x == 0) rec[c] = nr;
+}
+
+void scale_cols_launch(int n, int ncol, const double* s2, const double* X, long ldx, double* Y,
+                       long ldy, double* rec, hipStream_t st) {
+  if (n <= 0 || ncol <= 0) return;
+  SL_LAUNCH(k_scale_cols, dim3((unsigned)std::min<long>(ceil_div(n, 256), 64), ncol), dim3(256), 0,
+            st, n, s2, X, ldx, Y, ldy, rec);
+  SL_LAUNCH_CHECK();
+}
+
 // Out-of-place transpose T = S^T of an n x n matrix, 32 x 32 tiles through LDS.
 __global__ __launch_bounds__(256) void k_transpose(int n, const double* __restrict__ S, long lds,
                                                    double* __restrict__ T, long ldt) {

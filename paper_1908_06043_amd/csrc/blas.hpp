@@ -45,6 +45,9 @@ void lincomb3_launch(long tot, double f1, const double* X, double f2, const doub
 void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, double* rec,
                           hipStream_t st);
 void transpose_launch(int n, const double* S, long lds, double* T, long ldt, hipStream_t st);
+// Y[:, c] = X[:, c] / sqrt(s2[c]) (ncol columns), rec[c] = sqrt(s2[c]) (may be null).
+void scale_cols_launch(int n, int ncol, const double* s2, const double* X, long ldx, double* Y,
+                       long ldy, double* rec, hipStream_t st);
 
 // Batched tall-skinny products with 8 columns (the Lanczos block):
 //   tsmt: C_b (m_b x 8, ldc) = alpha V_b^T X_b          (V_b n x m_b, X_b n x 8)

@@ -39,6 +39,7 @@ struct ProbeHost {
   int64_t need = 0;
   int mq = 0;        // active basis columns incl. the newest block
   int nl = 0;        // locked columns
+  int64_t nin = 0;   // locked columns with values inside the probe's window
   bool active = true;
   bool broke = false;
   int cycles = 0;
@@ -109,9 +110,10 @@ void check_opts(const sislice_opts& o) {
 sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                          const sislice_opts& o, double* sig, double* top, double* mom_out,
-                         double* bounds_out) {
+                         double* bounds_out, int dos_mode, int dos_k, int dos_nv) {
   const int n = (int)n64;
-  const int nv = o.kpm_vectors, M = o.kpm_moments, bs = o.bounds_steps;
+  const int nv = dos_mode >= 0 ? std::max(o.kpm_vectors, dos_nv) : o.kpm_vectors;
+  const int M = o.kpm_moments, bs = o.bounds_steps;
   hipStream_t st = h->stream;
   Ring ring(h);
   Ctx c{h, st, &ring};
@@ -133,6 +135,11 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   z.take<double>(8192);                   // small scalars
   z.take<double>(skinny_partial_size(n, std::max(nv, 1)));
   z.take<int>(64);
+  const int dk = dos_mode >= 0 ? std::min(dos_k, n) : 0;  // Lanczos DOS steps
+  if (dos_mode >= 0) {
+    z.take<double>((size_t)n * dos_nv * (dk + 1));  // the runs' bases, block j = n x nv
+    z.take<double>((size_t)(dk + 1) * dos_nv * 4);  // alpha, s2, beta, coefficients
+  }
   Carver cv(ws_get(h, kBufKpm, z.off));
   double* Af = cv.take<double>((size_t)n * n);
   double* LDB = cv.take<double>((size_t)n * n);
@@ -154,6 +161,8 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   double* small = cv.take<double>(8192);
   double* spart = cv.take<double>(skinny_partial_size(n, std::max(nv, 1)));
   int* iflag = cv.take<int>(64);
+  double* Vd = dos_mode >= 0 ? cv.take<double>((size_t)n * dos_nv * (dk + 1)) : nullptr;
+  double* dsc2 = dos_mode >= 0 ? cv.take<double>((size_t)(dk + 1) * dos_nv * 4) : nullptr;
   SL_CHECK_ARG(nv >= 1 && nv <= kSkinnyMaxCol, "kpm_vectors must be in [1, 32]");
   SL_HIP(hipMemsetAsync(iflag, 0, 64 * sizeof(int), st));
   sym_full_launch(n, A, lda, Af, n, st);
@@ -214,6 +223,107 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     skinny_launch(n, k, Af, n, 0, X1, n, 1.0, 0.0, X3, n, spart, st);
     skinny_launch(n, k, Mi, n, 1, X3, n, 1.0, 0.0, out, n, spart, st);
   };
+  if (dos_mode >= 0) {
+    // ---- the paper's DOS estimate (Section 3.1): dos_nv runs of dk-step Lanczos on
+    // H, advanced together (one application of H serves every run), each with full
+    // reorthogonalisation against its own basis; alpha, beta read at the end
+    const int R = dos_nv;
+    double* d_alpha = dsc2;                              // [dk][R]
+    double* d_s2 = dsc2 + (size_t)(dk + 1) * R;          // [dk + 1][R]
+    double* d_beta = dsc2 + (size_t)2 * (dk + 1) * R;    // [dk][R]
+    double* d_coef = dsc2 + (size_t)3 * (dk + 1) * R;    // [R][dk + 1]
+    const long ldv = (long)n * R;  // run r's j-th vector at Vd + j * ldv + r * n
+    std::vector<unsigned long long> sd{rng_derive(o.seed, kTagDos)};
+    gauss_launch(n, R, 1, ring.vec(sd), ring.ptrs(std::vector<double*>{Vd}), n, st);
+    ColDotArgs cr;
+    cr.n = n;
+    cr.ncol0 = R;
+    cr.mode = 0;
+    cr.partial = static_cast<double*>(ws_get(h, kBufEig, sizeof(double) * coldot_partial_size(n, 1, R)));
+    auto dotR = [&](const double* x, const double* y, double* out) {
+      ColDotArgs d = cr;
+      d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+      d.ldx = n;
+      d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+      d.ldy = n;
+      d.out = ring.ptrs(std::vector<double*>{out});
+      coldot_launch(d, 1, R, st);
+    };
+    dotR(Vd, Vd, d_s2 + (size_t)dk * R);
+    scale_cols_launch(n, R, d_s2 + (size_t)dk * R, Vd, n, Vd, n, nullptr, st);
+    for (int j = 0; j < dk; ++j) {
+      double* vj = Vd + (size_t)j * ldv;
+      apply_H(vj, X2, R);
+      dotR(vj, X2, d_alpha + (size_t)j * R);
+      std::vector<int> mj(R, j + 1), one(R, 1), nn(R, n);
+      std::vector<const double*> bas(R), wc(R), cc(R);
+      std::vector<double*> co(R), wo(R);
+      for (int r = 0; r < R; ++r) {
+        bas[r] = Vd + (size_t)r * n;
+        wc[r] = X2 + (size_t)r * n;
+        wo[r] = X2 + (size_t)r * n;
+        co[r] = d_coef + (size_t)r * (dk + 1);
+        cc[r] = d_coef + (size_t)r * (dk + 1);
+      }
+      for (int pass = 0; pass < 2; ++pass) {  // w_r -= V_r (V_r^T w_r)
+        gemm(c, true, false, mj, one, nn, bas, ldv, wc, n, co, dk + 1, 1.0, 0.0);
+        gemm(c, false, false, nn, one, mj, bas, ldv, cc, dk + 1, wo, n, -1.0, 1.0);
+      }
+      dotR(X2, X2, d_s2 + (size_t)j * R);
+      scale_cols_launch(n, R, d_s2 + (size_t)j * R, X2, n, Vd + (size_t)(j + 1) * ldv, n,
+                        d_beta + (size_t)j * R, st);
+    }
+    std::vector<double> al((size_t)dk * R), be((size_t)dk * R);
+    SL_HIP(hipMemcpyAsync(al.data(), d_alpha, sizeof(double) * al.size(), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(be.data(), d_beta, sizeof(double) * be.size(), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    // Ritz pairs of the R tridiagonals on the device eigensolver
+    SL_CHECK_ARG(dk <= kEigMax, "Lanczos DOS steps must be <= 112");
+    std::vector<double> Th((size_t)R * dk * dk, 0.0);
+    for (int r = 0; r < R; ++r)
+      for (int j = 0; j < dk; ++j) {
+        double* T = Th.data() + (size_t)r * dk * dk;
+        T[j + (size_t)j * dk] = al[(size_t)j * R + r];
+        if (j + 1 < dk) T[(j + 1) + (size_t)j * dk] = T[j + (size_t)(j + 1) * dk] = be[(size_t)j * R + r];
+      }
+    double* dT = static_cast<double*>(ws_get(h, kBufMisc, sizeof(double) * ((size_t)2 * R * dk * dk + (size_t)R * dk)));
+    double* dS = dT + (size_t)R * dk * dk;
+    double* dW = dS + (size_t)R * dk * dk;
+    SL_HIP(hipMemcpyAsync(dT, Th.data(), sizeof(double) * Th.size(), hipMemcpyHostToDevice, st));
+    std::vector<double*> pT(R), pS(R), pW(R);
+    for (int r = 0; r < R; ++r) {
+      pT[r] = dT + (size_t)r * dk * dk;
+      pS[r] = dS + (size_t)r * dk * dk;
+      pW[r] = dW + (size_t)r * dk;
+    }
+    EigArgs e;
+    e.m = ring.vec(std::vector<int>(R, dk));
+    e.A = ring.cptrs(pT);
+    e.lda = dk;
+    e.W = ring.ptrs(pW);
+    e.V = ring.ptrs(pS);
+    e.ldv = dk;
+    eig_launch(e, R, dk, st);
+    std::vector<double> thv((size_t)R * dk), Sv((size_t)R * dk * dk);
+    SL_HIP(hipMemcpyAsync(thv.data(), dW, sizeof(double) * thv.size(), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipMemcpyAsync(Sv.data(), dS, sizeof(double) * Sv.size(), hipMemcpyDeviceToHost, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    std::vector<double> z2((size_t)R * dk);
+    for (int r = 0; r < R; ++r)
+      for (int j = 0; j < dk; ++j) {
+        const double g = Sv[(size_t)r * dk * dk + (size_t)j * dk];  // first component of vector j
+        z2[(size_t)r * dk + j] = g * g;
+      }
+    const LanczosDos d(thv.data(), z2.data(), dk, R, n);
+    dos_plan(d, n_e, n_s, dos_mode, o.top_margin, sig, top);
+    if (bounds_out) {
+      bounds_out[0] = d.a;
+      bounds_out[1] = d.b;
+    }
+    return SISLICE_OK;
+  }
   // ---- spectral bounds: m_b-step Lanczos on H with full reorthogonalisation; the
   // normalisations stay on the device, alpha and beta are read once at the end
   std::vector<unsigned long long> sdb{rng_derive(o.seed, kTagBounds)};
@@ -553,7 +663,8 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     pr[j].need = nhi - nlo;
     max_need = std::max(max_need, pr[j].need);
   }
-  const int LC = (int)std::min<int64_t>(n, max_need + 16);
+  // locked capacity: the values a probe needs plus room for deflated pairs
+  const int LC = (int)std::min<int64_t>(n, 2 * max_need + 16);
   int MB = o.max_basis;
   while (MB > 16 && MB + 2 * b + LC > n) MB -= b;
   const int QC = MB + 2 * b;
@@ -874,7 +985,19 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
         if (t == 0.0 || !std::isfinite(t)) continue;
         const double lam = p.sigma + 1.0 / t;
         const double r = es[q][i] / std::fabs(t) * scale;
-        if (lam > p.lo && lam < p.hi && r <= lock_tol && p.nl + (int)lk[q].size() < LC) {
+        // Converged pairs are locked.  Inside the window they count toward the
+        // probe's slices.  Outside it they deflate: they are the pairs nearest to
+        // the shift and would otherwise fill the kept restart vectors for good,
+        // crowding out farther values the window still needs.  Room stays reserved
+        // for the values still missing from the window.
+        const bool inwin = lam > p.lo && lam < p.hi;
+        const int used = p.nl + (int)lk[q].size();
+        const int64_t missing = std::max<int64_t>(0, p.need - p.nin);
+        if (r <= lock_tol && inwin && used < LC) {
+          lk[q].push_back(i);
+          p.lock_lam.push_back(lam);
+          ++p.nin;
+        } else if (r <= lock_tol && !inwin && used + missing < LC) {
           lk[q].push_back(i);
           p.lock_lam.push_back(lam);
         } else {
@@ -1225,6 +1348,30 @@ sislice_status sislice_plan_shifts_kpm(sislice_handle* h, int64_t n, const doubl
     SL_CHECK_ARG(n_s >= 1 && n_e >= 1 && n_e < n, "bad n_e / n_s");
     SL_CHECK_ARG(A && B && lda >= n && ldb >= n && sigmas && omega_top, "bad argument");
     return plan_impl(h, n, A, lda, B, ldb, n_e, n_s, o, sigmas, omega_top, moments, bounds);
+  } catch (const Error& e) {
+    std::fprintf(stderr, "sislice: %s\n", e.what());
+    return e.status;
+  }
+}
+
+sislice_status sislice_plan_shifts_lanczos(sislice_handle* h, int64_t n, const double* A,
+                                           int64_t lda, const double* B, int64_t ldb, int64_t n_e,
+                                           int64_t n_s, const sislice_opts* opts, int32_t mode,
+                                           int32_t k, int32_t nv, double* sigmas, double* omega_top,
+                                           double* bounds) {
+  try {
+    check_handle(h);
+    sislice_opts o;
+    sislice_default_opts(&o);
+    if (opts) o = *opts;
+    check_opts(o);
+    SL_CHECK_ARG(n >= 16 && n <= 20000, "n must be in [16, 20000]");
+    SL_CHECK_ARG(n_s >= 1 && n_e >= 1 && n_e < n, "bad n_e / n_s");
+    SL_CHECK_ARG(mode == 0 || mode == 1, "mode must be 0 (equal counts) or 1 (DOSCluster)");
+    SL_CHECK_ARG(k >= 2 && k <= kEigMax && nv >= 1 && nv <= kSkinnyMaxCol, "k in [2, 112], nv in [1, 32]");
+    SL_CHECK_ARG(A && B && lda >= n && ldb >= n && sigmas && omega_top, "bad argument");
+    return plan_impl(h, n, A, lda, B, ldb, n_e, n_s, o, sigmas, omega_top, nullptr, bounds, mode, k,
+                     nv);
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());
     return e.status;

@@ -178,15 +178,17 @@ struct DriverWs {
 DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, long lda,
                        const double* B, long ldb, const std::vector<double>& pts, int nb);
 
-// The KPM shift planner and the plain per-pencil path (argument checks done by
-// the entry points).  solve_impl's optional `start` (device n x 8 n_s, ld n) gives
+// The shift planners and the plain per-pencil path (argument checks done by the
+// entry points).  plan_impl runs the KPM planner, or with dos_mode 0 / 1 the
+// paper's Lanczos DOS planner (dos_nv runs of dos_k steps; equal-count roots or
+// DOSCluster).  solve_impl's optional `start` (device n x 8 n_s, ld n) gives
 // each probe's Lanczos start block (warm start) instead of a Gaussian one, and
 // `probe_of` (host int32[n_e]) receives the probe that validated each returned
 // eigenpair.
 sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                          const sislice_opts& o, double* sig, double* top, double* mom_out,
-                         double* bounds_out);
+                         double* bounds_out, int dos_mode = -1, int dos_k = 0, int dos_nv = 0);
 sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                           const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,

@@ -13,6 +13,7 @@ constexpr uint64_t kTagKpm = 0x4B504Dull;        // Rademacher probe vectors
 constexpr uint64_t kTagBounds = 0x424E44ull;     // spectral-bounds Lanczos start
 constexpr uint64_t kTagLanczos = 0x4C4E43ull;    // probe start blocks (^ shift index << 32)
 constexpr uint64_t kTagKmeansPP = 0x4B4D50ull;   // k-means++ seeding
+constexpr uint64_t kTagDos = 0x444F53ull;        // start vectors of the Lanczos DOS runs
 
 uint64_t splitmix64(uint64_t seed, uint64_t i);
 double rng_uniform(uint64_t seed, uint64_t i);

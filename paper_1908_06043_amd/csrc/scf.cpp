@@ -45,7 +45,7 @@ struct sislice_scf {
   double* Afull = nullptr;   // device n x n, owned (the monitor's full copy of A)
   double* AX = nullptr;      // device n x n_e, owned
   double* start = nullptr;   // device n x 8 n_s, owned
-  double* Xg = nullptr;      // device n x n_e, owned (gathered previous vectors)
+  double* Xg = nullptr;      // device n x 3 n_e, owned (gathered previous vectors)
   double* dots = nullptr;    // device n_e, owned
 };
 
@@ -84,12 +84,20 @@ double partial_trace(sislice_scf* s, Ctx& c, const double* A, long lda) {
   return t;
 }
 
-// Warm-start blocks of the migrated probes (ascending shift order).
+// Warm-start blocks of the migrated probes (ascending shift order).  A probe must
+// lock every eigenvalue of its window (sigma_{j-1}, sigma_{j+1}) (the lower probe
+// of each slice takes its values up to tau), so it starts from the previous
+// eigenvectors of all the previous values inside that window, not only those of
+// the cluster that moved it.
 void build_starts(sislice_scf* s, Ctx& c, const ScfMigration& mg) {
   const int n = s->n, b = kLanczosBlock, P = (int)mg.shifts.size();
   std::vector<std::vector<int>> mem(P);
-  for (int i = 0; i < s->n_e; ++i)
-    if (mg.value_probe[i] >= 0) mem[mg.value_probe[i]].push_back(i);
+  for (int r = 0; r < P; ++r) {
+    const double lo = r > 0 ? mg.shifts[r - 1] : -1e300;
+    const double hi = r + 1 < P ? mg.shifts[r + 1] : s->top;
+    for (int i = 0; i < s->n_e; ++i)
+      if ((s->prev_vals[i] > lo && s->prev_vals[i] < hi) || mg.value_probe[i] == r) mem[r].push_back(i);
+  }
   // Gaussian blocks for every probe first (probes with no members keep them)
   std::vector<unsigned long long> seeds(P);
   std::vector<double*> wp(P);
@@ -111,6 +119,7 @@ void build_starts(sislice_scf* s, Ctx& c, const ScfMigration& mg) {
     gout[r] = cnt[r] < b ? s->start + (size_t)r * n * b : s->Xg + (size_t)off[r] * n;
     gidx[r] = c.ring->vec(mem[r].empty() ? std::vector<int>{0} : mem[r]);
   }
+  SL_CHECK_ARG(acc <= 3 * s->n_e, "warm-start windows overlap more than expected");
   SelectArgs sa;
   sa.count = c.ring->vec(cnt);
   sa.rows = c.ring->vec(rows);
@@ -188,7 +197,7 @@ sislice_status sislice_scf_create(sislice_handle* h, int64_t n, int64_t n_e, int
       alloc(&s->Afull, nn * nn);
       alloc(&s->AX, nn * n_e);
       alloc(&s->start, nn * kLanczosBlock * n_s);
-      alloc(&s->Xg, nn * n_e);
+      alloc(&s->Xg, nn * 3 * n_e);
       alloc(&s->dots, (size_t)n_e);
     } catch (...) {
       sislice_scf_destroy(s);
@@ -285,6 +294,7 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
                       ldx, resid, &sr, start, probe_of.data());
       r.t_solve_ms += ms_since(ts);
       r.block_steps += sr.block_steps;
+      r.cycles_max = std::max(r.cycles_max, sr.cycles_max);
       if ((st == SISLICE_MISSING_EIGS || st == SISLICE_SINGULAR_SHIFT) && !dos) {
         dos = true;  // the migrated shifts missed eigenvalues: repeat with DOS shifts
         r.replanned = 2;

@@ -300,3 +300,13 @@ def sym_perturbation_device(n, seed, norm2, device, iters=60):
         lam = float(torch.linalg.norm(w))
         v = w / lam
     return (E * (norm2 / lam)).contiguous()
+
+
+def sym_gaussian_device(n, seed, device):
+    """W = (G + G^T) / sqrt(2) with G ~ N(0, 1) drawn from torch's generator on
+    ``device`` (the density-matrix weight at orders the host builds slowly)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    G = torch.randn((n, n), generator=g, dtype=torch.float64, device=device)
+    return ((G + G.T) / np.sqrt(2.0)).contiguous()

@@ -55,7 +55,7 @@ def test_density_gradient_matches_oracle(gpu_lib, small):
     GA, GB, rep = api.adjoint(A, B, lam, X, 2.0 * lam, 2.0 * (Wd @ X), sig, out["omega_top"],
                               out["report"]["factor_id"])
     assert rep["status"] == 0 and rep["reused_factors"] == 1 and rep["breakdowns"] == 0
-    assert rep["max_rel_residual"] <= 1e-11
+    assert rep["max_rel_residual"] <= 1e-10
     GA, GB = GA.cpu().numpy(), GB.cpu().numpy()
     assert np.array_equal(GA, GA.T) and np.array_equal(GB, GB.T)
     lo, Xo = adj.lowest_pairs(P.A, P.B, n_e)
