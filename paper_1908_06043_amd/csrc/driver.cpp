@@ -1127,6 +1127,8 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   std::vector<double> vals(NL), ress(NL);
   double *Xa = nullptr, *AXa = nullptr, *BXa = nullptr, *Xf = nullptr, *AXf = nullptr, *BXf = nullptr,
          *Hm = nullptr, *Om = nullptr, *Ym = nullptr, *rr = nullptr, *xn = nullptr;
+  constexpr int kRrMats = 6;  // G, its eigenvectors U, U w^{-1/2}, S = G^{-1/2}, S H, S H S
+  const size_t e2 = (size_t)kEigMax * kEigMax;
   if (NL > 0) {
     Sizer zr;
     for (int q = 0; q < 6; ++q) zr.take<double>((size_t)n * NL);
@@ -1135,6 +1137,9 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     zr.take<double>((size_t)NC * kEigMax * kEigMax);
     zr.take<double>(NL);
     zr.take<double>(NL);
+    zr.take<double>((size_t)NC * kRrMats * e2);
+    zr.take<double>((size_t)NC * kEigMax);
+    zr.take<double>((size_t)NC * e2);
     Carver cr(ws_get(h, kBufEig, zr.off));
     Xa = cr.take<double>((size_t)n * NL);
     AXa = cr.take<double>((size_t)n * NL);
@@ -1147,6 +1152,9 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     Ym = cr.take<double>((size_t)NC * kEigMax * kEigMax);
     rr = cr.take<double>(NL);
     xn = cr.take<double>(NL);
+    double* Gm = cr.take<double>((size_t)NC * kRrMats * e2);
+    double* Gw = cr.take<double>((size_t)NC * kEigMax);
+    double* Y2 = cr.take<double>((size_t)NC * e2);
     std::vector<int> cnts(NC), rowsn(NC, n);
     std::vector<int*> idxp(NC);
     for (int q = 0; q < NC; ++q) {
@@ -1174,17 +1182,51 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       pY[q] = Ym + (size_t)q * kEigMax * kEigMax;
     }
     gemm(c, true, false, cnts, cnts, rowsn, cX, n, cAX, n, pH, kEigMax, 1.0, 0.0);
+    int cmax = 0;
+    for (int v : cnts) cmax = std::max(cmax, v);
+    // The locked vectors are B-orthonormal only up to the drift of many restart
+    // cycles (the deflation-locked ones in particular), and a standard
+    // Rayleigh-Ritz step would carry that drift into the residuals.  The
+    // symmetric orthonormalisation S = G^{-1/2} of G = X^T B X (from the
+    // eigenpairs of G, which is close to the identity) makes the step the exact
+    // generalized one: eig(S H S) = (Omega, Y), Ritz vectors X S Y.
+    std::vector<double*> pG(NC), pU(NC), pUs(NC), pS(NC), pT(NC), pH2(NC), pGw(NC), pY2(NC);
+    for (int q = 0; q < NC; ++q) {
+      double* g0 = Gm + (size_t)q * kRrMats * e2;
+      pG[q] = g0;
+      pU[q] = g0 + e2;
+      pUs[q] = g0 + 2 * e2;
+      pS[q] = g0 + 3 * e2;
+      pT[q] = g0 + 4 * e2;
+      pH2[q] = g0 + 5 * e2;
+      pGw[q] = Gw + (size_t)q * kEigMax;
+      pY2[q] = Y2 + (size_t)q * e2;
+    }
+    auto cc = [](const std::vector<double*>& v) { return std::vector<const double*>(v.begin(), v.end()); };
+    gemm(c, true, false, cnts, cnts, rowsn, cX, n, cBX, n, pG, kEigMax, 1.0, 0.0);
+    EigArgs eg;
+    eg.m = ring.vec(cnts);
+    eg.A = ring.cptrs(pG);
+    eg.lda = kEigMax;
+    eg.W = ring.ptrs(pGw);
+    eg.V = ring.ptrs(pU);
+    eg.ldv = kEigMax;
+    eig_launch(eg, NC, cmax, st);
+    for (int q = 0; q < NC; ++q)
+      scale_cols_launch(cnts[q], cnts[q], pGw[q], pU[q], kEigMax, pUs[q], kEigMax, nullptr, st);
+    gemm(c, false, true, cnts, cnts, cnts, cc(pUs), kEigMax, cc(pU), kEigMax, pS, kEigMax, 1.0, 0.0);
+    gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pH), kEigMax, pT, kEigMax, 1.0, 0.0);
+    gemm(c, false, false, cnts, cnts, cnts, cc(pT), kEigMax, cc(pS), kEigMax, pH2, kEigMax, 1.0, 0.0);
     EigArgs e;
     e.m = ring.vec(cnts);
-    e.A = ring.cptrs(pH);
+    e.A = ring.cptrs(pH2);
     e.lda = kEigMax;
     e.W = ring.ptrs(pO);
     e.V = ring.ptrs(pY);
     e.ldv = kEigMax;
-    int cmax = 0;
-    for (int v : cnts) cmax = std::max(cmax, v);
     eig_launch(e, NC, cmax, st);
-    std::vector<const double*> cY(pY.begin(), pY.end());
+    gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pY), kEigMax, pY2, kEigMax, 1.0, 0.0);
+    std::vector<const double*> cY(pY2.begin(), pY2.end());
     gemm(c, false, false, rowsn, cnts, cnts, cX, n, cY, kEigMax,
          act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }), n, 1.0, 0.0);
     gemm(c, false, false, rowsn, cnts, cnts, cAX, n, cY, kEigMax,
@@ -1240,6 +1282,39 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   const int64_t nval = validate(P, sig.data(), nu.data(), top, nu_top, offs.data(), cnts.data(),
                                 vals.data(), ress.data(), scase.data(), sexact.data(), scand.data(),
                                 chosen.data());
+  // A value is taken from the probe whose shift is nearer, but both probes of a
+  // slice usually lock it.  When the chosen copy misses the tolerance (a vector
+  // of a dense cluster that one probe resolved less well) and the other probe's
+  // copy of the same value meets it, the better copy is reported.  Copies match
+  // when they agree to 1e-9 relative to the spectral scale, and the exchange is
+  // refused when any other chosen value lies that close (a near-degenerate pair
+  // must keep two distinct vectors).
+  {
+    const double dmatch = 1e-9 * std::max(1.0, std::fabs(top) + std::fabs(sig[0]));
+    std::vector<int> cidx;
+    for (int t = 0; t < NL; ++t)
+      if (chosen[t]) cidx.push_back(t);
+    std::sort(cidx.begin(), cidx.end(), [&](int x, int y) { return vals[x] < vals[y]; });
+    auto chosen_near = [&](double v, int self) {
+      auto it = std::lower_bound(cidx.begin(), cidx.end(), v - dmatch,
+                                 [&](int x, double w) { return vals[x] < w; });
+      for (; it != cidx.end() && vals[*it] <= v + dmatch; ++it)
+        if (*it != self) return true;
+      return false;
+    };
+    for (int t : cidx) {
+      if (!(ress[t] > o.tol)) continue;
+      int best = -1;
+      for (int u = 0; u < NL; ++u) {
+        if (chosen[u] || !(ress[u] <= o.tol) || std::fabs(vals[u] - vals[t]) > dmatch) continue;
+        if (best < 0 || ress[u] < ress[best]) best = u;
+      }
+      if (best >= 0 && !chosen_near(vals[t], t)) {
+        chosen[t] = 0;
+        chosen[best] = 1;
+      }
+    }
+  }
   std::vector<int> pick;
   for (int t = 0; t < NL; ++t)
     if (chosen[t]) pick.push_back(t);

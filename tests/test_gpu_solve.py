@@ -14,7 +14,8 @@ def dev(M):
 
 
 @pytest.mark.parametrize("n,nrhs,seed", [(1, 1, 0), (5, 3, 1), (64, 8, 2), (65, 8, 3), (130, 20, 4),
-                                         (333, 8, 5), (777, 33, 6), (1000, 64, 7)])
+                                         (333, 8, 5), (777, 33, 6), (1000, 64, 7),
+                                         (2500, 8, 8)])
 def test_solve_matches_oracle(gpu_lib, n, nrhs, seed):
     C = inputs.random_symmetric(n, seed)
     f = gpu_lib.ldlt_factor(dev(C), dev(np.eye(n)), 0.0)
@@ -23,10 +24,17 @@ def test_solve_matches_oracle(gpu_lib, n, nrhs, seed):
     X = gpu_lib.ldlt_solve(f, dev(Y)).cpu().numpy()
     ref = bk.ldlt_solve(bk.bk_ldlt(C), Y)
     kappa = np.linalg.cond(C)
-    # both are backward stable: compare residuals and the solutions within cond * eps
-    r = np.linalg.norm(C @ X - Y) / (np.linalg.norm(C) * np.linalg.norm(X))
+
+    def backward(Xs):
+        return np.linalg.norm(C @ Xs - Y) / (np.linalg.norm(C) * np.linalg.norm(Xs))
+
+    # both are backward stable, so the solutions agree to cond(C) times the sum of
+    # their backward errors (each at least one rounding); the oracle's own
+    # Bunch-Kaufman growth sets its share at larger n
+    r, r_ref = backward(X), backward(ref)
     assert r < 1e-13
-    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-14 * max(kappa, 1.0) * 10
+    bound = 10.0 * max(kappa, 1.0) * (max(r, 1e-16) + max(r_ref, 1e-16))
+    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) < bound
 
 
 def test_solve_pencil_shift_and_repeat(gpu_lib):
