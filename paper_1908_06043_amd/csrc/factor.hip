@@ -714,6 +714,106 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
   }
 }
 
+// The same update on 128x128 tiles for large trailing matrices: each wavefront
+// owns a 64x64 quarter as 4x4 v_mfma_f64_16x16x4 blocks, so every operand value a
+// lane loads feeds four MFMAs instead of two, and the C tile is read and written
+// once per 128x128 instead of per 64x64.  On a diagonal tile the quarter above the
+// diagonal is skipped.
+__global__ __launch_bounds__(256) void k_trailing_update128(int n, double* const* LDs, long ldld,
+                                                            double* const* Wps, long ldw,
+                                                            const FactorState* states) {
+  constexpr int KS = kMaxNb / 4;  // k-steps of 4
+  constexpr int TB = 128;
+  const int s = blockIdx.y;
+  const int k0 = states[s].k0, kb = states[s].kb;
+  const int k1 = k0 + kb;
+  if (kb <= 0 || k1 >= n) return;
+  const int T = (n - k1 + TB - 1) / TB;
+  const int lin = blockIdx.x;
+  if (lin >= T * (T + 1) / 2) return;
+  int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+  while (ti * (ti + 1) / 2 > lin) --ti;
+  while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+  const int tj = lin - ti * (ti + 1) / 2;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int wi = (w & 1) * 64, wj = (w >> 1) * 64;
+  if (ti == tj && wi < wj) return;  // strictly above the diagonal
+  const int row0 = k1 + ti * TB, col0 = k1 + tj * TB;
+  double* LD = LDs[s];
+  const double* Wp = Wps[s];
+  const int lr = l & 15, lk = l >> 4;
+  const int nks = (kb + 3) >> 2;
+  int ri[4], cj[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) ri[x] = min(row0 + wi + 16 * x + lr, n - 1);
+#pragma unroll
+  for (int y = 0; y < 4; ++y) cj[y] = min(col0 + wj + 16 * y + lr, n - 1);
+  d4 acc[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
+        acc[x][y][r] = LD[ri[x] + (long)j * ldld];
+      }
+  constexpr int CK = 1;
+  const int nch = (nks + CK - 1) / CK;
+  double lop[2][CK][4], wop[2][CK][4];
+  auto load_chunk = [&](int ch, double (&lb)[CK][4], double (&wb)[CK][4]) {
+#pragma unroll
+    for (int u = 0; u < CK; ++u) {
+      const int k = 4 * (CK * ch + u) + lk;
+      const bool kv = k < kb;
+      const int kc = kv ? k : 0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const double v = LD[ri[x] + (long)(k0 + kc) * ldld];
+        lb[u][x] = kv ? v : 0.0;
+      }
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const double v = Wp[cj[y] + (long)kc * ldw];
+        wb[u][y] = kv ? -v : 0.0;
+      }
+    }
+  };
+  auto mfma_chunk = [&](const double (&lb)[CK][4], const double (&wb)[CK][4]) {
+#pragma unroll
+    for (int u = 0; u < CK; ++u)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(wb[u][y], lb[u][x], acc[x][y]);
+  };
+  load_chunk(0, lop[0], wop[0]);
+#pragma unroll
+  for (int ch = 0; ch < KS / CK; ch += 2) {
+    if (ch < nch) {
+      if (ch + 1 < nch) load_chunk(ch + 1, lop[1], wop[1]);
+      mfma_chunk(lop[0], wop[0]);
+    }
+    if (ch + 1 < nch) {
+      if (ch + 2 < nch) load_chunk(ch + 2, lop[0], wop[0]);
+      mfma_chunk(lop[1], wop[1]);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int i = row0 + wi + 16 * x + lr;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jc = col0 + wj + 16 * y + lk + 4 * r;
+        if (i < n && jc < n && i >= jc) LD[i + (long)jc * ldld] = acc[x][y][r];
+      }
+    }
+  }
+}
+
 // Suffix compositions of the interchanges: for the panel ending at e, Q_e[v] is
 // the final row of the entry found at row v (v >= e) when that panel finished.
 __global__ __launch_bounds__(256) void k_perm_suffix(int n, const int* const* swps,
@@ -789,6 +889,10 @@ __global__ __launch_bounds__(256) void k_factor_finalize(int n, const int* const
 
 // ------------------------------------------------------------------ host side
 
+// Trailing order from which the update runs on 128x128 tiles (below it, the
+// 64x64 tiles keep more workgroups in flight).
+constexpr long kUpdateWideMin = 1024;
+
 void factor_launch(const FactorPlan& fp, hipStream_t st) {
   const int n = fp.n, S = fp.nshift, nb = fp.nb;
   if (S <= 0 || n <= 0) return;
@@ -861,10 +965,16 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       prof_end(ph, tp);
       const long k1_lb = std::min<long>(n, k0_lb + min_kb);
       if (k1_lb >= n) continue;
-      const long T = ceil_div(n - k1_lb, 64);
       const int tu = prof_begin(ph, kProfUpdate);
-      SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0,
-                         st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+      if (n - k1_lb >= kUpdateWideMin) {
+        const long T = ceil_div(n - k1_lb, 128);
+        SL_LAUNCH(k_trailing_update128, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
+                  fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+      } else {
+        const long T = ceil_div(n - k1_lb, 64);
+        SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
+                  fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+      }
       SL_LAUNCH_CHECK();
       prof_end(ph, tu);
     }
