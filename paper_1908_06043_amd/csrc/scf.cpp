@@ -270,6 +270,16 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
           s->shifts = mg.shifts;
           build_starts(s, c, mg);
           start = s->start;
+          // The top boundary of a warm step sits two local spacings above the
+          // previous n_e-th value: the planner's boundary holds a margin of values
+          // beyond lambda_{n_e} that the kept eigenvectors do not span, and the top
+          // probe would spend most of the step on them.  Should the perturbation
+          // lift lambda_{n_e} past it, the solve moves the boundary up (top-boundary
+          // recovery).
+          const int m = std::min(n_e - 1, std::max(8, n_e / n_s));
+          const double lam_ne = s->prev_vals[n_e - 1];
+          const double spacing = m > 0 ? (lam_ne - s->prev_vals[n_e - 1 - m]) / m : 0.0;
+          s->top = lam_ne + 2.0 * spacing + 1e-12 * std::max(1.0, std::fabs(lam_ne));
           if (!(s->top > s->shifts.back()))
             s->top = s->shifts.back() + (s->shifts.back() - s->shifts.front()) / n_s + 1e-12;
         }
