@@ -714,16 +714,23 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
   }
 }
 
-// The same update on 128x128 tiles for large trailing matrices: each wavefront
-// owns a 64x64 quarter as 4x4 v_mfma_f64_16x16x4 blocks, so every operand value a
-// lane loads feeds four MFMAs instead of two, and the C tile is read and written
-// once per 128x128 instead of per 64x64.  On a diagonal tile the quarter above the
-// diagonal is skipped.
-__global__ __launch_bounds__(256) void k_trailing_update128(int n, double* const* LDs, long ldld,
-                                                            double* const* Wps, long ldw,
-                                                            const FactorState* states) {
-  constexpr int KS = kMaxNb / 4;  // k-steps of 4
+// The same update on 128x128 tiles for large trailing matrices.  Each wavefront
+// owns a 64x64 quarter as 4x4 v_mfma_f64_16x16x4 blocks (every operand value feeds
+// four MFMAs), and the C tile is read and written once per 128x128.  The operand
+// panels of the tile (128 rows of L and 128 rows of W, 16 k-columns per chunk) are
+// fetched once per workgroup with coalesced 1 KB column runs into double-buffered
+// LDS (64 KB; two workgroups per CU), and the next chunk is in flight while the
+// wavefronts run the current one's 64 MFMAs.
+// Layout per chunk and operand: [k][row], rows padded to 132 doubles so that the
+// four k-groups a wavefront reads at once fall on different banks.
+constexpr int kUpdK = 16;           // k-columns per staged chunk
+constexpr int kUpdLd = 128 + 4;     // padded row count per k-column
+__global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* const* LDs, long ldld,
+                                                             double* const* Wps, long ldw,
+                                                             const FactorState* states) {
   constexpr int TB = 128;
+  __shared__ double sL[2][kUpdK * kUpdLd];
+  __shared__ double sW[2][kUpdK * kUpdLd];
   const int s = blockIdx.y;
   const int k0 = states[s].k0, kb = states[s].kb;
   const int k1 = k0 + kb;
@@ -738,68 +745,81 @@ __global__ __launch_bounds__(256) void k_trailing_update128(int n, double* const
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
   const int wi = (w & 1) * 64, wj = (w >> 1) * 64;
-  if (ti == tj && wi < wj) return;  // strictly above the diagonal
+  // on a diagonal tile the quarter above the diagonal stores nothing, but its
+  // wavefront still helps stage the operands
+  const bool active = !(ti == tj && wi < wj);
   const int row0 = k1 + ti * TB, col0 = k1 + tj * TB;
   double* LD = LDs[s];
   const double* Wp = Wps[s];
   const int lr = l & 15, lk = l >> 4;
-  const int nks = (kb + 3) >> 2;
-  int ri[4], cj[4];
+  const int nks = (kb + 3) >> 2;             // k-steps of 4
+  const int nch = (kb + kUpdK - 1) / kUpdK;  // staged chunks
+  // staging: thread t fetches row (t % 128) of columns (t / 128) + 2j, j < 8
+  const int sr = tid & 127, sc = tid >> 7;
+  const int lrow = min(row0 + sr, n - 1), wrow = min(col0 + sr, n - 1);
+  double stL[kUpdK / 2], stW[kUpdK / 2];
+  auto fetch = [&](int ch) {
 #pragma unroll
-  for (int x = 0; x < 4; ++x) ri[x] = min(row0 + wi + 16 * x + lr, n - 1);
-#pragma unroll
-  for (int y = 0; y < 4; ++y) cj[y] = min(col0 + wj + 16 * y + lr, n - 1);
-  d4 acc[4][4];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
-        acc[x][y][r] = LD[ri[x] + (long)j * ldld];
-      }
-  constexpr int CK = 1;
-  const int nch = (nks + CK - 1) / CK;
-  double lop[2][CK][4], wop[2][CK][4];
-  auto load_chunk = [&](int ch, double (&lb)[CK][4], double (&wb)[CK][4]) {
-#pragma unroll
-    for (int u = 0; u < CK; ++u) {
-      const int k = 4 * (CK * ch + u) + lk;
+    for (int j = 0; j < kUpdK / 2; ++j) {
+      const int k = ch * kUpdK + sc + 2 * j;
       const bool kv = k < kb;
       const int kc = kv ? k : 0;
-#pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const double v = LD[ri[x] + (long)(k0 + kc) * ldld];
-        lb[u][x] = kv ? v : 0.0;
-      }
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const double v = Wp[cj[y] + (long)kc * ldw];
-        wb[u][y] = kv ? -v : 0.0;
-      }
+      const double a = LD[lrow + (long)(k0 + kc) * ldld];
+      const double b = Wp[wrow + (long)kc * ldw];
+      stL[j] = kv ? a : 0.0;
+      stW[j] = kv ? -b : 0.0;
     }
   };
-  auto mfma_chunk = [&](const double (&lb)[CK][4], const double (&wb)[CK][4]) {
+  auto stage = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < CK; ++u)
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(wb[u][y], lb[u][x], acc[x][y]);
-  };
-  load_chunk(0, lop[0], wop[0]);
-#pragma unroll
-  for (int ch = 0; ch < KS / CK; ch += 2) {
-    if (ch < nch) {
-      if (ch + 1 < nch) load_chunk(ch + 1, lop[1], wop[1]);
-      mfma_chunk(lop[0], wop[0]);
+    for (int j = 0; j < kUpdK / 2; ++j) {
+      sL[buf][(sc + 2 * j) * kUpdLd + sr] = stL[j];
+      sW[buf][(sc + 2 * j) * kUpdLd + sr] = stW[j];
     }
-    if (ch + 1 < nch) {
-      if (ch + 2 < nch) load_chunk(ch + 2, lop[0], wop[0]);
-      mfma_chunk(lop[1], wop[1]);
+  };
+  fetch(0);
+  d4 acc[4][4];
+  if (active) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      const int i = min(row0 + wi + 16 * x + lr, n - 1);
+#pragma unroll
+      for (int y = 0; y < 4; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
+          acc[x][y][r] = LD[i + (long)j * ldld];
+        }
     }
   }
+  stage(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) fetch(ch + 1);
+    if (active) {
+      const double* L0 = sL[buf] + wi + lr;
+      const double* W0 = sW[buf] + wj + lr;
+      const int ksteps = min(kUpdK / 4, nks - ch * (kUpdK / 4));
+      for (int u = 0; u < ksteps; ++u) {
+        const int kk = (4 * u + lk) * kUpdLd;
+        double lo[4], wo[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) lo[x] = L0[kk + 16 * x];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) wo[y] = W0[kk + 16 * y];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(wo[y], lo[x], acc[x][y]);
+      }
+    }
+    if (ch + 1 < nch) {
+      stage(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  if (!active) return;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int i = row0 + wi + 16 * x + lr;
@@ -968,7 +988,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const int tu = prof_begin(ph, kProfUpdate);
       if (n - k1_lb >= kUpdateWideMin) {
         const long T = ceil_div(n - k1_lb, 128);
-        SL_LAUNCH(k_trailing_update128, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
+        SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
                   fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
       } else {
         const long T = ceil_div(n - k1_lb, 64);
