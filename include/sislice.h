@@ -187,7 +187,10 @@ sislice_status sislice_plan_shifts_lanczos(sislice_handle *h, int64_t n, const d
  * every shift and the top boundary, read the inertias, run block shift-invert
  * Lanczos in the B inner product per shift (b = opts->block, thick restart with
  * locking), explicit Rayleigh-Ritz with A and B, residuals, slice validation
- * (Sec. 2.2), and return the lowest n_e validated eigenpairs.
+ * (Sec. 2.2), and return the lowest n_e validated eigenpairs.  A value is
+ * reported from the probe whose shift is nearer; when that copy misses the
+ * tolerance and the other probe of its slice holds a copy of the same value
+ * that meets it, that copy is reported instead.
  *   sigmas     host double[n_s], ascending, or NULL: then the shifts and the top
  *              boundary are planned with sislice_plan_shifts_kpm.
  *   omega_top  host double in/out: the top boundary when sigmas != NULL (must
@@ -334,7 +337,9 @@ sislice_status sislice_scf_migrate(const double *ritz, const int32_t *probe_of, 
  *     starts every probe from a Gaussian block.  Later steps compare
  *     eta = tr(X^T A X) of the previous eigenvectors under the previous pencil
  *     (the sum of the previous eigenvalues) and the new one; within eta_tol the
- *     shifts migrate (sislice_scf_migrate; k-means++ after a DOS step) and every
+ *     shifts migrate (sislice_scf_migrate; k-means++ after a DOS step), the top
+ *     boundary moves to two local spacings above the previous lambda_{n_e} (the
+ *     solve lifts it when the pencil has moved past it), and every
  *     probe starts from the previous eigenvectors of the values that seed it (a
  *     Gaussian combination of them, or the vectors padded with Gaussian columns
  *     when fewer than the block size); otherwise, or when the migrated shifts
