@@ -320,13 +320,26 @@ __global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  for (int st = 0; st < kTsRows / 64; ++st) {
+  // the 64x64 block of the next stage is loaded into registers while the current
+  // one is consumed: element e = tid + 256 j -> (row e & 63, column e >> 6)
+  double vn[16];
+  auto load_v = [&](int st) {
     const int rs = r0 + 64 * st;
-    __syncthreads();
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int r = e & 63, ii = e >> 6;
-      sV[r][ii] = (rs + r < n && i0 + ii < m) ? V[rs + r + (long)(i0 + ii) * a.ldv] : 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j, r = e & 63, ii = e >> 6;
+      vn[j] = (rs + r < n && i0 + ii < m) ? V[rs + r + (long)(i0 + ii) * a.ldv] : 0.0;
     }
+  };
+  load_v(0);
+  for (int st = 0; st < kTsRows / 64; ++st) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int e = tid + 256 * j;
+      sV[e & 63][e >> 6] = vn[j];
+    }
+    if (st + 1 < kTsRows / 64) load_v(st + 1);
     __syncthreads();
     for (int rr = rg; rr < 64; rr += 4) {
       const double v = sV[rr][i];
@@ -377,8 +390,10 @@ void tsmt_launch(TsArgs a, int batch, int mmax, hipStream_t st) {
 }
 
 // k_tsmm: Y_b = beta Y_b + alpha (V_b C_b + V2_b C2_b), n x 8.  The coefficients
-// sit in LDS; four consecutive lanes share a row (two output columns each), so a
-// wavefront reads 16 consecutive rows of V per column: one 128-byte segment.
+// sit in LDS.  Four consecutive lanes share a row and split the columns of V
+// (lane g takes k = g mod 4, for all eight outputs), so a wavefront reads 16 rows
+// of four different columns per load (four 128-byte segments, none repeated) and
+// the four partial sums of a row meet through lane shuffles.
 __global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
   extern __shared__ double sC[];  // [m1 + m2][8]
   const int b = blockIdx.y, tid = threadIdx.x;
@@ -400,43 +415,41 @@ __global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
   const int row = blockIdx.x * 64 + (tid >> 2), g = tid & 3;
   const bool rv = row < n;
   const int rc = rv ? row : n - 1;
-  double acc0 = 0.0, acc1 = 0.0;
-  const double* V1 = a.V[b] + rc;
-  int k = 0;
-  for (; k + 4 <= m1; k += 4) {
-    double v[4];
+  double acc[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = V1[(long)(k + u) * a.ldv];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc0 += v[u] * sC[(k + u) * 8 + 2 * g];
-      acc1 += v[u] * sC[(k + u) * 8 + 2 * g + 1];
-    }
-  }
-  for (; k < m1; ++k) {
-    const double v = V1[(long)k * a.ldv];
-    acc0 += v * sC[k * 8 + 2 * g];
-    acc1 += v * sC[k * 8 + 2 * g + 1];
-  }
-  if (m2 > 0) {
-    const double* V2 = a.V2[b] + rc;
-    const double* sC2 = sC + m1 * 8;
-    int k2 = 0;
-    for (; k2 + 4 <= m2; k2 += 4) {
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  auto run = [&](const double* Vb, long ldv, const double* sCb, int mb) {
+    int k = g;
+    for (; k + 12 < mb; k += 16) {
       double v[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = V2[(long)(k2 + u) * a.ldv2];
+      for (int u = 0; u < 4; ++u) v[u] = Vb[(long)(k + 4 * u) * ldv];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        acc0 += v[u] * sC2[(k2 + u) * 8 + 2 * g];
-        acc1 += v[u] * sC2[(k2 + u) * 8 + 2 * g + 1];
+        const double* cr = sCb + (k + 4 * u) * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] += v[u] * cr[c];
       }
     }
-    for (; k2 < m2; ++k2) {
-      const double v = V2[(long)k2 * a.ldv2];
-      acc0 += v * sC2[k2 * 8 + 2 * g];
-      acc1 += v * sC2[k2 * 8 + 2 * g + 1];
+    for (; k < mb; k += 4) {
+      const double v = Vb[(long)k * ldv];
+      const double* cr = sCb + k * 8;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[c] += v * cr[c];
     }
+  };
+  run(a.V[b] + rc, a.ldv, sC, m1);
+  if (m2 > 0) run(a.V2[b] + rc, a.ldv2, sC + m1 * 8, m2);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    acc[c] += __shfl_xor(acc[c], 1);
+    acc[c] += __shfl_xor(acc[c], 2);
+  }
+  double acc0 = acc[0], acc1 = acc[1];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) {
+    acc0 = (g == q) ? acc[2 * q] : acc0;
+    acc1 = (g == q) ? acc[2 * q + 1] : acc1;
   }
   if (rv) {
     double* Y = a.Y[b] + row;
