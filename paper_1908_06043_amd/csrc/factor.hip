@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states,
 // |d_k| >= alpha * max_{i>k} |s_ik| for the Schur-complement column s at step k.
 // As long as that holds for every column, the factorization is the pivot-free
 // LDL^T, which parallelises like Cholesky: the panel's diagonal block is factored
-// in LDS (k_fast_diag), the rows below follow from one triangular solve with the
+// in LDS (k_fast_diag4), the rows below follow from one triangular solve with the
 // block (k_fast_trsm: W21 = C21 L11^{-T}, L21 = W21 D1^{-1}) together with the
 // column maxima of |W|, and k_fast_commit accepts the longest prefix of columns
 // that pass the test.  The pivoting panel kernel then continues from the first
@@ -121,29 +121,25 @@ __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states,
 __device__ __forceinline__ double u64_to_f64(unsigned long long v) { return __longlong_as_double((long long)v); }
 
 // Pivot-free LDL^T of the panel's diagonal block (nbe <= NB columns), one
-// wavefront per shift: lane i holds row i of the block in registers, so no step
-// needs a barrier across wavefronts.  The register window is rotated by four
-// columns every four steps, which keeps every register index static (the pivot
-// column of step k is a[k - t0] inside the unrolled group t0 .. t0 + 3).  The
-// pivot is broadcast with readlane, the multipliers l_ck = A[c][k] / d through
-// LDS.  The finished W columns are kept in LDS for the outputs: the block's rows
-// of W (unscaled) and L, D, the in-block column maxima of |W|, and L11
-// column-major for the row solves of k_fast_trsm.
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
+// 256-thread workgroup per shift: lane q of row i holds the columns q + 4m of the
+// row, so each step's update is a quarter of the row per lane, at the price of two
+// workgroup barriers per step (the pivot and the multipliers l_ck = A[c][k] / d go
+// through LDS).  The register window is rotated by one register every four steps,
+// which keeps every register index static (the pivot column of step k = t0 + kk is
+// register 0 of the lanes q == kk).  The finished W columns are kept in LDS for the
+// outputs: the block's rows of W (unscaled) and L, D, the in-block column maxima
+// of |W|, and L11 column-major for the row solves of k_fast_trsm.
 template <int NB>
-__global__ __launch_bounds__(64) void k_fast_diag(int n, const double* const* LDs, long ldld,
-                                                  double* const* Wps, long ldw,
-                                                  double* const* Lps, double* const* auxs,
-                                                  const FactorState* states, int nb) {
+__global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* LDs, long ldld,
+                                                    double* const* Wps, long ldw,
+                                                    double* const* Lps, double* const* auxs,
+                                                    const FactorState* states, int nb) {
+  constexpr int M = NB / 4;
   __shared__ double Wb[NB][NB + 1];  // Wb[i][k]: final W of column k (rows >= k)
-  __shared__ double lcol[NB + 64];   // multipliers; zero past NB (window registers past the block)
-  const int s = blockIdx.x, i = threadIdx.x;
+  __shared__ double lcol[2 * NB];    // multipliers; zero past NB (window registers past the block)
+  __shared__ double dsh;
+  const int s = blockIdx.x, tid = threadIdx.x;
+  const int i = tid >> 2, q = tid & 3;
   const FactorState st = states[s];
   const int k0 = st.k0 + st.kb;
   if (st.done || k0 >= n) return;
@@ -156,59 +152,73 @@ __global__ __launch_bounds__(64) void k_fast_diag(int n, const double* const* LD
   double* cin = aux + nb;
   unsigned long long* cout = reinterpret_cast<unsigned long long*>(aux + 2 * nb);
   double* L11 = aux + 3 * nb;  // column-major nb x nb, strictly lower part
-  const bool lane_ok = i < NB;
-  double a[NB];  // a[j] = A[i][t0 + j] for the current group start t0
+  const bool row_ok = i < NB && i < nbe;
+  double a[M];  // a[m] = A[i][t0 + q + 4m] for the current group start t0
 #pragma unroll
-  for (int j = 0; j < NB; ++j)
-    a[j] = (lane_ok && i < nbe && j < nbe && i >= j) ? LD[(k0 + i) + (long)(k0 + j) * ldld] : 0.0;
-  for (int c = i; c < nb; c += 64) cout[c] = 0ull;
-  lcol[NB + i] = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const int c = q + 4 * m;
+    a[m] = (row_ok && c < nbe && i >= c) ? LD[(k0 + i) + (long)(k0 + c) * ldld] : 0.0;
+  }
+  for (int c = tid; c < nb; c += 256) cout[c] = 0ull;
+  for (int c = tid; c < 2 * NB; c += 256) lcol[c] = 0.0;
   for (int t0 = 0; t0 < nbe; t0 += 4) {
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int k = t0 + kk;
       if (k < nbe) {
-        const double ak = a[kk];  // A[i][k]
-        const double d = readlane_f64(ak, k);
-        const double r = 1.0 / d;
-        if (lane_ok) {
-          Wb[i][k] = ak;
-          lcol[i] = ak * r;
+        // the pivot column k is register 0 of the lanes q == kk
+        if (q == kk && i < NB) {
+          Wb[i][k] = a[0];
+          if (i == k) dsh = a[0];
         }
         __syncthreads();
-        // A[i][c] -= A[i][k] l_ck for the columns c = t0 + j > k of the window
-        // (registers past column NB - 1 hold no column and meet zero multipliers)
-        const double* lc = lcol + t0;
-#pragma unroll
-        for (int j = kk + 1; j < NB; ++j) a[j] -= ak * lc[j];
+        const double r = 1.0 / dsh;
+        if (q == kk && i < NB) lcol[i] = a[0] * r;
         __syncthreads();
+        const double ak = (i < NB) ? Wb[i][k] : 0.0;
+        // A[i][c] -= A[i][k] l_ck for the columns c = t0 + q + 4m > k of the window
+        // (registers past column NB - 1 hold no column and meet zero multipliers)
+        const double* lc = lcol + t0 + q;
+        if (q > kk) a[0] -= ak * lc[0];
+#pragma unroll
+        for (int m = 1; m < M; ++m) a[m] -= ak * lc[4 * m];
+      }
+    }
+    __syncthreads();  // lcol of this group is read before the next group rewrites it
+#pragma unroll
+    for (int m = 0; m + 1 < M; ++m) a[m] = a[m + 1];
+    a[M - 1] = 0.0;
+  }
+  __syncthreads();
+  // outputs: rows i >= k of each column k, coalesced over rows
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e % NB, k = e / NB;
+    if (k < nbe && r < nbe) {
+      const double w = Wb[r][k];
+      const double lv = (r > k) ? w * (1.0 / Wb[k][k]) : 0.0;
+      if (r >= k) Wp[(k0 + r) + (long)k * ldw] = w;
+      if (r > k) Lp[(k0 + r) + (long)k * ldw] = lv;
+      L11[r + (long)k * nb] = lv;
+    }
+  }
+  // in-block column maxima below the diagonal: lane q takes the rows r = i + 1 + q + 4t
+  {
+    double mx = 0.0;
+    if (row_ok) {
+      for (int r = i + 1 + q; r < nbe; r += 4) {
+        const double v = fabs(Wb[r][i]);
+        mx = (v > mx || v != v) ? v : mx;
       }
     }
 #pragma unroll
-    for (int j = 0; j + 4 < NB; ++j) a[j] = a[j + 4];
-#pragma unroll
-    for (int j = NB - 4; j < NB; ++j) a[j] = 0.0;
-  }
-  __syncthreads();
-  // outputs (columns k < nbe; lane i = row i)
-  for (int k = 0; k < nbe; ++k) {
-    const double rd = 1.0 / Wb[k][k];
-    if (lane_ok && i < nbe) {
-      const double w = Wb[i][k];
-      const double lv = (i > k) ? w * rd : 0.0;
-      if (i >= k) Wp[(k0 + i) + (long)k * ldw] = w;
-      if (i > k) Lp[(k0 + i) + (long)k * ldw] = lv;
-      L11[i + (long)k * nb] = lv;
+    for (int off = 1; off < 4; off <<= 1) {
+      const double o = __shfl_xor(mx, off);
+      mx = (o > mx || o != o) ? o : mx;
     }
-  }
-  if (lane_ok && i < nbe) {
-    double mx = 0.0;
-    for (int r = i + 1; r < nbe; ++r) {
-      const double v = fabs(Wb[r][i]);
-      mx = (v > mx || v != v) ? v : mx;
+    if (row_ok && q == 0) {
+      cin[i] = mx;
+      Dv[i] = Wb[i][i];
     }
-    cin[i] = mx;
-    Dv[i] = Wb[i][i];
   }
 }
 
@@ -941,7 +951,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
         const int tf = prof_begin(ph, kProfPanel);
         const long rows = n - k0_lb - 1;
         if (nb > 32) {
-          SL_LAUNCH(k_fast_diag<64>, dim3(S), dim3(64), 0, st, n, (const double* const*)fp.d_LD,
+          SL_LAUNCH(k_fast_diag4<64>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
                     fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
           SL_LAUNCH_CHECK();
           if (rows > 0) {
@@ -951,7 +961,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
             SL_LAUNCH_CHECK();
           }
         } else {
-          SL_LAUNCH(k_fast_diag<32>, dim3(S), dim3(64), 0, st, n, (const double* const*)fp.d_LD,
+          SL_LAUNCH(k_fast_diag4<32>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
                     fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
           SL_LAUNCH_CHECK();
           if (rows > 0) {
