@@ -724,18 +724,19 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
   }
 }
 
-// The same update on 128x128 tiles for large trailing matrices.  Each wavefront
-// owns a 64x64 quarter as 4x4 v_mfma_f64_16x16x4 blocks (every operand value feeds
-// four MFMAs), and the C tile is read and written once per 128x128.  The operand
-// panels of the tile (128 rows of L and 128 rows of W, 16 k-columns per chunk) are
-// fetched once per workgroup with coalesced 1 KB column runs into double-buffered
-// LDS (64 KB; two workgroups per CU), and the next chunk is in flight while the
-// wavefronts run the current one's 64 MFMAs.
+// The same update on 128x128 tiles for large trailing matrices, one 1024-thread
+// workgroup per tile.  Each of the 16 wavefronts owns a 32x32 block of the tile as
+// 2x2 v_mfma_f64_16x16x4 blocks, so a wavefront needs 62 registers and a CU keeps
+// two workgroups (eight wavefronts per SIMD) in flight; the C tile is read and
+// written once per 128x128.  The operand panels of the tile (128 rows of L and 128
+// rows of W, 16 k-columns per chunk) are fetched once per workgroup with coalesced
+// 1 KB column runs into double-buffered LDS (66 KB), and the next chunk is in
+// flight while the wavefronts run the current one's MFMAs.
 // Layout per chunk and operand: [k][row], rows padded to 132 doubles so that the
 // four k-groups a wavefront reads at once fall on different banks.
 constexpr int kUpdK = 16;           // k-columns per staged chunk
 constexpr int kUpdLd = 128 + 4;     // padded row count per k-column
-__global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* const* LDs, long ldld,
+__global__ __launch_bounds__(1024) void k_trailing_update_lds(int n, double* const* LDs, long ldld,
                                                              double* const* Wps, long ldw,
                                                              const FactorState* states) {
   constexpr int TB = 128;
@@ -754,24 +755,24 @@ __global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* cons
   const int tj = lin - ti * (ti + 1) / 2;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
-  const int wi = (w & 1) * 64, wj = (w >> 1) * 64;
-  // on a diagonal tile the quarter above the diagonal stores nothing, but its
-  // wavefront still helps stage the operands
-  const bool active = !(ti == tj && wi < wj);
+  const int wi = (w & 3) * 32, wj = (w >> 2) * 32;
+  // on a diagonal tile the blocks above the diagonal store nothing, but their
+  // wavefronts still help stage the operands
+  const bool active = !(ti == tj && wi + 31 < wj);
   const int row0 = k1 + ti * TB, col0 = k1 + tj * TB;
   double* LD = LDs[s];
   const double* Wp = Wps[s];
   const int lr = l & 15, lk = l >> 4;
   const int nks = (kb + 3) >> 2;             // k-steps of 4
   const int nch = (kb + kUpdK - 1) / kUpdK;  // staged chunks
-  // staging: thread t fetches row (t % 128) of columns (t / 128) + 2j, j < 8
+  // staging: thread t fetches row (t % 128) of columns (t / 128) + 8j, j < 2
   const int sr = tid & 127, sc = tid >> 7;
   const int lrow = min(row0 + sr, n - 1), wrow = min(col0 + sr, n - 1);
-  double stL[kUpdK / 2], stW[kUpdK / 2];
+  double stL[kUpdK / 8], stW[kUpdK / 8];
   auto fetch = [&](int ch) {
 #pragma unroll
-    for (int j = 0; j < kUpdK / 2; ++j) {
-      const int k = ch * kUpdK + sc + 2 * j;
+    for (int j = 0; j < kUpdK / 8; ++j) {
+      const int k = ch * kUpdK + sc + 8 * j;
       const bool kv = k < kb;
       const int kc = kv ? k : 0;
       const double a = LD[lrow + (long)(k0 + kc) * ldld];
@@ -782,19 +783,19 @@ __global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* cons
   };
   auto stage = [&](int buf) {
 #pragma unroll
-    for (int j = 0; j < kUpdK / 2; ++j) {
-      sL[buf][(sc + 2 * j) * kUpdLd + sr] = stL[j];
-      sW[buf][(sc + 2 * j) * kUpdLd + sr] = stW[j];
+    for (int j = 0; j < kUpdK / 8; ++j) {
+      sL[buf][(sc + 8 * j) * kUpdLd + sr] = stL[j];
+      sW[buf][(sc + 8 * j) * kUpdLd + sr] = stW[j];
     }
   };
   fetch(0);
-  d4 acc[4][4];
+  d4 acc[2][2];
   if (active) {
 #pragma unroll
-    for (int x = 0; x < 4; ++x) {
+    for (int x = 0; x < 2; ++x) {
       const int i = min(row0 + wi + 16 * x + lr, n - 1);
 #pragma unroll
-      for (int y = 0; y < 4; ++y)
+      for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
@@ -813,15 +814,15 @@ __global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* cons
       const int ksteps = min(kUpdK / 4, nks - ch * (kUpdK / 4));
       for (int u = 0; u < ksteps; ++u) {
         const int kk = (4 * u + lk) * kUpdLd;
-        double lo[4], wo[4];
+        double lo[2], wo[2];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) lo[x] = L0[kk + 16 * x];
+        for (int x = 0; x < 2; ++x) lo[x] = L0[kk + 16 * x];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) wo[y] = W0[kk + 16 * y];
+        for (int y = 0; y < 2; ++y) wo[y] = W0[kk + 16 * y];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = mfma16x16x4(wo[y], lo[x], acc[x][y]);
+          for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(wo[y], lo[x], acc[x][y]);
       }
     }
     if (ch + 1 < nch) {
@@ -831,10 +832,10 @@ __global__ __launch_bounds__(256) void k_trailing_update_lds(int n, double* cons
   }
   if (!active) return;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
+  for (int x = 0; x < 2; ++x) {
     const int i = row0 + wi + 16 * x + lr;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
+    for (int y = 0; y < 2; ++y) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jc = col0 + wj + 16 * y + lk + 4 * r;
@@ -998,7 +999,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const int tu = prof_begin(ph, kProfUpdate);
       if (n - k1_lb >= kUpdateWideMin) {
         const long T = ceil_div(n - k1_lb, 128);
-        SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
+        SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st, n,
                   fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
       } else {
         const long T = ceil_div(n - k1_lb, 64);
