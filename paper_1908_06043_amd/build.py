@@ -30,8 +30,13 @@ def hipcc():
     raise RuntimeError("hipcc not found: the HIP library cannot be built")
 
 
+# -amdgpu-mfma-vgpr-form keeps MFMA accumulators in ordinary VGPRs.  Without it the
+# GEMM and adjoint SYR2K loops copy every accumulator between AGPRs and VGPRs on
+# each K chunk (64 and 128 copies per chunk), which costs more issue slots than
+# the MFMAs themselves; with it no kernel gains registers or spills.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-result", "-Wno-unused-function", "-Wno-unused-value"]
 
 

@@ -5,7 +5,8 @@
 //
 // GEMM design (gfx950): 64x64 output tile per 256-thread workgroup, four
 // wavefronts each owning 32x32 as 2x2 v_mfma_f64_16x16x4 blocks; K staged
-// through LDS in chunks of 16 (sA[k][i], sB[k][j]).  The MFMA A operand carries
+// through double-buffered LDS in chunks of 16 (sA[k][i], sB[k][j]), the next
+// chunk's loads in flight during the current chunk's MFMAs.  The MFMA A operand carries
 // op(B)^T and the B operand op(A)^T so that accumulator register r of lane l
 // holds C(i0 + l%16, j0 + l/16 + 4r): sixteen consecutive rows of one column,
 // i.e. coalesced column-major stores.  Transposed operands only change the
@@ -21,8 +22,8 @@ constexpr int GK = 16;   // K chunk
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ double sA[GK][GT + 2];
-  __shared__ double sB[GK][GT + 2];
+  __shared__ double sA[2][GK][GT + 2];
+  __shared__ double sB[2][GK][GT + 2];
   const int zb = blockIdx.z;
   const int b = zb / g.splits, sp = zb % g.splits;
   const int m = g.m ? g.m[b] : g.m0;
@@ -43,46 +44,74 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = kb; k0 < ke; k0 += GK) {
-#pragma unroll
-    for (int q = 0; q < GK * GT / 256; ++q) {
-      const int e = tid + 256 * q;
-      int ii, kk;
-      if (!TA) {
-        ii = e & 63;
-        kk = e >> 6;
-      } else {
-        kk = e & 15;
-        ii = e >> 4;
-      }
-      const int gi = i0 + ii, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < m && gk < ke) v = TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda];
-      sA[kk][ii] = v;
-      int jj, kk2;
-      if (!TB) {
-        kk2 = e & 15;
-        jj = e >> 4;
-      } else {
-        jj = e & 63;
-        kk2 = e >> 6;
-      }
-      const int gj = j0 + jj, gk2 = k0 + kk2;
-      double u = 0.0;
-      if (gj < n && gk2 < ke) u = TB ? B[gj + (long)gk2 * g.ldb] : B[gk2 + (long)gj * g.ldb];
-      sB[kk2][jj] = u;
+  // Staging: element e = tid + 256 q of a chunk, read along the contiguous
+  // dimension of each operand; the next chunk is in registers while the current
+  // one feeds the MFMAs, so one barrier per chunk suffices.
+  constexpr int NQ = GK * GT / 256;
+  double ra[NQ], rb[NQ];
+  auto a_pos = [&](int q, int& ii, int& kk) {
+    const int e = tid + 256 * q;
+    if (!TA) {
+      ii = e & 63;
+      kk = e >> 6;
+    } else {
+      kk = e & 15;
+      ii = e >> 4;
     }
-    __syncthreads();
+  };
+  auto b_pos = [&](int q, int& jj, int& kk) {
+    const int e = tid + 256 * q;
+    if (!TB) {
+      kk = e & 15;
+      jj = e >> 4;
+    } else {
+      jj = e & 63;
+      kk = e >> 6;
+    }
+  };
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int ii, kk, jj, kk2;
+      a_pos(q, ii, kk);
+      b_pos(q, jj, kk2);
+      const int gi = i0 + ii, gk = k0 + kk;
+      ra[q] = (gi < m && gk < ke) ? (TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda]) : 0.0;
+      const int gj = j0 + jj, gk2 = k0 + kk2;
+      rb[q] = (gj < n && gk2 < ke) ? (TB ? B[gj + (long)gk2 * g.ldb] : B[gk2 + (long)gj * g.ldb]) : 0.0;
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      int ii, kk, jj, kk2;
+      a_pos(q, ii, kk);
+      b_pos(q, jj, kk2);
+      sA[buf][kk][ii] = ra[q];
+      sB[buf][kk2][jj] = rb[q];
+    }
+  };
+  if (kb < ke) {
+    fetch(kb);
+    stage(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kb; k0 < ke; k0 += GK) {
+    const bool more = k0 + GK < ke;
+    if (more) fetch(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
-      const double bA0 = sA[kk + lk][wi + lr], bA1 = sA[kk + lk][wi + 16 + lr];
-      const double aB0 = sB[kk + lk][wj + lr], aB1 = sB[kk + lk][wj + 16 + lr];
+      const double bA0 = sA[buf][kk + lk][wi + lr], bA1 = sA[buf][kk + lk][wi + 16 + lr];
+      const double aB0 = sB[buf][kk + lk][wj + lr], aB1 = sB[buf][kk + lk][wj + 16 + lr];
       acc[0][0] = mfma16x16x4(aB0, bA0, acc[0][0]);
       acc[0][1] = mfma16x16x4(aB1, bA0, acc[0][1]);
       acc[1][0] = mfma16x16x4(aB0, bA1, acc[1][0]);
       acc[1][1] = mfma16x16x4(aB1, bA1, acc[1][1]);
     }
+    if (more) stage(buf ^ 1);
     __syncthreads();
+    buf ^= 1;
   }
   if (g.splits > 1) {
     double* P = g.partial + ((long)b * g.splits + sp) * g.pstride;
