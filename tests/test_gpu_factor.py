@@ -38,6 +38,36 @@ def test_random_symmetric_inertia_and_backward_error(gpu_lib, n, seed):
     assert inertia_of(D) == f.inertia
 
 
+@pytest.mark.parametrize("n,seed", [(1153, 11), (1537, 12)])
+def test_random_symmetric_wide_update_tiles(gpu_lib, n, seed):
+    """Orders above 1024 take the 128x128 LDS-staged trailing update; random
+    symmetric matrices pivot often, so panel widths (the update rank) and tile
+    tails are ragged."""
+    C = inputs.random_symmetric(n, seed)
+    f = gpu_lib.ldlt_factor(dev(C), dev(np.eye(n)), 0.0)
+    w = np.linalg.eigvalsh(C)
+    assert f.inertia == (int(np.sum(w < 0)), 0, int(np.sum(w > 0)))
+    LD = f.LD.cpu().numpy()
+    ip = f.ipiv.cpu().numpy()
+    assert backward_error(C, LD, ip) <= 100 * n * U
+    L, D, perm, blocks = decode_factor(LD, ip)
+    assert inertia_of(D) == f.inertia
+
+
+def test_multi_shift_random_n1300_wide_update(gpu_lib):
+    """Five shifts in lock step, each with its own panel widths, through the wide update."""
+    n = 1300
+    C = inputs.random_symmetric(n, 13)
+    w = np.linalg.eigvalsh(C)
+    sig = inputs.safe_shifts(w, np.linspace(w[0] - 0.1, w[-1] + 0.1, 5))
+    facs = gpu_lib.ldlt_factor_multi(dev(C), dev(np.eye(n)), sig)
+    assert [f.inertia[0] for f in facs] == [int(np.sum(w < s)) for s in sig]
+    assert all(sum(f.inertia) == n and f.inertia[1] == 0 for f in facs)
+    for s, f in zip(sig[1:4], facs[1:4]):
+        Cs = C - s * np.eye(n)
+        assert backward_error(Cs, f.LD.cpu().numpy(), f.ipiv.cpu().numpy()) <= 100 * n * U
+
+
 def test_pencil_n200_inertia_matches_construction_and_oracle(gpu_lib):
     P = inputs.pencil_clusters4(200, 0)
     sig = inputs.safe_shifts(P.lam, np.linspace(-2.1, 2.1, 15))
