@@ -319,16 +319,19 @@ __global__ __launch_bounds__(256) void k_fast_commit(int n, double* const* LDs, 
   const double* Dv = aux;
   const double* cin = aux + nb;
   const unsigned long long* cout = reinterpret_cast<const unsigned long long*>(aux + 2 * nb);
-  if (tid == 0) {
-    int j = 0;
-    for (; j < nbe; ++j) {
+  // the accepted prefix: lane j of the first wavefront judges column j (nbe <= 64),
+  // and the first rejected column is the lowest set bit of the ballot
+  if (tid < 64) {
+    const int j = tid;
+    bool ok = false;
+    if (j < nbe) {
       const double d = Dv[j];
       const double cm = fmax(cin[j], u64_to_f64(cout[j]));
-      bool ok = isfinite(d) && d != 0.0 && isfinite(cm) && cin[j] == cin[j];
+      ok = isfinite(d) && d != 0.0 && isfinite(cm) && cin[j] == cin[j];
       if (PIVOT) ok = ok && fabs(d) >= kBkAlpha * cm;
-      if (!ok) break;
     }
-    js = j;
+    const unsigned long long bad = __ballot(!ok);
+    if (tid == 0) js = bad ? min(__ffsll((long long)bad) - 1, nbe) : nbe;
   }
   __syncthreads();
   const int jst = js;
@@ -343,17 +346,15 @@ __global__ __launch_bounds__(256) void k_fast_commit(int n, double* const* LDs, 
       colpanels[s][col] = st.npanel;
     }
   }
-  if (c == 0 && tid == 0) {
-    long neg = 0, pos = 0;
-    for (int q = 0; q < jst; ++q) {
-      if (Dv[q] < 0.0)
-        ++neg;
-      else
-        ++pos;
+  if (c == 0 && tid < 64) {
+    const bool acc = tid < jst;
+    const bool negd = acc && Dv[tid] < 0.0;
+    const unsigned long long negm = __ballot(negd), posm = __ballot(acc && !negd);
+    if (tid == 0) {
+      states[s].jstart = jst;
+      states[s].neg += __popcll(negm);
+      states[s].pos += __popcll(posm);
     }
-    states[s].jstart = jst;
-    states[s].neg += neg;
-    states[s].pos += pos;
   }
 }
 
