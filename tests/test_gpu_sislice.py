@@ -88,6 +88,16 @@ def test_n1000_scf_pencil(gpu_lib):
     check_result(P, out, 100)
 
 
+@pytest.mark.parametrize("max_basis", [48, 64])
+def test_n1000_small_basis_caps(gpu_lib, max_basis):
+    """A restart keeps max_basis - 4 blocks (16 and 32 vectors here): the smaller
+    caps take more restart cycles and still meet the bar."""
+    P = inputs.pencil_scf(1000, 100, seed=1)
+    opts = gpu_lib.default_opts(max_basis=max_basis)
+    out = gpu_lib.solve(dev(P.A), dev(P.B), 100, 8, opts=opts)
+    check_result(P, out, 100)
+
+
 def test_full_size_n4096_ne400_16_shifts(gpu_lib):
     """The benchmark workload: N=4096, lowest 400, 16 KPM shifts, Lanczos block 8."""
     P = inputs.pencil_scf(4096, 400, seed=0)
