@@ -420,7 +420,25 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
       double b0 = 0.0, b1 = 0.0;
       const double* L0 = LD + i0 + (long)k0 * ldld;
       const double* L1 = LD + (two ? i1 : i0) + (long)k0 * ldld;
+      // eight columns per step with all sixteen loads issued first (one wait per
+      // step); even columns accumulate into a, odd ones into b, in column order
       int p = 0;
+      for (; p + 8 <= j; p += 8) {
+        double x0[8], x1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          x0[u] = L0[(long)(p + u) * ldld];
+          x1[u] = L1[(long)(p + u) * ldld];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u += 2) {
+          const double w0 = wk[p + u], w1 = wk[p + u + 1];
+          a0 -= x0[u] * w0;
+          b0 -= x0[u + 1] * w1;
+          a1 -= x1[u] * w0;
+          b1 -= x1[u + 1] * w1;
+        }
+      }
       for (; p + 1 < j; p += 2) {
         const double w0 = wk[p], w1 = wk[p + 1];
         const double x00 = L0[(long)p * ldld], x01 = L0[(long)(p + 1) * ldld];
@@ -470,7 +488,15 @@ __global__ __launch_bounds__(1024) void k_bk_panel(int n, double* const* LDs, lo
       for (int i = k + tid; i < n; i += NT) {
         double acc = (i < imax) ? LD[imax + (long)i * ldld] : LD[i + (long)imax * ldld];
         const double* Lr = LD + i + (long)k0 * ldld;
-        for (int p = 0; p < j; ++p) acc -= Lr[(long)p * ldld] * wk[p];
+        int p = 0;
+        for (; p + 8 <= j; p += 8) {
+          double x[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) x[u] = Lr[(long)(p + u) * ldld];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc -= x[u] * wk[p + u];
+        }
+        for (; p < j; ++p) acc -= Lr[(long)p * ldld] * wk[p];
         Wp[i + (long)(j + 1) * ldw] = acc;
         if (i == imax) {
           sh_arr = fabs(acc);
