@@ -2,18 +2,27 @@
 // (Section 2.1: (V^T A V) Q = Q Omega) and of the Lanczos tridiagonal-block
 // matrices.
 //
-// Design (gfx950): one 1024-thread workgroup per matrix, everything resident in
-// LDS: the lower triangle of A packed (m(m+1)/2 doubles) and the eigenvector
-// matrix V (m x m), which for m <= 112 fits the 160 KB of a CU.  Cyclic Jacobi in
-// the parallel round-robin order: each round rotates m/2 disjoint (p, q) pairs
-// (Golub & Van Loan, symmetric Schur 2x2 rotation), applies all of them to A as
-// independent 2x2 blocks J_k^T A_{kl} J_l and to the columns of V, then moves to
-// the next pairing.  A rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|)
-// (relative threshold, so tiny and large eigenvalues both converge to full
-// relative accuracy); the iteration stops after a sweep without rotations.
+// Design (gfx950): two kernels per batch.
+//  k_syevj: one 1024-thread workgroup per matrix, the lower triangle of A packed
+//  in LDS (m(m+1)/2 doubles).  Cyclic Jacobi in the parallel round-robin order:
+//  each round rotates m/2 disjoint (p, q) pairs (Golub & Van Loan, symmetric
+//  Schur 2x2 rotation) and applies all of them to A as independent 2x2 blocks
+//  J_k^T A_{kl} J_l, then moves to the next pairing.  The (c, s) of every pair of
+//  every round are written to a rotation record in device memory; at the end the
+//  eigenvalues are sorted ascending and the rank of each diagonal position kept.
+//  k_syevj_vecs: forms V = J_1 J_2 ... by replaying the record on rows of the
+//  identity.  Rows of V never mix, so one wavefront owns two rows in LDS (lane k
+//  applies pair k of each round) and needs no workgroup barrier, and the rows of
+//  one matrix spread over many CUs instead of sharing the LDS bandwidth of the one
+//  CU that runs the rotations.
+// A rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (relative
+// threshold, so tiny and large eigenvalues both converge to full relative
+// accuracy); the iteration stops after a sweep without rotations.
 #include "common.hpp"
 #include "eig.hpp"
 #include "handle.hpp"
+
+#include <algorithm>
 
 namespace sislice {
 
@@ -30,7 +39,12 @@ __device__ __forceinline__ int rr_player(int pos, int r, int M) {
   return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (M - 1));
 }
 
-__global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
+// Per-matrix metadata after k_syevj: [0] sweeps that rotated, [1 + i] rank of
+// diagonal position i in ascending order.
+constexpr int kMetaStride = kEigMax + 16;
+
+__global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__ rot, long rstride,
+                                                int* __restrict__ meta) {
   extern __shared__ double sh[];
   const int b = blockIdx.x, tid = threadIdx.x;
   const int m = a.m[b];
@@ -38,27 +52,25 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
   const int M = m + (m & 1);
   const int h = M / 2;
   const int npk = m * (m + 1) / 2;
-  double* A = sh;                    // packed lower
-  double* V = sh + npk;              // V[j * m + i]
-  double* cs = V + m * m;            // [h]
-  double* sn = cs + h;               // [h]
+  double* A = sh;              // packed lower
+  double* cs = A + npk;        // [h]
+  double* sn = cs + h;         // [h]
   int* pp = reinterpret_cast<int*>(sn + h);  // [h]
   int* qq = pp + h;                          // [h]
-  int* flag = qq + h;                        // [2]
+  int* flag = qq + h;                        // [4], then rank [m]
+  double2* rb = rot + (long)b * rstride;     // [sweep][round][pair]
   const double* Ain = a.A[b];
   const long lda = a.lda;
   for (int e = tid; e < m * m; e += blockDim.x) {
     const int i = e % m, j = e / m;
     if (i >= j) A[pidx(i, j, m)] = Ain[i + (long)j * lda];
-    V[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
   const int ntask_blk = h * (h + 1) / 2;
-  // Each thread's tasks are the same in every round: decode them once.
-  //   A: 2x2 block tasks t = tid + 1024 j -> pair indices (k >= l)
-  //   V: column-pair tasks t = tid + 1024 j -> (row i, pair k)
-  constexpr int JA = 2, JV = 7;  // enough for m <= kEigMax (h <= 56)
-  int tk[JA], tl[JA], vi[JV], vk[JV];
+  // Each thread's 2x2 block tasks t = tid + 1024 j -> pair indices (k >= l) are
+  // the same in every round: decode them once.
+  constexpr int JA = 2;  // enough for m <= kEigMax (h <= 56)
+  int tk[JA], tl[JA];
 #pragma unroll
   for (int j = 0; j < JA; ++j) {
     const int t = tid + 1024 * j;
@@ -72,15 +84,10 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
     tk[j] = k;
     tl[j] = l;
   }
-#pragma unroll
-  for (int j = 0; j < JV; ++j) {
-    const int t = tid + 1024 * j;
-    vi[j] = (t < m * h) ? t % m : -1;
-    vk[j] = (t < m * h) ? t / m : 0;
-  }
   // flag[0]: a rotation happened in this sweep; rflag[r & 1]: in round r (the slot
   // of the next round is cleared by thread 0 while the current one is being set)
   int* rflag = flag + 2;
+  int nsw = 0;
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
     if (tid == 0) {
       flag[0] = 0;
@@ -115,9 +122,10 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
         qq[tid] = q;
         cs[tid] = c;
         sn[tid] = s;
+        rb[(long)(sweep * (M - 1) + r) * h + tid] = make_double2(c, s);
       }
       __syncthreads();
-      if (rflag[r & 1] == 0) continue;  // no rotation in this round: A and V unchanged
+      if (rflag[r & 1] == 0) continue;  // no rotation in this round: A unchanged
       // A <- J^T A J as independent 2x2 blocks of pair pairs (k >= l)
 #pragma unroll
       for (int j = 0; j < JA; ++j) {
@@ -152,26 +160,16 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
           if (vq_k && vq_l) A[i11] = sl * r10 + cl * r11;
         }
       }
-      // V <- V J
-#pragma unroll
-      for (int j = 0; j < JV; ++j) {
-        const int i = vi[j], k = vk[j];
-        if (i < 0) continue;
-        const double c = cs[k], s = sn[k];
-        if (s == 0.0) continue;
-        const int p = pp[k], q = qq[k];
-        const double vp = V[p * m + i], vq = V[q * m + i];
-        V[p * m + i] = c * vp - s * vq;
-        V[q * m + i] = s * vp + c * vq;
-      }
       __syncthreads();
     }
     if (flag[0] == 0) break;
+    ++nsw;
     __syncthreads();
   }
   __syncthreads();
   // sort ascending: rank of each eigenvalue (ties by index)
-  int* rank = flag + 2;
+  int* rank = flag + 4;
+  int* mb = meta + (long)b * kMetaStride;
   for (int i = tid; i < m; i += blockDim.x) {
     const double wi = A[pidx(i, i, m)];
     int rk = 0;
@@ -180,24 +178,99 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a) {
       rk += (wj < wi) || (wj == wi && j < i);
     }
     rank[i] = rk;
+    mb[1 + i] = rk;
   }
+  if (tid == 0) mb[0] = nsw;
   __syncthreads();
   double* W = a.W[b];
+  for (int i = tid; i < m; i += blockDim.x) W[rank[i]] = A[pidx(i, i, m)];
+}
+
+constexpr int kVecRowsPerWave = 2;
+constexpr int kVecWaves = 4;
+constexpr int kVecRows = kVecRowsPerWave * kVecWaves;  // rows of V per workgroup
+constexpr int kVecPf = 16;                              // rounds of (c, s) loaded ahead
+
+__global__ __launch_bounds__(64 * kVecWaves) void k_syevj_vecs(EigArgs a,
+                                                               const double2* __restrict__ rot,
+                                                               long rstride,
+                                                               const int* __restrict__ meta) {
+  __shared__ double Vs[kVecRows][kEigMax];
+  const int b = blockIdx.x;
+  const int m = a.m[b];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.y * kVecRows + w * kVecRowsPerWave;  // first row of this wavefront
+  if (m <= 0 || i0 >= m) return;  // uniform per wavefront; no workgroup barrier follows
+  const int M = m + (m & 1), h = M / 2, R = M - 1;
+  const int* mb = meta + (long)b * kMetaStride;
+  const long total = (long)mb[0] * R;  // rounds to replay
+  const bool has1 = i0 + 1 < m;
+  double* v0 = Vs[w * kVecRowsPerWave];
+  double* v1 = Vs[w * kVecRowsPerWave + 1];
+  for (int j = lane; j < m; j += 64) {
+    v0[j] = (j == i0) ? 1.0 : 0.0;
+    v1[j] = (j == i0 + 1) ? 1.0 : 0.0;
+  }
+  const bool act = lane < h;
+  // players of pair `lane` in round r (the round-robin of k_syevj), advanced by one
+  // position per round: 1..R cyclically, player 0 fixed
+  int pa = lane, pb = M - 1 - lane;
+  const double2* rb = rot + (long)b * rstride + lane;
+  double2 cur[kVecPf], nxt[kVecPf];
+#pragma unroll
+  for (int j = 0; j < kVecPf; ++j)
+    cur[j] = (act && j < total) ? rb[(long)j * h] : make_double2(1.0, 0.0);
+  for (long g0 = 0; g0 < total; g0 += kVecPf) {
+#pragma unroll
+    for (int j = 0; j < kVecPf; ++j) {
+      const long g = g0 + kVecPf + j;
+      nxt[j] = (act && g < total) ? rb[g * h] : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int j = 0; j < kVecPf; ++j) {
+      if (g0 + j >= total) break;  // uniform per wavefront
+      // the writes of the previous round (other lanes' columns) are read below
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_wave_barrier();
+      const double c = cur[j].x, s = cur[j].y;
+      const int p = min(pa, pb), q = max(pa, pb);
+      if (act && s != 0.0 && q < m) {
+        const double x0 = v0[p], y0 = v0[q];
+        v0[p] = c * x0 - s * y0;
+        v0[q] = s * x0 + c * y0;
+        if (has1) {
+          const double x1 = v1[p], y1 = v1[q];
+          v1[p] = c * x1 - s * y1;
+          v1[q] = s * x1 + c * y1;
+        }
+      }
+      if (lane != 0) pa = (pa == R) ? 1 : pa + 1;
+      pb = (pb == R) ? 1 : pb + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < kVecPf; ++j) cur[j] = nxt[j];
+  }
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
   double* Vout = a.V[b];
   const long ldv = a.ldv;
-  for (int i = tid; i < m; i += blockDim.x) W[rank[i]] = A[pidx(i, i, m)];
-  for (int e = tid; e < m * m; e += blockDim.x) {
-    const int i = e % m, j = e / m;
-    Vout[i + (long)rank[j] * ldv] = V[j * m + i];
+  for (int j = lane; j < m; j += 64) {
+    const long col = (long)mb[1 + j] * ldv;
+    Vout[i0 + col] = v0[j];
+    if (has1) Vout[i0 + 1 + col] = v1[j];
   }
 }
 
 size_t eig_lds_bytes(int mmax) {
   const int M = mmax + (mmax & 1);
   const int h = M / 2;
-  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + (size_t)mmax * mmax + 2 * h) +
-         sizeof(int) * (2 * h + 2 + mmax) + 64;
+  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + 2 * h) +
+         sizeof(int) * (2 * h + 4 + mmax) + 64;
 }
+
+// Rotation records are staged per chunk of the batch so that their workspace
+// stays near this size however large the batch is.
+constexpr size_t kRotChunkBytes = size_t(256) << 20;
 
 void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
   static std::once_flag attr;
@@ -205,12 +278,36 @@ void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
     SL_HIP(hipFuncSetAttribute((const void*)k_syevj, hipFuncAttributeMaxDynamicSharedMemorySize,
                                160 * 1024));
   });
+  SL_CHECK_ARG(mmax <= kEigMax, "projected problem too large for the LDS eigensolver");
+  SL_CHECK_ARG(a.max_sweeps >= 1, "max_sweeps must be positive");
+  if (batch <= 0 || mmax <= 0) return;
   const size_t lds = eig_lds_bytes(mmax);
-  SL_CHECK_ARG(lds <= 160 * 1024, "projected problem too large for the LDS eigensolver");
-  const int tk = prof_begin(current_handle(), kProfEig);
-  SL_LAUNCH(k_syevj, dim3(batch), dim3(1024), lds, st, a);
-  SL_LAUNCH_CHECK();
-  prof_end(current_handle(), tk);
+  sislice_handle* h = current_handle();
+  SL_CHECK_ARG(h != nullptr, "no current handle for the eigensolver workspace");
+  const int Mx = mmax + (mmax & 1);
+  const long rstride = (long)a.max_sweeps * (Mx - 1) * (Mx / 2);  // double2 per matrix
+  const size_t rot_bytes = (size_t)rstride * sizeof(double2);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(batch, kRotChunkBytes / rot_bytes));
+  const size_t meta_off = ((size_t)chunk * rot_bytes + 255) & ~size_t(255);
+  char* ws = static_cast<char*>(
+      ws_get(h, kBufEigRot, meta_off + (size_t)chunk * kMetaStride * sizeof(int)));
+  double2* rot = reinterpret_cast<double2*>(ws);
+  int* meta = reinterpret_cast<int*>(ws + meta_off);
+  const int tk = prof_begin(h, kProfEig);
+  for (int c0 = 0; c0 < batch; c0 += chunk) {
+    const int nb = std::min(chunk, batch - c0);
+    EigArgs c = a;
+    c.m = a.m + c0;
+    c.A = a.A + c0;
+    c.W = a.W + c0;
+    c.V = a.V + c0;
+    SL_LAUNCH(k_syevj, dim3(nb), dim3(1024), lds, st, c, rot, rstride, meta);
+    SL_LAUNCH_CHECK();
+    SL_LAUNCH(k_syevj_vecs, dim3(nb, (mmax + kVecRows - 1) / kVecRows), dim3(64 * kVecWaves), 0,
+              st, c, rot, rstride, meta);
+    SL_LAUNCH_CHECK();
+  }
+  prof_end(h, tk);
 }
 
 }  // namespace sislice

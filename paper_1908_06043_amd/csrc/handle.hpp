@@ -14,7 +14,7 @@ struct sislice_handle {
     void* ptr = nullptr;
     size_t cap = 0;
   };
-  Buf bufs[9];
+  Buf bufs[10];
   void* host_stage = nullptr;  // pinned staging for small host<->device records
   size_t host_cap = 0;
   unsigned* sync = nullptr;  // epoch flags and ticket counters of the persistent solves
@@ -70,7 +70,8 @@ enum BufId {
   kBufMisc = 5,
   kBufLanczos = 6,
   kBufRing = 7,
-  kBufAdjoint = 8
+  kBufAdjoint = 8,
+  kBufEigRot = 9
 };
 
 // Returns a device buffer of at least `bytes`, reallocating (contents lost) if needed.
