@@ -415,7 +415,10 @@ uint64_t sislice_splitmix64(uint64_t seed, uint64_t i);
  * Rayleigh-Ritz (Sec. 2.1): `batch` matrices of order m <= 112, device,
  * column-major with leading dimension lda, lower triangle read.  W device
  * double[batch*m] eigenvalues ascending; V device batch*(m x m) eigenvectors
- * (leading dimension m).  Asynchronous. */
+ * (leading dimension m).  The rotations are recorded in a workspace of the
+ * handle (about 4 MB per matrix of order 112, batches above 64 such matrices
+ * are processed in chunks); it grows on the first call that needs more, and a
+ * failed growth returns SISLICE_ERR_ALLOC.  Asynchronous. */
 sislice_status sislice_sym_eig(sislice_handle *h, int32_t m, int32_t batch, const double *A,
                                int64_t lda, double *W, double *V);
 
