@@ -228,13 +228,14 @@ __global__ __launch_bounds__(64 * kVecWaves) void k_syevj_vecs(EigArgs a,
     }
 #pragma unroll
     for (int j = 0; j < kVecPf; ++j) {
-      if (g0 + j >= total) break;  // uniform per wavefront
+      // guard rather than break: the loop unrolls fully and cur[] stays in registers
+      const bool live = g0 + j < total;  // uniform per wavefront
       // the writes of the previous round (other lanes' columns) are read below
       asm volatile("" ::: "memory");
       __builtin_amdgcn_wave_barrier();
       const double c = cur[j].x, s = cur[j].y;
       const int p = min(pa, pb), q = max(pa, pb);
-      if (act && s != 0.0 && q < m) {
+      if (live && act && s != 0.0 && q < m) {
         const double x0 = v0[p], y0 = v0[q];
         v0[p] = c * x0 - s * y0;
         v0[q] = s * x0 + c * y0;
