@@ -25,13 +25,13 @@ Planners.
 * ``plan_cluster``: DOSCluster on a grid of n_omega = 10 k points of
   [a, omega_top]; intervals with gamma = Phi(u) - Phi(l) < 2 merge into the
   adjacent interval with fewer estimated eigenvalues; intervals with gamma > 50
-  are searched again with n_omega' = 2 C(l, u) / C(a, omega_top) n_omega points
-  (at least 10) and replaced when that finds two or more; repeated until nothing
-  changes (at most 20 rounds); then the safeguards: while fewer than n_s
-  intervals, the one with the most eigenvalues is split at its CDOS midpoint;
-  while more, the one with the fewest merges into its adjacent neighbour with
-  fewer (or, isolated, into the nearest); each shift is the DOS expectation over
-  its interval (the psi formula).
+  are searched again with n_omega' = 2 C(l, u) / C(a, omega_top) n_omega points,
+  C = ceil(gamma) (rounded half up, at least 10) and replaced when that finds two
+  or more; repeated until nothing changes (at most 20 rounds); then the
+  safeguards: while fewer than n_s intervals, the one with the most eigenvalues
+  is split at its CDOS midpoint; while more, the one with the fewest merges into
+  its adjacent neighbour with fewer (or, isolated, into the nearest); each shift
+  is the DOS expectation over its interval (the psi formula).
 """
 from __future__ import annotations
 
@@ -210,20 +210,26 @@ def _merge_small(dos, I, tol=2.0):
     return I
 
 
-def plan_cluster(dos, ritz, n_e, n_s, k, top_margin=2.0, big=50.0):
-    """DOSCluster with refinement, safeguards and DOS-expectation shifts."""
-    a, top = window(dos, n_e, n_s, top_margin)
-    n_omega = 10 * k
-    total = _gamma(dos, (a, top))
-    I = dos_cluster(dos, a, top, n_omega, ritz)
-    for _ in range(20):
+def count(dos, iv):
+    """C(l, u) = ceil(gamma(l, u)), the approximate eigenvalue count of Sec. 3.1."""
+    return math.ceil(_gamma(dos, iv))
+
+
+def refine(dos, I, a, top, n_omega, ritz, big=50.0, rounds=20):
+    """Refinement steps 2-4 of Sec. 3.1: merge intervals with gamma < 2 into the
+    adjacent interval with fewer estimated eigenvalues; rerun DOSCluster on every
+    interval with gamma > big over n_omega' = 2 C(l, u) / C(a, top) n_omega grid
+    points (rounded half up; at least 10 points is this project's own floor) and
+    replace it when that finds two or more intervals; repeat until nothing is
+    replaced (at most `rounds` times)."""
+    c_all = count(dos, (a, top))
+    for _ in range(rounds):
         I = _merge_small(dos, I)
         new = []
         grew = False
         for iv in I:
-            g = _gamma(dos, iv)
-            if g > big:
-                nw = max(10, int(math.floor(2.0 * g / total * n_omega + 0.5)))
+            if _gamma(dos, iv) > big:
+                nw = max(10, int(math.floor(2.0 * count(dos, iv) / c_all * n_omega + 0.5)))
                 sub = dos_cluster(dos, iv[0], iv[1], nw, ritz)
                 if len(sub) >= 2:
                     new.extend(sub)
@@ -233,6 +239,16 @@ def plan_cluster(dos, ritz, n_e, n_s, k, top_margin=2.0, big=50.0):
         I = sorted(new)
         if not grew:
             break
+    return I
+
+
+def safeguards(dos, I, n_s):
+    """Exactly n_s intervals (Sec. 3.1 safeguards): while too few, split the
+    interval with the most estimated eigenvalues at its CDOS midpoint (ties: the
+    lower one); while too many, merge the one with the fewest (ties: the lower
+    one) into its adjacent neighbour with fewer (ties: the lower one), or, when it
+    has no adjacent neighbour, into the nearer of its list neighbours."""
+    I = list(I)
     while len(I) < n_s:
         j = max(range(len(I)), key=lambda q: (_gamma(dos, I[q]), -q))
         l, u = I[j]
@@ -247,6 +263,16 @@ def plan_cluster(dos, ritz, n_e, n_s, k, top_margin=2.0, big=50.0):
         lo, hi = min(I[t][0], I[j][0]), max(I[t][1], I[j][1])
         keep = [I[q] for q in range(len(I)) if q not in (j, t)]
         I = sorted(keep + [(lo, hi)])
+    return I
+
+
+def plan_cluster(dos, ritz, n_e, n_s, k, top_margin=2.0, big=50.0):
+    """DOSCluster with refinement, safeguards and DOS-expectation shifts."""
+    a, top = window(dos, n_e, n_s, top_margin)
+    n_omega = 10 * k
+    I = dos_cluster(dos, a, top, n_omega, ritz)
+    I = refine(dos, I, a, top, n_omega, ritz, big)
+    I = safeguards(dos, I, n_s)
     shifts = np.array([dos.expectation(l, u) for l, u in I])
     return np.sort(shifts), top, I
 

@@ -43,25 +43,24 @@ def lloyd(x, c0, max_iter=300):
     return c, lab
 
 
-def kmeanspp_init(x, k, seed):
+def kmeanspp_from_draws(x, k, u):
+    """k-means++ seeding from given uniform draws u[0..k) in [0, 1): the first
+    centre is point floor(u[0] n) (clamped to n - 1); centre c >= 1 is the first
+    point i whose running sum of squared distances to the nearest chosen centre,
+    D^2(x_0) + ... + D^2(x_i) (left to right), exceeds u[c] times their total.
+    A zero total (every point is a chosen centre) repeats the last centre."""
     x = np.asarray(x, dtype=np.float64)
     n = x.size
-    s = prng.derive(seed, prng.TAG_KMEANSPP)
-    draw = 0
-    u = prng.uniform(s, draw, 1)[0]
-    draw += 1
-    centres = [x[min(int(u * n), n - 1)]]
+    centres = [x[min(int(u[0] * n), n - 1)]]
     d2 = (x - centres[0]) ** 2
-    while len(centres) < k:
+    for c in range(1, k):
         total = 0.0
         for v in d2:                       # left-to-right sum in index order
             total += float(v)
-        u = prng.uniform(s, draw, 1)[0]
-        draw += 1
         if total == 0.0:
             centres.append(centres[-1])
             continue
-        target = u * total
+        target = u[c] * total
         cum = 0.0
         pick = n - 1
         for i in range(n):
@@ -72,6 +71,13 @@ def kmeanspp_init(x, k, seed):
         centres.append(x[pick])
         d2 = np.minimum(d2, (x - x[pick]) ** 2)
     return np.array(centres)
+
+
+def kmeanspp_init(x, k, seed):
+    """k-means++ with draw c taken from SplitMix64 output c of the k-means++
+    sub-stream of `seed`."""
+    s = prng.derive(seed, prng.TAG_KMEANSPP)
+    return kmeanspp_from_draws(x, k, prng.uniform(s, 0, k))
 
 
 def migrate(ritz, prev_shifts, use_kmeanspp=False, seed=0, max_iter=300):

@@ -398,7 +398,9 @@ void dos_plan(const LanczosDos& d, int64_t n_e, int64_t n_s, int mode, double to
     return;
   }
   const int nw = 10 * d.k;
-  const double total = gamma_of(d, Iv(a, top));
+  // C(l, u) = ceil(gamma(l, u)) is the paper's approximate count (Sec. 3.1); the
+  // refined grid has 2 C(l, u) / C(a, top) nw points, rounded half up, at least 10
+  const double c_all = std::ceil(gamma_of(d, Iv(a, top)));
   std::vector<Iv> I = dos_cluster(d, a, top, nw);
   for (int round = 0; round < 20; ++round) {
     I = merge_small(d, I);
@@ -407,7 +409,7 @@ void dos_plan(const LanczosDos& d, int64_t n_e, int64_t n_s, int mode, double to
     for (const Iv& iv : I) {
       const double g = gamma_of(d, iv);
       if (g > 50.0) {
-        const int nw2 = std::max(10, (int)std::floor(2.0 * g / total * nw + 0.5));
+        const int nw2 = std::max(10, (int)std::floor(2.0 * std::ceil(g) / c_all * nw + 0.5));
         std::vector<Iv> sub = dos_cluster(d, iv.first, iv.second, nw2);
         if (sub.size() >= 2) {
           nwI.insert(nwI.end(), sub.begin(), sub.end());

@@ -60,6 +60,59 @@ def test_ties_go_to_lower_centroid_and_empty_cluster_keeps_centroid():
     assert c[1] == 10.0 and np.all(lab == 0)
 
 
+def _worked_cases():
+    cases, cur = [], {}
+    for line in open(os.path.join(HERE, "golden", "kmeanspp_worked.txt")):
+        if not line.strip() or line.startswith("#"):
+            continue
+        key, *vals = line.split()
+        cur[key] = [float(v) for v in vals]
+        if key == "centres":
+            cases.append(cur)
+            cur = {}
+    return cases
+
+
+def test_kmeanspp_hand_worked_cases():
+    cases = _worked_cases()
+    assert len(cases) == 4
+    for c in cases:
+        got = kmeans.kmeanspp_from_draws(c["points"], len(c["draws"]), c["draws"])
+        assert list(got) == c["centres"]
+
+
+def test_kmeanspp_seeded_draws_are_the_splitmix64_substream():
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-3, 3, 40)
+    for seed in (0, 7, 123456789):
+        s = prng.derive(seed, prng.TAG_KMEANSPP)
+        u = [prng.uniform(s, c, 1)[0] for c in range(6)]
+        assert np.array_equal(kmeans.kmeanspp_init(x, 6, seed), kmeans.kmeanspp_from_draws(x, 6, u))
+
+
+def test_kmeanspp_d2_law():
+    # second centre over a fine uniform grid of draws: the share of draws that
+    # pick point i is D^2_i / sum D^2 up to the grid step
+    x = np.array([0.0, 1.0, 3.0, 7.0, 8.0])
+    d2 = (x - 3.0) ** 2
+    M = 5400
+    hits = np.zeros(x.size)
+    for t in range(M):
+        c = kmeans.kmeanspp_from_draws(x, 2, [0.5, (t + 0.5) / M])
+        hits[int(np.flatnonzero(x == c[1])[0])] += 1
+    assert np.all(np.abs(hits / M - d2 / d2.sum()) <= 1.0 / M)
+    # the seeded stream follows the same law: second centre given the first
+    counts = np.zeros(x.size)
+    for seed in range(12000):
+        c = kmeans.kmeanspp_init(x, 2, seed)
+        if c[0] == 3.0:
+            counts[int(np.flatnonzero(x == c[1])[0])] += 1
+    m = counts.sum()
+    p = d2 / d2.sum()
+    assert m > 1800 and counts[2] == 0
+    assert np.all(np.abs(counts / m - p) <= 4.0 * np.sqrt(p * (1 - p) / m) + 1e-12)
+
+
 def test_kmeanspp_reproducible_and_distinct():
     rng = np.random.default_rng(3)
     x = rng.uniform(-5, 5, 300)

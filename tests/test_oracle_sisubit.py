@@ -59,3 +59,17 @@ def test_algorithm2_converges_to_nearest_eigenpairs():
     assert np.max(np.abs(got - np.sort(P.lam[near]))) < 1e-12
     assert np.max(res[np.argsort(np.abs(lam - sigma))[:8]]) < 1e-12
     assert np.max(np.abs(X.T @ P.B @ X - np.eye(k))) < 1e-12
+
+
+def test_norm2_power_iteration_branch():
+    # above order 1500 the norm comes from power iteration: a symmetric matrix with
+    # a known spectrum (largest |lambda| = 3, next 2.5) in a random orthogonal basis
+    n = 1600
+    lam = np.linspace(-2.5, 2.5, n)
+    lam[n // 3] = 3.0
+    Q, _ = np.linalg.qr(np.random.default_rng(11).standard_normal((n, n)))
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    assert abs(sisubit.norm2_sym(A) - 3.0) < 1e-12
+    # a largest eigenvalue of negative sign is found by its modulus
+    assert abs(sisubit.norm2_sym(-A) - 3.0) < 1e-12
