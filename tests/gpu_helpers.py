@@ -1,5 +1,19 @@
-"""Helpers for the GPU parity tests: decode the library's documented factor format."""
+"""Helpers for the GPU parity tests: decode the library's documented factor format,
+and the host-side spectral norm that scales the tolerances."""
 import numpy as np
+import scipy.sparse.linalg as spla
+
+
+def host_norm2(A):
+    """||A||_2 of a symmetric host matrix, computed on the host (never taken from
+    the library): exact below order 1500, else the largest-magnitude eigenvalue by
+    ARPACK's Lanczos to 1e-12 relative."""
+    A = np.asarray(A)
+    if A.shape[0] <= 1500:
+        return float(np.max(np.abs(np.linalg.eigvalsh(A))))
+    v0 = np.ones(A.shape[0])
+    w = spla.eigsh(A, k=1, which="LM", tol=1e-12, v0=v0, return_eigenvectors=False)
+    return float(np.abs(w[0]))
 
 
 def decode_factor(LD, ipiv):
