@@ -121,6 +121,17 @@ sislice_status sislice_create(sislice_handle **h, int device, void *stream);
 sislice_status sislice_destroy(sislice_handle *h);
 sislice_status sislice_set_stream(sislice_handle *h, void *stream);
 
+/* Bound of the device-side waits.  The triangular solves of the shift-invert
+ * step (Algorithm 2, third step) hand row blocks between workgroups, and a
+ * workgroup polls for a block it needs; a poll that does not find it after
+ * `polls` attempts (about 1 us each; default 2^21, about 2 s) gives up so that
+ * the launch still completes, and the call that ran it (or, for the
+ * asynchronous sislice_ldlt_solve, the next synchronising call on the handle)
+ * returns SISLICE_ERR_HIP.  Correct hand-offs complete in microseconds; the
+ * bound only turns a logic fault into an error instead of a hung device.
+ * polls in [0, 2^32 - 1]; applies to the handle and its batch workers. */
+sislice_status sislice_set_wait_limit(sislice_handle *h, int64_t polls);
+
 /* Bunch-Kaufman LDL^T of C = A - sigma B (Sec. 2.1: the probe's major cost) and
  * the Sylvester inertia of D (Sec. 2.2).
  *   A, B   device, n x n, lower triangle read (lda, ldb >= n).

@@ -69,6 +69,7 @@ _SIGS = {
     "sislice_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, C.c_void_p]),
     "sislice_destroy": (C.c_int, [C.c_void_p]),
     "sislice_set_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "sislice_set_wait_limit": (C.c_int, [C.c_void_p, C.c_int64]),
     "sislice_ldlt_factor": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                       C.c_int64, C.c_double, C.c_void_p, C.c_int64, C.c_void_p,
                                       c_int64_p]),

@@ -45,6 +45,11 @@ def handle(device=None):
     return C.c_void_p(h)
 
 
+def set_wait_limit(polls, device=None):
+    """Polls after which a device-side hand-off wait gives up (sislice_set_wait_limit)."""
+    _check(_lib.load().sislice_set_wait_limit(handle(device), int(polls)), "sislice_set_wait_limit")
+
+
 def _mat(M, name):
     if not (isinstance(M, torch.Tensor) and M.is_cuda and M.dtype == torch.float64 and M.dim() == 2
             and M.shape[0] == M.shape[1] and M.is_contiguous()):

@@ -323,9 +323,12 @@ extern "C" sislice_status sislice_adjoint(sislice_handle* h, int64_t n, const do
     SL_CHECK_ARG(std::isfinite(omega_top), "omega_top must be finite");
     if (!(tol > 0.0)) tol = 1e-10;
     if (max_iter <= 0) max_iter = 500;
-    return adjoint_impl(h, (int)n, A, lda, B, ldb, (int)n_e, evals, evecs, ldx, g_evals, g_evecs,
-                        ldg, (int)n_s, sigmas, omega_top, factor_id, tol, max_iter, GA, ldga, GB,
-                        ldgb, report);
+    const sislice_status st =
+        adjoint_impl(h, (int)n, A, lda, B, ldb, (int)n_e, evals, evecs, ldx, g_evals, g_evecs, ldg,
+                     (int)n_s, sigmas, omega_top, factor_id, tol, max_iter, GA, ldga, GB, ldgb,
+                     report);
+    check_waits(h);
+    return st;
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());
     return e.status;

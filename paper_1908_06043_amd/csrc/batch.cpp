@@ -44,6 +44,7 @@ void ensure_workers(sislice_handle* h, int nw) {
       hipStreamDestroy(s);
       throw Error(st, "worker handle creation failed");
     }
+    w->wait_limit = h->wait_limit;
     h->workers.push_back(w);
     h->worker_streams.push_back(s);
   }
@@ -179,6 +180,7 @@ extern "C" sislice_status sislice_solve_batched(sislice_handle* h, int64_t count
         double top = 0.0;
         status[i] = solve_impl(w, p.n, p.A, p.lda, p.B, p.ldb, p.n_e, p.n_s, nullptr, &top, oi,
                                p.evals, p.evecs, p.ldx, p.resid, &rep);
+        check_waits(w);
         conv[i] = (status[i] == SISLICE_OK || status[i] == SISLICE_NOT_CONVERGED) ? rep.n_converged : 0;
       } catch (const Error& e) {
         std::fprintf(stderr, "sislice: problem %d: %s\n", i, e.what());

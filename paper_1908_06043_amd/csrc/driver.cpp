@@ -1471,8 +1471,10 @@ sislice_status sislice_solve(sislice_handle* h, int64_t n, const double* A, int6
     SL_CHECK_ARG(n_e >= 1 && n_e < n, "n_e must be in [1, n)");
     SL_CHECK_ARG(A && B && lda >= n && ldb >= n && omega_top, "bad matrix argument");
     SL_CHECK_ARG(evals && evecs && resid && ldx >= n, "bad output argument");
-    return solve_impl(h, n, A, lda, B, ldb, n_e, n_s, sigmas, omega_top, o, evals, evecs, ldx, resid,
-                      report, nullptr, nullptr);
+    const sislice_status st = solve_impl(h, n, A, lda, B, ldb, n_e, n_s, sigmas, omega_top, o,
+                                         evals, evecs, ldx, resid, report, nullptr, nullptr);
+    check_waits(h);
+    return st;
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());
     return e.status;

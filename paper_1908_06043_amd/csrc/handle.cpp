@@ -78,6 +78,29 @@ unsigned* sync_words(sislice_handle* h, size_t words) {
   return h->sync;
 }
 
+unsigned* wait_flag(sislice_handle* h) {
+  if (!h->wait_word) {
+    if (hipMalloc(&h->wait_word, 256) != hipSuccess) {
+      h->wait_word = nullptr;
+      throw Error(SISLICE_ERR_ALLOC, "wait-flag allocation failed");
+    }
+    SL_HIP(hipMemsetAsync(h->wait_word, 0, 256, h->stream));
+  }
+  return h->wait_word;
+}
+
+void check_waits(sislice_handle* h) {
+  if (!h || !h->wait_word) return;
+  auto* hv = static_cast<unsigned*>(host_stage(h, sizeof(unsigned)));
+  SL_HIP(hipMemcpyAsync(hv, h->wait_word, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));
+  if (*hv == 0) return;
+  SL_HIP(hipMemsetAsync(h->wait_word, 0, sizeof(unsigned), h->stream));
+  SL_HIP(hipStreamSynchronize(h->stream));
+  throw Error(SISLICE_ERR_HIP, "a triangular-solve hand-off wait exceeded its bound of " +
+                                   std::to_string(h->wait_limit) + " polls");
+}
+
 int prof_begin(sislice_handle* h, int cat) {
   if (!h || !h->prof) return -1;
   if (h->evnext + 2 > h->evpool.size()) {
@@ -277,6 +300,7 @@ sislice_status sislice_destroy(sislice_handle* h) {
     if (b.ptr) hipFree(b.ptr);
   if (h->host_stage) hipHostFree(h->host_stage);
   if (h->sync) hipFree(h->sync);
+  if (h->wait_word) hipFree(h->wait_word);
   if (h->ring_host) hipHostFree(h->ring_host);
   for (auto e : h->evpool) hipEventDestroy(e);
   for (auto& e : h->ev)
@@ -289,6 +313,16 @@ sislice_status sislice_set_stream(sislice_handle* h, void* stream) {
   SL_API_BEGIN
   check_handle(h);
   h->stream = static_cast<hipStream_t>(stream);
+  return SISLICE_OK;
+  SL_API_END
+}
+
+sislice_status sislice_set_wait_limit(sislice_handle* h, int64_t polls) {
+  SL_API_BEGIN
+  check_handle(h);
+  SL_CHECK_ARG(polls >= 0 && polls <= 0xFFFFFFFFll, "wait limit out of range");
+  h->wait_limit = (unsigned)polls;
+  for (auto* w : h->workers) w->wait_limit = (unsigned)polls;
   return SISLICE_OK;
   SL_API_END
 }
@@ -317,6 +351,7 @@ sislice_status sislice_ldlt_factor_multi(sislice_handle* h, int64_t n, const dou
   SL_HIP(hipMemcpyAsync(hi, fp.d_inertia, sizeof(int64_t) * 3 * n_shifts, hipMemcpyDeviceToHost,
                         h->stream));
   SL_HIP(hipStreamSynchronize(h->stream));
+  check_waits(h);
   bool singular = false;
   for (int64_t s = 0; s < 3 * n_shifts; ++s) inertia[s] = hi[s];
   for (int64_t s = 0; s < n_shifts; ++s) singular |= inertia[3 * s + 1] > 0;

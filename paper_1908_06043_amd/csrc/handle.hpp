@@ -20,6 +20,10 @@ struct sislice_handle {
   unsigned* sync = nullptr;  // epoch flags and ticket counters of the persistent solves
   size_t sync_cap = 0;       // in unsigned words
   unsigned epoch = 0;
+  // bounded device waits: polls before a waiter gives up, and the device word it
+  // raises then (allocated on first use, zero while no wait has expired)
+  unsigned wait_limit = 1u << 21;
+  unsigned* wait_word = nullptr;
   void* ring_host = nullptr;  // pinned ring for per-step pointer tables
   size_t ring_cap = 0;
   // staged-but-not-uploaded tables: flushed (one copy) before the next launch
@@ -108,6 +112,12 @@ void check_handle(sislice_handle* h);
 // Zero-initialised flag/counter words for persistent launches; grows (and
 // re-zeroes) on demand.  Returns the base pointer.
 unsigned* sync_words(sislice_handle* h, size_t words);
+// The wait-error word of the handle's bounded device waits (allocated and zeroed
+// on first use).
+unsigned* wait_flag(sislice_handle* h);
+// After a stream synchronisation: throws SISLICE_ERR_HIP (and clears the word)
+// when a device wait of an earlier launch expired.
+void check_waits(sislice_handle* h);
 inline unsigned next_epoch(sislice_handle* h) { return ++h->epoch; }
 
 // Kernel-class timing: prof_begin records an event before a launch on the

@@ -331,6 +331,7 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
     ++s->step;
     r.t_total_ms = ms_since(t0);
     if (rep) *rep = r;
+    check_waits(h);
     return st;
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());

@@ -166,6 +166,21 @@ __device__ __forceinline__ bool is_sentinel(double v) {
   return (unsigned long long)__double_as_longlong(v) == kSentinelBits;
 }
 
+// Every wait is bounded: after `limit` unsuccessful polls a waiter stops, raises
+// the handle's wait-error word (the host turns it into an error status after the
+// call) and goes on with what it read, so the launch always drains.  Correct
+// hand-offs finish in microseconds; the default bound is about a second.
+struct WaitBound {
+  unsigned* err;
+  unsigned limit;
+};
+
+__device__ __forceinline__ bool wait_expired(const WaitBound& wb, unsigned& polls) {
+  if (polls++ < wb.limit) return false;
+  __hip_atomic_store(wb.err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return true;
+}
+
 // sX[c][rr] = block rows rr < rows of column c of B (ld ldb), once none is the
 // sentinel; rows past `rows` read as zero.  A block that is already complete (the
 // common case for a workgroup that started after its predecessors) is read in one
@@ -174,7 +189,7 @@ __device__ __forceinline__ bool is_sentinel(double v) {
 // coherence point on every poll; the block is then loaded and checked in full
 // (other lanes' stores may still be on their way).
 __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, long ldb, int nrhs,
-                                           int rows) {
+                                           int rows, const WaitBound& wb) {
   {
     int ok = 1;
     for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
@@ -188,11 +203,22 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
     }
     if (__syncthreads_and(ok)) return;
   }
+  __shared__ int expired;
   if (threadIdx.x == 0) {
     const double* last = B + (rows - 1) + (long)(nrhs - 1) * ldb;
-    while (is_sentinel(ld_shared_blk(last))) __builtin_amdgcn_s_sleep(1);
+    unsigned polls = 0;
+    int ex = 0;
+    while (is_sentinel(ld_shared_blk(last))) {
+      if (wait_expired(wb, polls)) {
+        ex = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    expired = ex;
   }
   __syncthreads();
+  unsigned polls = 0;
   for (;;) {
     int ok = 1;
     for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
@@ -204,7 +230,9 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
       }
       sX[c][rr] = v;
     }
-    if (__syncthreads_and(ok)) return;
+    // a wait that already expired, or one that expires here, goes on with what it read
+    // (the decision is uniform: `expired` and the poll count are the same in every lane)
+    if (__syncthreads_and(ok) || expired || wait_expired(wb, polls)) return;
     __builtin_amdgcn_s_sleep(2);
   }
 }
@@ -214,14 +242,15 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
 // own elements and the block is complete one round trip after it lands, instead
 // of one round trip for the probe element and another for the block.
 __device__ __forceinline__ void poll_block_spin(double (*sX)[SB], const double* B, long ldb,
-                                                int nrhs, int rows) {
+                                                int nrhs, int rows, const WaitBound& wb) {
   for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
     const int rr = e & 63, c = e >> 6;
     double v = 0.0;
     if (rr < rows) {
       const double* p = B + rr + (long)c * ldb;
       v = ld_shared_blk(p);
-      while (is_sentinel(v)) {
+      unsigned polls = 0;
+      while (is_sentinel(v) && !wait_expired(wb, polls)) {
         __builtin_amdgcn_s_sleep(1);
         v = ld_shared_blk(p);
       }
@@ -272,6 +301,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
+  const WaitBound wb{a.wait_err, a.wait_limit};
   const int b = (int)ticket(a.ctr + s, nblk);
   const double* LD = a.LD[s];
   const int* perm = a.perm[s];
@@ -313,7 +343,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       sM[e & 63][e >> 6] = lnext[q];
     }
     if (cb + 3 < b) load_L(cb + 1);
-    poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB);
+    poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB, wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -358,7 +388,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = lnext[q];
     }
-    poll_block_spin(sZ, Z + (b - 2) * SB, a.ldz, nrhs, SB);
+    poll_block_spin(sZ, Z + (b - 2) * SB, a.ldz, nrhs, SB, wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -377,7 +407,7 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = mf[q];
     }
-    poll_block_spin(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB);
+    poll_block_spin(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB, wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -409,6 +439,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
+  const WaitBound wb{a.wait_err, a.wait_limit};
   const int t = (int)ticket(a.ctr + s, nblk);
   const int b = nblk - 1 - t;
   const double* LD = a.LD[s];
@@ -487,7 +518,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       sM[e & 63][e >> 6] = lnext[q];
     }
     if (cb - 1 > b + 2) load_L(cb - 1);
-    poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB));
+    poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB), wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -532,7 +563,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = lnext[q];
     }
-    poll_block_spin(sV, V + (b + 2) * SB, a.ldz, nrhs, min(SB, n - (b + 2) * SB));
+    poll_block_spin(sV, V + (b + 2) * SB, a.ldz, nrhs, min(SB, n - (b + 2) * SB), wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -551,7 +582,7 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       const int e = tid + 256 * q;
       sM[e & 63][e >> 6] = mb[q];
     }
-    poll_block_spin(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB));
+    poll_block_spin(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB), wb);
 #pragma unroll
     for (int m = 0; m < NR / 4; ++m) {
       const int c = q0 + 4 * m;
@@ -610,6 +641,8 @@ void solve_launch(SolveArgs a, hipStream_t st, int mode) {
   // 8 XCDs x ceil(nshift / 8) shift slots x nblk blocks (see solve_shift_of)
   const unsigned grid = (unsigned)(8 * ceil_div(a.nshift, 8) * nblk);
   sislice_handle* ph = current_handle();
+  a.wait_err = wait_flag(ph);
+  a.wait_limit = ph->wait_limit;
   const int tk = prof_begin(ph, kProfSolve);
   // sentinels in the result buffers of the sweeps of this launch
   const long tot = (long)a.n * a.nrhs;

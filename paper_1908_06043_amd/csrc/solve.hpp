@@ -25,6 +25,8 @@ struct SolveArgs {
   long ldz = 0;
   unsigned* ctr = nullptr;              // nshift ticket counters, zero-initialised once
   int applyD = 1;                       // backward sweep applies D^{-1} first (0: identity)
+  unsigned* wait_err = nullptr;         // raised when a hand-off wait exceeds wait_limit polls
+  unsigned wait_limit = 0;              // (both set by solve_launch from the handle)
 };
 
 // mode 0: X = P^T L^{-T} D^{-1} L^{-1} P Y (both sweeps, Z/V scratch)

@@ -49,3 +49,23 @@ def test_solve_pencil_shift_and_repeat(gpu_lib):
     assert np.array_equal(X1, X2)                        # deterministic, epoch flags reused
     r = np.linalg.norm(C @ X1 - Y) / (np.linalg.norm(C) * np.linalg.norm(X1))
     assert r < 1e-13
+
+
+def test_bounded_waits_report_an_error_and_recover(gpu_lib):
+    """The hand-off waits of the sweeps are bounded.  With the bound forced to zero
+    polls from the host, every wait that does not find its block at the first look
+    gives up at once (the kernels still run to completion): the solve reports
+    SISLICE_ERR_HIP.  With the default bound restored, the next solve is correct."""
+    P = inputs.pencil_scf(1000, 100, seed=1)
+    A, B = dev(P.A), dev(P.B)
+    print("bounded waits: solve with a zero wait bound", flush=True)
+    gpu_lib.set_wait_limit(0)
+    try:
+        out = gpu_lib.solve(A, B, 100, 8, check=False)
+    finally:
+        gpu_lib.set_wait_limit(1 << 21)
+    assert out["status"] == -2
+    print("bounded waits: solve with the default bound", flush=True)
+    out = gpu_lib.solve(A, B, 100, 8)
+    ev = out["evals"].cpu().numpy()
+    assert out["status"] == 0 and np.max(np.abs(ev - P.lam[:100])) <= 1e-10 * np.max(np.abs(P.lam))
