@@ -91,10 +91,11 @@ unsigned* wait_flag(sislice_handle* h) {
 
 void check_waits(sislice_handle* h) {
   if (!h || !h->wait_word) return;
-  auto* hv = static_cast<unsigned*>(host_stage(h, sizeof(unsigned)));
-  SL_HIP(hipMemcpyAsync(hv, h->wait_word, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+  // a local word, not the pinned staging area: callers may still hold results there
+  unsigned hv = 0;
+  SL_HIP(hipMemcpyAsync(&hv, h->wait_word, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
   SL_HIP(hipStreamSynchronize(h->stream));
-  if (*hv == 0) return;
+  if (hv == 0) return;
   SL_HIP(hipMemsetAsync(h->wait_word, 0, sizeof(unsigned), h->stream));
   SL_HIP(hipStreamSynchronize(h->stream));
   throw Error(SISLICE_ERR_HIP, "a triangular-solve hand-off wait exceeded its bound of " +
@@ -351,9 +352,9 @@ sislice_status sislice_ldlt_factor_multi(sislice_handle* h, int64_t n, const dou
   SL_HIP(hipMemcpyAsync(hi, fp.d_inertia, sizeof(int64_t) * 3 * n_shifts, hipMemcpyDeviceToHost,
                         h->stream));
   SL_HIP(hipStreamSynchronize(h->stream));
-  check_waits(h);
   bool singular = false;
   for (int64_t s = 0; s < 3 * n_shifts; ++s) inertia[s] = hi[s];
+  check_waits(h);
   for (int64_t s = 0; s < n_shifts; ++s) singular |= inertia[3 * s + 1] > 0;
   return singular ? SISLICE_SINGULAR_SHIFT : SISLICE_OK;
   SL_API_END
