@@ -163,6 +163,20 @@ sislice_status sislice_ldlt_factor_multi(sislice_handle *h, int64_t n, const dou
 sislice_status sislice_ldlt_solve(sislice_handle *h, int64_t n, const double *LD, int64_t ldld,
                                   const int32_t *ipiv, int64_t nrhs, double *X, int64_t ldx);
 
+/* sislice_ldlt_solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, kernels and results, but no call allocates, frees or
+ * synchronises.  Its workspace is one fixed device array of 13 MiB per GPU (held
+ * from the first handle created on that GPU until the process ends), so
+ * n <= 4096 (SISLICE_ERR_ARG beyond) and 1 <= nrhs <= 64.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams or
+ * handles) race.  Asynchronous; an expired hand-off wait (see
+ * sislice_set_wait_limit) is reported by the next synchronising call on the
+ * handle. */
+sislice_status sislice_ldlt_solve_noalloc(sislice_handle *h, int64_t n, const double *LD,
+                                          int64_t ldld, const int32_t *ipiv, int64_t nrhs,
+                                          double *X, int64_t ldx);
+
 /* Shift placement from a stochastic Chebyshev DOS estimate (Sec. 3.1 with the
  * kernel polynomial method in place of the Lanczos DOS): spectral bounds by a
  * Lanczos run on L_B^{-1} A L_B^{-T}, opts->kpm_moments Jackson-damped moments

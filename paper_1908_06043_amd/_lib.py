@@ -78,6 +78,8 @@ _SIGS = {
                                             c_void_pp, C.c_int64, c_void_pp, c_int64_p]),
     "sislice_ldlt_solve": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                      C.c_int64, C.c_void_p, C.c_int64]),
+    "sislice_ldlt_solve_noalloc": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
+                                             C.c_void_p, C.c_int64, C.c_void_p, C.c_int64]),
     "sislice_plan_shifts_kpm": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                           C.c_void_p, C.c_int64, C.c_int64, C.c_int64,
                                           C.POINTER(Opts), c_double_p, c_double_p, c_double_p,

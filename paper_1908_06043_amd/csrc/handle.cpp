@@ -282,7 +282,17 @@ sislice_status sislice_create(sislice_handle** out, int device, void* stream) {
   auto* h = new sislice_handle();
   h->device = device;
   h->stream = static_cast<hipStream_t>(stream);
-  for (auto& e : h->ev) SL_HIP(hipEventCreate(&e));
+  try {
+    for (auto& e : h->ev) SL_HIP(hipEventCreate(&e));
+    // set-up of the allocation-free entry point: the wait word exists from the
+    // start and the scratch array's address on this device is known
+    wait_flag(h);
+    h->scratch = noalloc_scratch_setup(device);
+    SL_HIP(hipStreamSynchronize(h->stream));
+  } catch (...) {
+    sislice_destroy(h);
+    throw;
+  }
   *out = h;
   return SISLICE_OK;
   SL_API_END

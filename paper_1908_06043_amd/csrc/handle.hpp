@@ -24,6 +24,8 @@ struct sislice_handle {
   // raises then (allocated on first use, zero while no wait has expired)
   unsigned wait_limit = 1u << 21;
   unsigned* wait_word = nullptr;
+  // device address of the allocation-free solve's scratch array on this device
+  void* scratch = nullptr;
   void* ring_host = nullptr;  // pinned ring for per-step pointer tables
   size_t ring_cap = 0;
   // staged-but-not-uploaded tables: flushed (one copy) before the next launch
@@ -115,6 +117,9 @@ unsigned* sync_words(sislice_handle* h, size_t words);
 // The wait-error word of the handle's bounded device waits (allocated and zeroed
 // on first use).
 unsigned* wait_flag(sislice_handle* h);
+// Device address of the allocation-free solve's scratch array on `device`
+// (looked up once per device; the device becomes current).
+void* noalloc_scratch_setup(int device);
 // After a stream synchronisation: throws SISLICE_ERR_HIP (and clears the word)
 // when a device wait of an earlier launch expired.
 void check_waits(sislice_handle* h);
