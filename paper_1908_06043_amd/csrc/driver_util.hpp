@@ -24,9 +24,21 @@ inline double ms_since(Clock::time_point t0) {
 // kernel (stream order then delivers them first).  The host bytes stay untouched
 // until the stream has passed that copy: the ring is rewound only after a
 // stream synchronisation.
+// Rings nest (a driver that calls the planner): both use the handle's one ring
+// memory, so a nested ring first uploads the outer one's staged tables, waits
+// for the stream and rewinds the outer ring (whose earlier tables have all been
+// consumed then); when the nested ring ends it uploads its own, waits again and
+// hands the launch hook back to the outer ring.
 class Ring {
  public:
   explicit Ring(sislice_handle* h, size_t cap = 16u << 20) : h_(h), cap_(cap) {
+    if (h->flush_fn == &Ring::flush_thunk && h->flush_ctx) {
+      outer_ = static_cast<Ring*>(h->flush_ctx);
+      outer_->flush();
+      SL_HIP(hipStreamSynchronize(h->stream));
+      outer_->off_ = outer_->pend_ = 0;
+      outer_->seen_.clear();
+    }
     if (h->ring_cap < cap) {
       if (h->ring_host) {
         SL_HIP(hipStreamSynchronize(h->stream));
@@ -46,10 +58,11 @@ class Ring {
     if (h_->flush_ctx == this) {
       try {
         flush();
+        if (outer_) (void)hipStreamSynchronize(h_->stream);
       } catch (...) {
       }
-      h_->flush_fn = nullptr;
-      h_->flush_ctx = nullptr;
+      h_->flush_fn = outer_ ? &Ring::flush_thunk : nullptr;
+      h_->flush_ctx = outer_;
     }
   }
   Ring(const Ring&) = delete;
@@ -120,6 +133,7 @@ class Ring {
  private:
   static void flush_thunk(void* self) { static_cast<Ring*>(self)->flush(); }
   sislice_handle* h_;
+  Ring* outer_ = nullptr;
   size_t cap_;
   char* host_;
   char* dev_;
@@ -132,6 +146,27 @@ struct Ctx {
   sislice_handle* h;
   hipStream_t st;
   Ring* ring;
+};
+
+// A device allocation owned by one call, for rare paths that need memory beyond
+// the handle's workspaces (hipFree waits for the device before releasing it).
+struct DevBuf {
+  void* p = nullptr;
+  void alloc(size_t bytes) {
+    release();
+    if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      p = nullptr;
+      throw Error(SISLICE_ERR_ALLOC, "device allocation failed");
+    }
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+  }
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
 };
 
 // Batched GEMM helper: per-batch sizes, pointer tables through the ring,
@@ -200,9 +235,10 @@ DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, lo
 // entry points).  plan_impl runs the KPM planner, or with dos_mode 0 / 1 the
 // paper's Lanczos DOS planner (dos_nv runs of dos_k steps; equal-count roots or
 // DOSCluster).  solve_impl's optional `start` (device n x 8 n_s, ld n) gives
-// each probe's Lanczos start block (warm start) instead of a Gaussian one, and
-// `probe_of` (host int32[n_e]) receives the probe that validated each returned
-// eigenpair.
+// each probe's Lanczos start block (warm start) instead of a Gaussian one (with
+// the subspace-iteration driver, opts.driver == 1: n x start_cols per probe, the
+// leading columns of its start basis), and `probe_of` (host int32[n_e]) receives
+// the probe that validated each returned eigenpair.
 sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_t lda,
                          const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                          const sislice_opts& o, double* sig, double* top, double* mom_out,
@@ -212,7 +248,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
                           double* evals, double* evecs, int64_t ldx, double* resid_out,
                           sislice_report* rep, const double* start = nullptr,
-                          int32_t* probe_of = nullptr);
+                          int32_t* probe_of = nullptr, int start_cols = 8);
 void check_opts(const sislice_opts& o);
 
 }  // namespace sislice
