@@ -59,6 +59,16 @@ typedef struct {
   double tol;            /* residual ||Ax - lambda Bx|| / (||A||_2 ||x||) target (1e-10) */
   double top_margin;     /* top boundary at the CDOS root of n_e + top_margin*n_e/n_s (2) */
   uint64_t seed;         /* SplitMix64 seed of every random draw (0)                     */
+  int32_t driver;        /* per-probe iteration: 0 block shift-invert Lanczos in the B
+                            inner product (block size `block`, thick restart); 1 the
+                            paper's shift-invert subspace iteration (Algorithm 2) with
+                            k = max(2 need, 16) columns (a multiple of 8, <= 112) for
+                            the probe with the largest need, rounds of M iterations,
+                            each round restarted from its Ritz vectors (0)            */
+  int32_t subspace_iters;/* M of Algorithm 2: applications per round (4)               */
+  int32_t max_recovery;  /* rounds of probe insertion into slices that miss
+                            eigenvalues (Sec. 3.3) before SISLICE_MISSING_EIGS (2)    */
+  int32_t reserved;      /* 0                                                          */
 } sislice_opts;
 
 /* Per-solve report, host memory owned by the caller.  Array members are optional
@@ -93,8 +103,13 @@ typedef struct {
    * forward/backward pair (the packed L read once per direction). */
   double bytes_solve;
   /* Identifies the factorizations of this solve, which the handle keeps until
-   * its next sislice_solve or sislice_adjoint (pass to sislice_adjoint). */
+   * its next sislice_solve, sislice_sisubit or sislice_adjoint (pass to
+   * sislice_adjoint); 0 when probes were inserted (the adjoint then refactors). */
   uint64_t factor_id;
+  /* Missing eigenvalues (Sec. 3.3): probes inserted into slices that held more
+   * eigenvalues than validated candidates, and the rounds of insertion. */
+  int32_t probes_inserted;
+  int32_t recovery_rounds;
 } sislice_report;
 
 /* Report of sislice_adjoint, host memory owned by the caller. */
@@ -230,6 +245,22 @@ sislice_status sislice_solve(sislice_handle *h, int64_t n, const double *A, int6
                              const double *sigmas, double *omega_top, const sislice_opts *opts,
                              double *evals, double *evecs, int64_t ldx, double *resid,
                              sislice_report *report);
+
+/* The paper's shift-invert subspace iteration, SISubIt(A, B, V0, sigma, M)
+ * (Algorithm 2): CholeskyQR of V0 in the B inner product, the LDL^T of
+ * A - sigma B, M times V <- L^{-T} D^{-1} L^{-1} B V followed by CholeskyQR,
+ * then Rayleigh-Ritz with A and B (Sec. 2.1).  CholeskyQR is applied twice
+ * per step (the same span; the second pass restores B-orthonormality).
+ *   V0      device n x k (ldv >= n), 1 <= k <= min(112, n); M in [1, 64].
+ *   evals   device double[k] out, ascending; X device n x k (ldx >= n) out,
+ *           B-orthonormal Ritz vectors; resid device double[k] out, the
+ *           normalised residuals ||A x - lambda B x|| / (||A||_2 ||x||).
+ * The factorization replaces the one that sislice_adjoint could reuse.  Returns
+ * SISLICE_SINGULAR_SHIFT when sigma is an eigenvalue.  Synchronises. */
+sislice_status sislice_sisubit(sislice_handle *h, int64_t n, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, double sigma, int64_t k,
+                               const double *V0, int64_t ldv, int32_t M, double *evals,
+                               double *X, int64_t ldx, double *resid);
 
 /* Reverse-mode derivative of the eigenpairs that sislice_solve returns (the
  * lowest n_e of the pencil of Sec. 1).  The paper does not differentiate them;
@@ -386,6 +417,8 @@ typedef struct {
   uint64_t factor_id;
   double t_solve_ms, t_total_ms;
   int32_t cycles_max;    /* largest number of Lanczos restart cycles of a probe        */
+  int32_t probes_inserted; /* probes inserted by the solve into slices that missed
+                              eigenvalues (Sec. 3.3)                                 */
 } sislice_scf_report;
 
 sislice_status sislice_scf_create(sislice_handle *h, int64_t n, int64_t n_e, int64_t n_s,

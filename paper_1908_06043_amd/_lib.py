@@ -22,7 +22,9 @@ class Opts(C.Structure):
     _fields_ = [("block", C.c_int32), ("max_basis", C.c_int32), ("max_cycles", C.c_int32),
                 ("kpm_moments", C.c_int32), ("kpm_vectors", C.c_int32),
                 ("bounds_steps", C.c_int32), ("nb", C.c_int32), ("profile", C.c_int32),
-                ("tol", C.c_double), ("top_margin", C.c_double), ("seed", C.c_uint64)]
+                ("tol", C.c_double), ("top_margin", C.c_double), ("seed", C.c_uint64),
+                ("driver", C.c_int32), ("subspace_iters", C.c_int32), ("max_recovery", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -34,7 +36,8 @@ class Report(C.Structure):
                 ("flops_factor", C.c_double), ("nu", c_int64_p), ("slice_case", c_int32_p),
                 ("slice_exact", c_int32_p), ("slice_cand", c_int32_p),
                 ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double),
-                ("bytes_solve", C.c_double), ("factor_id", C.c_uint64)]
+                ("bytes_solve", C.c_double), ("factor_id", C.c_uint64),
+                ("probes_inserted", C.c_int32), ("recovery_rounds", C.c_int32)]
 
 
 class AdjointReport(C.Structure):
@@ -49,7 +52,7 @@ class ScfReport(C.Structure):
                 ("deleted", C.c_int32), ("inserted", C.c_int32), ("status_solve", C.c_int32),
                 ("eta_prev", C.c_double), ("eta_new", C.c_double), ("block_steps", C.c_int64),
                 ("factor_id", C.c_uint64), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("cycles_max", C.c_int32)]
+                ("cycles_max", C.c_int32), ("probes_inserted", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -92,6 +95,9 @@ _SIGS = {
                                 C.c_int64, C.c_int64, C.c_int64, c_double_p, c_double_p,
                                 C.POINTER(Opts), C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p,
                                 C.POINTER(Report)]),
+    "sislice_sisubit": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
+                                  C.c_int64, C.c_double, C.c_int64, C.c_void_p, C.c_int64,
+                                  C.c_int32, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]),
     "sislice_adjoint": (C.c_int, [C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p,
                                   C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, c_double_p,

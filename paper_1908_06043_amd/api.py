@@ -137,6 +137,23 @@ def sym_eig(M):
     return (W[0], Vm[0]) if M.dim() == 2 else (W, Vm)
 
 
+def sisubit(A, B, sigma, V0, M):
+    """The paper's Algorithm 2 from the start basis V0 (n x k): M shift-invert
+    applications with CholeskyQR, then Rayleigh-Ritz.  Returns (evals, X, resid)."""
+    A = _mat(A, "A")
+    B = _mat(B, "B")
+    n, k = V0.shape
+    V0t = V0.t().contiguous()                      # column-major n x k
+    ev = torch.empty(k, dtype=torch.float64, device=A.device)
+    Xt = torch.empty((k, n), dtype=torch.float64, device=A.device)
+    rs = torch.empty(k, dtype=torch.float64, device=A.device)
+    st = _lib.load().sislice_sisubit(handle(A.device.index), n, A.data_ptr(), n, B.data_ptr(), n,
+                                     float(sigma), k, V0t.data_ptr(), n, int(M), ev.data_ptr(),
+                                     Xt.data_ptr(), n, rs.data_ptr())
+    _check(st, "sislice_sisubit")
+    return ev, Xt.t(), rs
+
+
 def plan_shifts_kpm(A, B, n_e, n_s, opts=None):
     A = _mat(A, "A")
     B = _mat(B, "B")

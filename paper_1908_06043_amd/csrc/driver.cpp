@@ -29,6 +29,7 @@
 #include "lanczos.hpp"
 #include "planner.hpp"
 #include "driver_util.hpp"
+#include "sisubit.hpp"
 #include "solve.hpp"
 
 namespace sislice {
@@ -103,6 +104,9 @@ void check_opts(const sislice_opts& o) {
   SL_CHECK_ARG(o.kpm_vectors >= 1 && o.kpm_vectors <= kSolveMaxRhs, "kpm_vectors in [1, 32]");
   SL_CHECK_ARG(o.bounds_steps >= 2 && o.bounds_steps <= 100, "bounds_steps in [2, 100]");
   SL_CHECK_ARG(o.tol > 0 && o.tol < 1, "tol in (0, 1)");
+  SL_CHECK_ARG(o.driver == 0 || o.driver == 1, "driver must be 0 (Lanczos) or 1 (subspace iteration)");
+  SL_CHECK_ARG(o.subspace_iters >= 1 && o.subspace_iters <= 64, "subspace_iters in [1, 64]");
+  SL_CHECK_ARG(o.max_recovery >= 0 && o.max_recovery <= 8, "max_recovery in [0, 8]");
 }
 
 // ---------------------------------------------------------------- planner
@@ -546,7 +550,8 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
                           const double* B, int64_t ldb, int64_t n_e, int64_t n_s,
                           const double* sigmas_in, double* omega_top_io, const sislice_opts& o,
                           double* evals, double* evecs, int64_t ldx, double* resid_out,
-                          sislice_report* rep, const double* start, int32_t* probe_of) {
+                          sislice_report* rep, const double* start, int32_t* probe_of,
+                          int start_cols) {
   const auto t_start = Clock::now();
   const int n = (int)n64;
   const int P = (int)n_s;
@@ -650,638 +655,935 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   const double bnorm = sym_norm2(c, n, Bf, nX, nX + (size_t)n * 8, nsmall, nsmall + 64, nsmall + 128,
                                  nsmall + 192, nsmall + 256, nflag, active1, o.seed ^ 0x5A5Aull);
   if (rep) rep->anorm = anorm;
-  // ---- 2. block Lanczos per probe
-  const auto t_l0 = Clock::now();
-  std::vector<ProbeHost> pr(P);
-  int64_t max_need = 0;
-  for (int j = 0; j < P; ++j) {
-    pr[j].sigma = sig[j];
-    pr[j].lo = j > 0 ? sig[j - 1] : -std::numeric_limits<double>::infinity();
-    pr[j].hi = j + 1 < P ? sig[j + 1] : top;
-    const int64_t nlo = j > 0 ? nu[j - 1] : 0;
-    const int64_t nhi = j + 1 < P ? nu[j + 1] : nu_top;
-    pr[j].need = nhi - nlo;
-    max_need = std::max(max_need, pr[j].need);
-  }
-  // locked capacity: the values a probe needs plus room for deflated pairs
-  const int LC = (int)std::min<int64_t>(n, 2 * max_need + 16);
-  int MB = o.max_basis;
-  while (MB > 16 && MB + 2 * b + LC > n) MB -= b;
-  const int QC = MB + 2 * b;
-  // thick restart: keep the Ritz vectors nearest the shift and add four blocks per
-  // cycle (measured against six and two: fewer Lanczos steps without more cycles)
-  const int kkeep_max = std::max(b, MB - 4 * b);
-  Sizer zl;
-  zl.take<double>((size_t)n * b * P);  // W_all
-  zl.take<double>((size_t)n * b * P);  // Z_all
-  for (int j = 0; j < P; ++j) {
-    zl.take<double>((size_t)n * QC);  // Q
-    zl.take<double>((size_t)n * QC);  // UQ
-    zl.take<double>((size_t)n * LC);  // L
-    zl.take<double>((size_t)n * LC);  // UL
-    zl.take<double>((size_t)n * MB);  // Xt
-    zl.take<double>((size_t)n * MB);  // Ut
-    zl.take<double>((size_t)n * b);   // solve scratch Z
-    zl.take<double>((size_t)n * b);   // solve scratch V
-    zl.take<double>((size_t)QC * QC);  // T
-    zl.take<double>((size_t)QC * QC);  // S (eigvecs)
-    zl.take<double>((size_t)QC * QC);  // S lock sel
-    zl.take<double>((size_t)QC * QC);  // S keep sel
-    zl.take<double>(QC);               // theta
-    zl.take<double>(QC);               // est
-    zl.take<double>((size_t)QC * b);   // CQ
-    zl.take<double>((size_t)LC * b);   // CL
-    zl.take<double>(4 * b * b);        // G, R1, R2, Rt
-    zl.take<int>(2 * QC);              // idx lock / keep
-  }
-  zl.take<int>(P);  // flags
-  const int ts_mmax = std::max(LC, QC);
-  zl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));  // tall-skinny partials
-  Carver cl(ws_get(h, kBufLanczos, zl.off));
-  double* Wall = cl.take<double>((size_t)n * b * P);
-  double* Zall = cl.take<double>((size_t)n * b * P);
-  struct ProbeDev {
-    double *Q, *UQ, *L, *UL, *Xt, *Ut, *Zs, *Vs, *T, *S, *SL, *SK, *th, *est, *CQ, *CL, *G, *R1, *R2, *Rt;
-    int *il, *ik;
-  };
-  std::vector<ProbeDev> pd(P);
-  for (int j = 0; j < P; ++j) {
-    auto& d = pd[j];
-    d.Q = cl.take<double>((size_t)n * QC);
-    d.UQ = cl.take<double>((size_t)n * QC);
-    d.L = cl.take<double>((size_t)n * LC);
-    d.UL = cl.take<double>((size_t)n * LC);
-    d.Xt = cl.take<double>((size_t)n * MB);
-    d.Ut = cl.take<double>((size_t)n * MB);
-    d.Zs = cl.take<double>((size_t)n * b);
-    d.Vs = cl.take<double>((size_t)n * b);
-    d.T = cl.take<double>((size_t)QC * QC);
-    d.S = cl.take<double>((size_t)QC * QC);
-    d.SL = cl.take<double>((size_t)QC * QC);
-    d.SK = cl.take<double>((size_t)QC * QC);
-    d.th = cl.take<double>(QC);
-    d.est = cl.take<double>(QC);
-    d.CQ = cl.take<double>((size_t)QC * b);
-    d.CL = cl.take<double>((size_t)LC * b);
-    double* g4 = cl.take<double>(4 * b * b);
-    d.G = g4;
-    d.R1 = g4 + b * b;
-    d.R2 = g4 + 2 * b * b;
-    d.Rt = g4 + 3 * b * b;
-    int* ii = cl.take<int>(2 * QC);
-    d.il = ii;
-    d.ik = ii + QC;
-  }
-  int* dflags = cl.take<int>(P);
-  double* tspart = cl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));
-  for (int j = 0; j < P; ++j) SL_HIP(hipMemsetAsync(pd[j].T, 0, sizeof(double) * QC * QC, st));
-  unsigned* sync = sync_words(h, (size_t)P + 64);  // one ticket counter per probe
-  auto Wj = [&](int j) { return Wall + (size_t)j * n * b; };
-  auto Zj = [&](int j) { return Zall + (size_t)j * n * b; };
-  // start blocks: Gaussian from the shared stream, or the caller's (warm start),
-  // B-orthonormalised (CholeskyQR2)
-  if (start) {
-    SL_HIP(hipMemcpyAsync(Wall, start, sizeof(double) * (size_t)n * b * P, hipMemcpyDeviceToDevice, st));
-  } else {
-    std::vector<unsigned long long> seeds(P);
-    std::vector<double*> wp(P);
-    for (int j = 0; j < P; ++j) {
-      seeds[j] = rng_derive(o.seed, kTagLanczos ^ ((uint64_t)j << 32));
-      wp[j] = Wj(j);
-    }
-    gauss_launch(n, b, P, ring.vec(seeds), ring.ptrs(wp), n, st);
-  }
-  std::vector<int> all(P);
-  std::iota(all.begin(), all.end(), 0);
-  auto act_vec = [&](const auto& js, auto f) {
-    using T = decltype(f(js[0]));
-    std::vector<T> v;
-    v.reserve(js.size());
-    for (const auto& j : js) v.push_back(f(j));
-    return v;
-  };
-  auto cholqr2 = [&](const std::vector<int>& js, const std::vector<double*>& Vin,
-                     const std::vector<double*>& Uin, long ldin, const std::vector<double*>& Vout,
-                     const std::vector<double*>& Uout, bool coupling) {
-    const int na = (int)js.size();
-    std::vector<int> ones(na, 1), bs(na, b), ns(na, n);
-    std::vector<const double*> cV(Vin.begin(), Vin.end()), cU(Uin.begin(), Uin.end());
-    auto gram = [&](const std::vector<const double*>& Vv, const std::vector<const double*>& Uv, long ld) {
-      TsArgs ta;
-      ta.n = n;
-      ta.m = ring.vec(bs);
-      ta.V = ring.cptrs(Vv);
-      ta.ldv = ld;
-      ta.X = ring.cptrs(Uv);
-      ta.ldx = ld;
-      ta.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].G; }));
-      ta.ldc = b;
-      ta.partial = tspart;
-      tsmt_launch(ta, na, b, st);
-    };
-    gram(cV, cU, ldin);
-    CholQrArgs q;
-    q.n = n;
-    q.active = ring.vec(ones);
-    q.G = ring.cptrs(act_vec(js, [&](int j) { return pd[j].G; }));
-    q.Vin = ring.cptrs(Vin);
-    q.Uin = ring.cptrs(Uin);
-    q.ldin = ldin;
-    q.Vout = ring.ptrs(Vout);
-    q.Uout = ring.ptrs(Uout);
-    q.ldout = n;
-    q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
-    q.flag = dflags;  // indexed by position; only read when all probes are active
-    cholqr_launch(q, na, st);
-    std::vector<const double*> cVo(Vout.begin(), Vout.end()), cUo(Uout.begin(), Uout.end());
-    gram(cVo, cUo, n);
-    q.Vin = ring.cptrs(Vout);
-    q.Uin = ring.cptrs(Uout);
-    q.ldin = n;
-    q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
-    cholqr_launch(q, na, st);
-    if (coupling) {
-      CouplingArgs ca;
-      ca.active = ring.vec(ones);
-      ca.R1 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
-      ca.R2 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
-      ca.Rt = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Rt; }));
-      ca.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
-      ca.ldt = QC;
-      ca.row0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq; }));
-      coupling_launch(ca, na, st);
-    }
-  };
-  // Z = B W, then B-orthonormalise into Q[:, 0:8]
-  gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
-  cholqr2(all, act_vec(all, Wj), act_vec(all, Zj), n, act_vec(all, [&](int j) { return pd[j].Q; }),
-          act_vec(all, [&](int j) { return pd[j].UQ; }), false);
-  for (int j = 0; j < P; ++j) pr[j].mq = b;
-  // slice bookkeeping
-  std::vector<int64_t> n_exact(P + 1);
-  for (int s = 0; s <= P; ++s) {
-    const int64_t lo = s == 0 ? 0 : nu[s - 1];
-    const int64_t hi = s == P ? nu_top : nu[s];
-    n_exact[s] = hi - lo;
-  }
-  auto slice_done = [&](int s) {
-    int64_t cnt = 0;
-    if (s == 0) {
-      for (double v : pr[0].lock_lam) cnt += v < sig[0];
-    } else if (s == P) {
-      for (double v : pr[P - 1].lock_lam) cnt += v >= sig[P - 1] && v < top;
-    } else {
-      const double lo = sig[s - 1], hi = sig[s], tau = 0.5 * (lo + hi);
-      for (double v : pr[s - 1].lock_lam) cnt += v >= lo && v <= tau;
-      for (double v : pr[s].lock_lam) cnt += v > tau && v < hi;
-    }
-    return cnt >= n_exact[s];
-  };
-  int block_steps = 0, cycles_max = 0;
-  double bytes_solve = 0.0;
-  const double lock_tol = o.tol / 100.0;
-  for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
-    std::vector<int> act;
-    for (int j = 0; j < P; ++j)
-      if (pr[j].active) act.push_back(j);
-    if (act.empty()) break;
-    // ---- steps until every active probe's basis is full
-    while (true) {
-      std::vector<int> js;
-      for (int j : act)
-        if (pr[j].mq <= MB) js.push_back(j);  // the projected order mq - b stays <= MB
-      if (js.empty()) break;
-      const int na = (int)js.size();
-      block_steps += na;
-      for (int j : js) pr[j].steps++;
-      // a. W_j = (A - sigma_j B)^{-1} U_j[:, last block]
-      SolveArgs sa;
-      sa.n = n;
-      sa.nshift = na;
-      sa.nrhs = b;
-      sa.epoch = next_epoch(h);
-      sa.LD = ring.cptrs(act_vec(js, [&](int j) { return LD[j]; }));
-      sa.ldld = n;
-      sa.perm = ring.cptrs(act_vec(js, [&](int j) { return perm[j]; }));
-      sa.blk = ring.cptrs(act_vec(js, [&](int j) { return blk[j]; }));
-      sa.Linv = ring.cptrs(act_vec(js, [&](int j) { return Linv[j]; }));
-      sa.Y = ring.cptrs(act_vec(js, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
-      sa.ldy = n;
-      sa.X = ring.ptrs(act_vec(js, Wj));
-      sa.ldx = n;
-      sa.Z = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Zs; }));
-      sa.V = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Vs; }));
-      sa.ldz = n;
-      sa.ctr = sync;
-      solve_launch(sa, st, 0);
-      bytes_solve += 8.0 * (double)n * (double)n * na;
-      // b. full B-reorthogonalisation, twice; T's new column block from the projections
-      const auto vb = std::vector<int>(na, b);
-      const auto vn = std::vector<int>(na, n);
-      const auto vmq = act_vec(js, [&](int j) { return pr[j].mq; });
-      const auto vnl = act_vec(js, [&](int j) { return pr[j].nl; });
-      const auto pW = act_vec(js, [&](int j) { return (const double*)Wj(j); });
-      const auto pWm = act_vec(js, Wj);
-      // one tall-skinny launch computes both projections (locked basis: CL = UL^T W,
-      // active basis: CQ = UQ^T W) and one applies W -= L CL + Q CQ
-      std::vector<int> m_lq(vnl);
-      m_lq.insert(m_lq.end(), vmq.begin(), vmq.end());
-      std::vector<int> ld_lq(na, LC);
-      ld_lq.insert(ld_lq.end(), na, QC);
-      std::vector<const double*> v_lq = act_vec(js, [&](int j) { return (const double*)pd[j].UL; });
-      for (int j : js) v_lq.push_back(pd[j].UQ);
-      std::vector<const double*> x_lq(pW);
-      x_lq.insert(x_lq.end(), pW.begin(), pW.end());
-      std::vector<double*> c_lq = act_vec(js, [&](int j) { return pd[j].CL; });
-      for (int j : js) c_lq.push_back(pd[j].CQ);
-      int mtot = 0;
-      for (int q = 0; q < na; ++q) mtot = std::max(mtot, vnl[q] + vmq[q]);
-      for (int pass = 0; pass < 2; ++pass) {
-        TsArgs ta;
-        ta.n = n;
-        ta.m = ring.vec(m_lq);
-        ta.V = ring.cptrs(v_lq);
-        ta.ldv = n;
-        ta.X = ring.cptrs(x_lq);
-        ta.ldx = n;
-        ta.C = ring.ptrs(c_lq);
-        ta.ldcb = ring.vec(ld_lq);
-        ta.partial = tspart;
-        tsmt_launch(ta, 2 * na, ts_mmax, st);
-        TsArgs tm;
-        tm.n = n;
-        tm.m = ring.vec(vnl);
-        tm.V = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].L; }));
-        tm.ldv = n;
-        tm.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].CL; }));
-        tm.ldc = LC;
-        tm.m2 = ring.vec(vmq);
-        tm.V2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].Q; }));
-        tm.ldv2 = n;
-        tm.C2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].CQ; }));
-        tm.ldc2 = QC;
-        tm.Y = ring.ptrs(pWm);
-        tm.ldy = n;
-        tm.alpha = -1.0;
-        tm.beta = 1.0;
-        tsmm_launch(tm, na, mtot, st);
-        TWriteArgs tw;
-        tw.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
-        tw.ldt = QC;
-        tw.S = ring.cptrs(act_vec(js, [&](int j) { return pd[j].CQ; }));
-        tw.lds = QC;
-        tw.rows = ring.vec(vmq);
-        tw.r0 = ring.vec(std::vector<int>(na, 0));
-        tw.c0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq - b; }));
-        tw.cols = b;
-        tw.add = pass;
-        twrite_launch(tw, na, st);
-      }
-      // c. Z = B W for every probe in one GEMM (inactive blocks are recomputed harmlessly)
-      gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
-      // d. CholeskyQR2 into the next block; coupling block of T
-      cholqr2(js, pWm, act_vec(js, Zj), n, act_vec(js, [&](int j) { return pd[j].Q + (size_t)pr[j].mq * n; }),
-              act_vec(js, [&](int j) { return pd[j].UQ + (size_t)pr[j].mq * n; }), true);
-      for (int j : js) pr[j].mq += b;
-    }
-    // ---- cycle end: Ritz pairs of T, estimates, locking and thick restart
-    const int na = (int)act.size();
-    const auto vmt = act_vec(act, [&](int j) { return pr[j].mq - b; });
-    int mtmax = 0;
-    for (int v : vmt) mtmax = std::max(mtmax, v);
-    EigArgs e;
-    e.m = ring.vec(vmt);
-    e.A = ring.cptrs(act_vec(act, [&](int j) { return pd[j].T; }));
-    e.lda = QC;
-    e.W = ring.ptrs(act_vec(act, [&](int j) { return pd[j].th; }));
-    e.V = ring.ptrs(act_vec(act, [&](int j) { return pd[j].S; }));
-    e.ldv = QC;
-    eig_launch(e, na, mtmax, st);
-    RitzEstArgs re;
-    re.mt = ring.vec(vmt);
-    re.S = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
-    re.lds = QC;
-    re.Rt = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Rt; }));
-    re.est = ring.ptrs(act_vec(act, [&](int j) { return pd[j].est; }));
-    ritz_est_launch(re, na, st);
-    std::vector<std::vector<double>> th(na, std::vector<double>(QC)), es(na, std::vector<double>(QC));
-    for (int q = 0; q < na; ++q) {
-      SL_HIP(hipMemcpyAsync(th[q].data(), pd[act[q]].th, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
-      SL_HIP(hipMemcpyAsync(es[q].data(), pd[act[q]].est, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
-    }
-    std::vector<int> hflags(P, 0);
-    SL_HIP(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * P, hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
-    ring.synced();
-    std::vector<std::vector<int>> lk(na), kp(na);
-    std::vector<std::vector<double>> thk(na);
-    for (int q = 0; q < na; ++q) {
-      const int j = act[q];
-      auto& p = pr[j];
-      p.cycles++;
-      const int mt = vmt[q];
-      const double scale = (anorm + std::fabs(p.sigma) * bnorm) / anorm;
-      std::vector<int> rest;
-      for (int i = 0; i < mt; ++i) {
-        const double t = th[q][i];
-        if (t == 0.0 || !std::isfinite(t)) continue;
-        const double lam = p.sigma + 1.0 / t;
-        const double r = es[q][i] / std::fabs(t) * scale;
-        // Converged pairs are locked.  Inside the window they count toward the
-        // probe's slices.  Outside it they deflate: they are the pairs nearest to
-        // the shift and would otherwise fill the kept restart vectors for good,
-        // crowding out farther values the window still needs.  Room stays reserved
-        // for the values still missing from the window.
-        const bool inwin = lam > p.lo && lam < p.hi;
-        const int used = p.nl + (int)lk[q].size();
-        const int64_t missing = std::max<int64_t>(0, p.need - p.nin);
-        if (r <= lock_tol && inwin && used < LC) {
-          lk[q].push_back(i);
-          p.lock_lam.push_back(lam);
-          ++p.nin;
-        } else if (r <= lock_tol && !inwin && used + missing < LC) {
-          lk[q].push_back(i);
-          p.lock_lam.push_back(lam);
-        } else {
-          rest.push_back(i);
-        }
-      }
-      std::stable_sort(rest.begin(), rest.end(),
-                       [&](int x, int y) { return std::fabs(th[q][x]) > std::fabs(th[q][y]); });
-      const int kk = std::min<int>((int)rest.size(), kkeep_max);
-      kp[q].assign(rest.begin(), rest.begin() + kk);
-      for (int i : kp[q]) thk[q].push_back(th[q][i]);
-    }
-    // device: select columns, lock GEMMs, keep GEMMs, move newest block, reset T
-    std::vector<int> nlk(na), nkp(na), rows(na);
-    for (int q = 0; q < na; ++q) {
-      nlk[q] = (int)lk[q].size();
-      nkp[q] = (int)kp[q].size();
-      rows[q] = vmt[q];
-    }
-    std::vector<int*> il_ptr(na), ik_ptr(na);
-    for (int q = 0; q < na; ++q) {
-      il_ptr[q] = ring.vec(lk[q]);
-      ik_ptr[q] = ring.vec(kp[q]);
-    }
-    SelectArgs sl;
-    sl.count = ring.vec(nlk);
-    sl.rows = ring.vec(rows);
-    sl.in = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
-    sl.ldi = QC;
-    sl.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SL; }));
-    sl.ldo = QC;
-    sl.idx = ring.cptrs(il_ptr);
-    select_launch(sl, na, (long)QC * QC, st);
-    SelectArgs sk = sl;
-    sk.count = ring.vec(nkp);
-    sk.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SK; }));
-    sk.idx = ring.cptrs(ik_ptr);
-    select_launch(sk, na, (long)QC * QC, st);
-    const auto vn = std::vector<int>(na, n);
-    gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
-         act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
-         act_vec(act, [&](int j) { return pd[j].L + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
-    gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
-         act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
-         act_vec(act, [&](int j) { return pd[j].UL + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
-    gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
-         act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
-         act_vec(act, [&](int j) { return pd[j].Xt; }), n, 1.0, 0.0);
-    gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
-         act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
-         act_vec(act, [&](int j) { return pd[j].Ut; }), n, 1.0, 0.0);
-    CopyArgs cp;
-    cp.n = n;
-    cp.ncol = ring.vec(std::vector<int>(na, b));
-    cp.lds = n;
-    cp.ldd = n;
-    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Q + (size_t)(pr[j].mq - b) * n; }));
-    cp.dst = ring.ptrs([&] {
-      std::vector<double*> v;
-      for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].Q + (size_t)nkp[q] * n);
-      return v;
-    }());
-    copy_launch(cp, na, b, st);
-    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
-    cp.dst = ring.ptrs([&] {
-      std::vector<double*> v;
-      for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].UQ + (size_t)nkp[q] * n);
-      return v;
-    }());
-    copy_launch(cp, na, b, st);
-    cp.ncol = ring.vec(nkp);
-    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Xt; }));
-    cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].Q; }));
-    copy_launch(cp, na, kkeep_max, st);
-    cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Ut; }));
-    cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].UQ; }));
-    copy_launch(cp, na, kkeep_max, st);
-    std::vector<double*> thp(na);
-    for (int q = 0; q < na; ++q) thp[q] = ring.vec(thk[q]);
-    TResetArgs tr;
-    tr.active = ring.vec(std::vector<int>(na, 1));
-    tr.T = ring.ptrs(act_vec(act, [&](int j) { return pd[j].T; }));
-    tr.ldt = QC;
-    tr.dim = QC;
-    tr.k = ring.vec(nkp);
-    tr.theta = ring.cptrs(thp);
-    treset_launch(tr, na, st);
-    for (int q = 0; q < na; ++q) {
-      auto& p = pr[act[q]];
-      p.nl += nlk[q];
-      p.mq = nkp[q] + b;
-    }
-    // probe activity from slice completion
-    std::vector<bool> done(P + 1);
-    for (int s = 0; s <= P; ++s) done[s] = slice_done(s);
-    for (int j = 0; j < P; ++j) {
-      pr[j].active = !(done[j] && done[j + 1]) && pr[j].nl < LC;
-      cycles_max = std::max(cycles_max, pr[j].cycles);
-    }
-  }
-  SL_HIP(hipStreamSynchronize(st));
-  ring.synced();
-  const double t_lanczos = ms_since(t_l0);
-  // ---- 3. explicit Rayleigh-Ritz with A on the locked vectors, residuals
-  const auto t_r0 = Clock::now();
+  // ---- 2. the probes: block shift-invert Lanczos (reading R1), or the paper's
+  // subspace iteration (Algorithm 2); both hand their Ritz pairs, in chunks of
+  // at most kEigMax per probe, to the validation
   struct Chunk {
     int probe, off, cnt;
     std::vector<int> cols;
   };
   std::vector<Chunk> chunks;
   int NL = 0;
-  for (int j = 0; j < P; ++j) {
-    std::vector<int> ord(pr[j].nl);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return pr[j].lock_lam[x] < pr[j].lock_lam[y]; });
-    for (int s0 = 0; s0 < (int)ord.size(); s0 += kEigMax) {
+  std::vector<double> vals, ress;
+  double* Xf = nullptr;
+  int block_steps = 0, cycles_max = 0;
+  double bytes_solve = 0.0;
+  double t_lanczos = 0.0, t_rr = 0.0;
+  if (o.driver == 1) {
+    const auto t_s0 = Clock::now();
+    std::vector<SubspaceProbe> sp(P);
+    int64_t max_need = 0;
+    for (int j = 0; j < P; ++j) {
+      auto& q = sp[j];
+      q.sigma = sig[j];
+      q.lo = j > 0 ? sig[j - 1] : -std::numeric_limits<double>::infinity();
+      q.hi = j + 1 < P ? sig[j + 1] : top;
+      const int64_t nlo = j > 0 ? nu[j - 1] : 0;
+      const int64_t nhi = j + 1 < P ? nu[j + 1] : nu_top;
+      q.need = nhi - nlo;
+      max_need = std::max(max_need, q.need);
+      q.LD = LD[j];
+      q.perm = perm[j];
+      q.blk = blk[j];
+      q.Linv = Linv[j];
+    }
+    const int k = std::min(subspace_dim(max_need), n);
+    SubspaceOut so = subspace_probes(c, n, Af, Bf, sp, anorm, o, k, o.subspace_iters, start,
+                                     start_cols, 0, n);
+    for (int j = 0; j < P; ++j) {
       Chunk ch;
       ch.probe = j;
       ch.off = NL;
-      ch.cnt = std::min<int>(kEigMax, (int)ord.size() - s0);
-      ch.cols.assign(ord.begin() + s0, ord.begin() + s0 + ch.cnt);
-      NL += ch.cnt;
+      ch.cnt = k;
+      for (int i = 0; i < k; ++i) ch.cols.push_back(i);
+      NL += k;
       chunks.push_back(std::move(ch));
     }
-  }
-  const int NC = (int)chunks.size();
-  std::vector<double> vals(NL), ress(NL);
-  double *Xa = nullptr, *AXa = nullptr, *BXa = nullptr, *Xf = nullptr, *AXf = nullptr, *BXf = nullptr,
-         *Hm = nullptr, *Om = nullptr, *Ym = nullptr, *rr = nullptr, *xn = nullptr;
-  constexpr int kRrMats = 6;  // G, its eigenvectors U, U w^{-1/2}, S = G^{-1/2}, S H, S H S
-  const size_t e2 = (size_t)kEigMax * kEigMax;
-  if (NL > 0) {
-    Sizer zr;
-    for (int q = 0; q < 6; ++q) zr.take<double>((size_t)n * NL);
-    zr.take<double>((size_t)NC * kEigMax * kEigMax);
-    zr.take<double>((size_t)NC * kEigMax);
-    zr.take<double>((size_t)NC * kEigMax * kEigMax);
-    zr.take<double>(NL);
-    zr.take<double>(NL);
-    zr.take<double>((size_t)NC * kRrMats * e2);
-    zr.take<double>((size_t)NC * kEigMax);
-    zr.take<double>((size_t)NC * e2);
-    Carver cr(ws_get(h, kBufEig, zr.off));
-    Xa = cr.take<double>((size_t)n * NL);
-    AXa = cr.take<double>((size_t)n * NL);
-    BXa = cr.take<double>((size_t)n * NL);
-    Xf = cr.take<double>((size_t)n * NL);
-    AXf = cr.take<double>((size_t)n * NL);
-    BXf = cr.take<double>((size_t)n * NL);
-    Hm = cr.take<double>((size_t)NC * kEigMax * kEigMax);
-    Om = cr.take<double>((size_t)NC * kEigMax);
-    Ym = cr.take<double>((size_t)NC * kEigMax * kEigMax);
-    rr = cr.take<double>(NL);
-    xn = cr.take<double>(NL);
-    double* Gm = cr.take<double>((size_t)NC * kRrMats * e2);
-    double* Gw = cr.take<double>((size_t)NC * kEigMax);
-    double* Y2 = cr.take<double>((size_t)NC * e2);
-    std::vector<int> cnts(NC), rowsn(NC, n);
-    std::vector<int*> idxp(NC);
-    for (int q = 0; q < NC; ++q) {
-      cnts[q] = chunks[q].cnt;
-      idxp[q] = ring.vec(chunks[q].cols);
+    vals = so.vals;
+    ress = so.ress;
+    Xf = so.X;
+    block_steps = so.applications;
+    cycles_max = so.rounds_max;
+    bytes_solve = so.bytes_solve;
+    t_lanczos = ms_since(t_s0);
+  } else {
+    // ---- 2. block Lanczos per probe
+    const auto t_l0 = Clock::now();
+    std::vector<ProbeHost> pr(P);
+    int64_t max_need = 0;
+    for (int j = 0; j < P; ++j) {
+      pr[j].sigma = sig[j];
+      pr[j].lo = j > 0 ? sig[j - 1] : -std::numeric_limits<double>::infinity();
+      pr[j].hi = j + 1 < P ? sig[j + 1] : top;
+      const int64_t nlo = j > 0 ? nu[j - 1] : 0;
+      const int64_t nhi = j + 1 < P ? nu[j + 1] : nu_top;
+      pr[j].need = nhi - nlo;
+      max_need = std::max(max_need, pr[j].need);
     }
-    SelectArgs sx;
-    sx.count = ring.vec(cnts);
-    sx.rows = ring.vec(rowsn);
-    sx.in = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return pd[ch.probe].L; }));
-    sx.ldi = n;
-    sx.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return Xa + (size_t)ch.off * n; }));
-    sx.ldo = n;
-    sx.idx = ring.cptrs(idxp);
-    select_launch(sx, NC, (long)n * kEigMax, st);
-    gemm(c, false, false, {n}, {NL}, {n}, {Af}, n, {Xa}, n, {AXa}, n, 1.0, 0.0);
-    gemm(c, false, false, {n}, {NL}, {n}, {Bf}, n, {Xa}, n, {BXa}, n, 1.0, 0.0);
-    auto cX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(Xa + (size_t)ch.off * n); });
-    auto cAX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(AXa + (size_t)ch.off * n); });
-    auto cBX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(BXa + (size_t)ch.off * n); });
-    std::vector<double*> pH(NC), pO(NC), pY(NC);
-    for (int q = 0; q < NC; ++q) {
-      pH[q] = Hm + (size_t)q * kEigMax * kEigMax;
-      pO[q] = Om + (size_t)q * kEigMax;
-      pY[q] = Ym + (size_t)q * kEigMax * kEigMax;
+    // locked capacity: the values a probe needs plus room for deflated pairs
+    const int LC = (int)std::min<int64_t>(n, 2 * max_need + 16);
+    int MB = o.max_basis;
+    while (MB > 16 && MB + 2 * b + LC > n) MB -= b;
+    const int QC = MB + 2 * b;
+    // thick restart: keep the Ritz vectors nearest the shift and add four blocks per
+    // cycle (measured against six and two: fewer Lanczos steps without more cycles)
+    const int kkeep_max = std::max(b, MB - 4 * b);
+    Sizer zl;
+    zl.take<double>((size_t)n * b * P);  // W_all
+    zl.take<double>((size_t)n * b * P);  // Z_all
+    for (int j = 0; j < P; ++j) {
+      zl.take<double>((size_t)n * QC);  // Q
+      zl.take<double>((size_t)n * QC);  // UQ
+      zl.take<double>((size_t)n * LC);  // L
+      zl.take<double>((size_t)n * LC);  // UL
+      zl.take<double>((size_t)n * MB);  // Xt
+      zl.take<double>((size_t)n * MB);  // Ut
+      zl.take<double>((size_t)n * b);   // solve scratch Z
+      zl.take<double>((size_t)n * b);   // solve scratch V
+      zl.take<double>((size_t)QC * QC);  // T
+      zl.take<double>((size_t)QC * QC);  // S (eigvecs)
+      zl.take<double>((size_t)QC * QC);  // S lock sel
+      zl.take<double>((size_t)QC * QC);  // S keep sel
+      zl.take<double>(QC);               // theta
+      zl.take<double>(QC);               // est
+      zl.take<double>((size_t)QC * b);   // CQ
+      zl.take<double>((size_t)LC * b);   // CL
+      zl.take<double>(4 * b * b);        // G, R1, R2, Rt
+      zl.take<int>(2 * QC);              // idx lock / keep
     }
-    gemm(c, true, false, cnts, cnts, rowsn, cX, n, cAX, n, pH, kEigMax, 1.0, 0.0);
-    int cmax = 0;
-    for (int v : cnts) cmax = std::max(cmax, v);
-    // The locked vectors are B-orthonormal only up to the drift of many restart
-    // cycles (the deflation-locked ones in particular), and a standard
-    // Rayleigh-Ritz step would carry that drift into the residuals.  The
-    // symmetric orthonormalisation S = G^{-1/2} of G = X^T B X (from the
-    // eigenpairs of G, which is close to the identity) makes the step the exact
-    // generalized one: eig(S H S) = (Omega, Y), Ritz vectors X S Y.
-    std::vector<double*> pG(NC), pU(NC), pUs(NC), pS(NC), pT(NC), pH2(NC), pGw(NC), pY2(NC);
-    for (int q = 0; q < NC; ++q) {
-      double* g0 = Gm + (size_t)q * kRrMats * e2;
-      pG[q] = g0;
-      pU[q] = g0 + e2;
-      pUs[q] = g0 + 2 * e2;
-      pS[q] = g0 + 3 * e2;
-      pT[q] = g0 + 4 * e2;
-      pH2[q] = g0 + 5 * e2;
-      pGw[q] = Gw + (size_t)q * kEigMax;
-      pY2[q] = Y2 + (size_t)q * e2;
+    zl.take<int>(P);  // flags
+    const int ts_mmax = std::max(LC, QC);
+    zl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));  // tall-skinny partials
+    Carver cl(ws_get(h, kBufLanczos, zl.off));
+    double* Wall = cl.take<double>((size_t)n * b * P);
+    double* Zall = cl.take<double>((size_t)n * b * P);
+    struct ProbeDev {
+      double *Q, *UQ, *L, *UL, *Xt, *Ut, *Zs, *Vs, *T, *S, *SL, *SK, *th, *est, *CQ, *CL, *G, *R1, *R2, *Rt;
+      int *il, *ik;
+    };
+    std::vector<ProbeDev> pd(P);
+    for (int j = 0; j < P; ++j) {
+      auto& d = pd[j];
+      d.Q = cl.take<double>((size_t)n * QC);
+      d.UQ = cl.take<double>((size_t)n * QC);
+      d.L = cl.take<double>((size_t)n * LC);
+      d.UL = cl.take<double>((size_t)n * LC);
+      d.Xt = cl.take<double>((size_t)n * MB);
+      d.Ut = cl.take<double>((size_t)n * MB);
+      d.Zs = cl.take<double>((size_t)n * b);
+      d.Vs = cl.take<double>((size_t)n * b);
+      d.T = cl.take<double>((size_t)QC * QC);
+      d.S = cl.take<double>((size_t)QC * QC);
+      d.SL = cl.take<double>((size_t)QC * QC);
+      d.SK = cl.take<double>((size_t)QC * QC);
+      d.th = cl.take<double>(QC);
+      d.est = cl.take<double>(QC);
+      d.CQ = cl.take<double>((size_t)QC * b);
+      d.CL = cl.take<double>((size_t)LC * b);
+      double* g4 = cl.take<double>(4 * b * b);
+      d.G = g4;
+      d.R1 = g4 + b * b;
+      d.R2 = g4 + 2 * b * b;
+      d.Rt = g4 + 3 * b * b;
+      int* ii = cl.take<int>(2 * QC);
+      d.il = ii;
+      d.ik = ii + QC;
     }
-    auto cc = [](const std::vector<double*>& v) { return std::vector<const double*>(v.begin(), v.end()); };
-    gemm(c, true, false, cnts, cnts, rowsn, cX, n, cBX, n, pG, kEigMax, 1.0, 0.0);
-    EigArgs eg;
-    eg.m = ring.vec(cnts);
-    eg.A = ring.cptrs(pG);
-    eg.lda = kEigMax;
-    eg.W = ring.ptrs(pGw);
-    eg.V = ring.ptrs(pU);
-    eg.ldv = kEigMax;
-    eig_launch(eg, NC, cmax, st);
-    for (int q = 0; q < NC; ++q)
-      scale_cols_launch(cnts[q], cnts[q], pGw[q], pU[q], kEigMax, pUs[q], kEigMax, nullptr, st);
-    gemm(c, false, true, cnts, cnts, cnts, cc(pUs), kEigMax, cc(pU), kEigMax, pS, kEigMax, 1.0, 0.0);
-    gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pH), kEigMax, pT, kEigMax, 1.0, 0.0);
-    gemm(c, false, false, cnts, cnts, cnts, cc(pT), kEigMax, cc(pS), kEigMax, pH2, kEigMax, 1.0, 0.0);
-    EigArgs e;
-    e.m = ring.vec(cnts);
-    e.A = ring.cptrs(pH2);
-    e.lda = kEigMax;
-    e.W = ring.ptrs(pO);
-    e.V = ring.ptrs(pY);
-    e.ldv = kEigMax;
-    eig_launch(e, NC, cmax, st);
-    gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pY), kEigMax, pY2, kEigMax, 1.0, 0.0);
-    std::vector<const double*> cY(pY2.begin(), pY2.end());
-    gemm(c, false, false, rowsn, cnts, cnts, cX, n, cY, kEigMax,
-         act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }), n, 1.0, 0.0);
-    gemm(c, false, false, rowsn, cnts, cnts, cAX, n, cY, kEigMax,
-         act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
-    gemm(c, false, false, rowsn, cnts, cnts, cBX, n, cY, kEigMax,
-         act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
-    ColDotArgs r1;
-    r1.n = n;
-    r1.ncol = ring.vec(cnts);
-    r1.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }));
-    r1.ldx = n;
-    r1.Y = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }));
-    r1.ldy = n;
-    r1.w = ring.cptrs(pO);
-    r1.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return rr + ch.off; }));
-    r1.mode = 1;
-    r1.partial = static_cast<double*>(ws_get(h, kBufMisc, sizeof(double) * coldot_partial_size(n, NC, kEigMax)));
-    coldot_launch(r1, NC, cmax, st);
-    ColDotArgs r2 = r1;
-    r2.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }));
-    r2.Y = r2.X;
-    r2.ldy = n;
-    r2.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return xn + ch.off; }));
-    r2.mode = 0;
-    coldot_launch(r2, NC, cmax, st);
-    std::vector<double> hr(NL), hx(NL), ho((size_t)NC * kEigMax);
-    SL_HIP(hipMemcpyAsync(hr.data(), rr, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(hx.data(), xn, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
-    SL_HIP(hipMemcpyAsync(ho.data(), Om, sizeof(double) * NC * kEigMax, hipMemcpyDeviceToHost, st));
+    int* dflags = cl.take<int>(P);
+    double* tspart = cl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));
+    for (int j = 0; j < P; ++j) SL_HIP(hipMemsetAsync(pd[j].T, 0, sizeof(double) * QC * QC, st));
+    unsigned* sync = sync_words(h, (size_t)P + 64);  // one ticket counter per probe
+    auto Wj = [&](int j) { return Wall + (size_t)j * n * b; };
+    auto Zj = [&](int j) { return Zall + (size_t)j * n * b; };
+    // start blocks: Gaussian from the shared stream, or the caller's (warm start),
+    // B-orthonormalised (CholeskyQR2)
+    if (start) {
+      SL_HIP(hipMemcpyAsync(Wall, start, sizeof(double) * (size_t)n * b * P, hipMemcpyDeviceToDevice, st));
+    } else {
+      std::vector<unsigned long long> seeds(P);
+      std::vector<double*> wp(P);
+      for (int j = 0; j < P; ++j) {
+        seeds[j] = rng_derive(o.seed, kTagLanczos ^ ((uint64_t)j << 32));
+        wp[j] = Wj(j);
+      }
+      gauss_launch(n, b, P, ring.vec(seeds), ring.ptrs(wp), n, st);
+    }
+    std::vector<int> all(P);
+    std::iota(all.begin(), all.end(), 0);
+    auto act_vec = [&](const auto& js, auto f) {
+      using T = decltype(f(js[0]));
+      std::vector<T> v;
+      v.reserve(js.size());
+      for (const auto& j : js) v.push_back(f(j));
+      return v;
+    };
+    auto cholqr2 = [&](const std::vector<int>& js, const std::vector<double*>& Vin,
+                       const std::vector<double*>& Uin, long ldin, const std::vector<double*>& Vout,
+                       const std::vector<double*>& Uout, bool coupling) {
+      const int na = (int)js.size();
+      std::vector<int> ones(na, 1), bs(na, b), ns(na, n);
+      std::vector<const double*> cV(Vin.begin(), Vin.end()), cU(Uin.begin(), Uin.end());
+      auto gram = [&](const std::vector<const double*>& Vv, const std::vector<const double*>& Uv, long ld) {
+        TsArgs ta;
+        ta.n = n;
+        ta.m = ring.vec(bs);
+        ta.V = ring.cptrs(Vv);
+        ta.ldv = ld;
+        ta.X = ring.cptrs(Uv);
+        ta.ldx = ld;
+        ta.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].G; }));
+        ta.ldc = b;
+        ta.partial = tspart;
+        tsmt_launch(ta, na, b, st);
+      };
+      gram(cV, cU, ldin);
+      CholQrArgs q;
+      q.n = n;
+      q.active = ring.vec(ones);
+      q.G = ring.cptrs(act_vec(js, [&](int j) { return pd[j].G; }));
+      q.Vin = ring.cptrs(Vin);
+      q.Uin = ring.cptrs(Uin);
+      q.ldin = ldin;
+      q.Vout = ring.ptrs(Vout);
+      q.Uout = ring.ptrs(Uout);
+      q.ldout = n;
+      q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
+      q.flag = dflags;  // indexed by position; only read when all probes are active
+      cholqr_launch(q, na, st);
+      std::vector<const double*> cVo(Vout.begin(), Vout.end()), cUo(Uout.begin(), Uout.end());
+      gram(cVo, cUo, n);
+      q.Vin = ring.cptrs(Vout);
+      q.Uin = ring.cptrs(Uout);
+      q.ldin = n;
+      q.R = ring.ptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
+      cholqr_launch(q, na, st);
+      if (coupling) {
+        CouplingArgs ca;
+        ca.active = ring.vec(ones);
+        ca.R1 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R1; }));
+        ca.R2 = ring.cptrs(act_vec(js, [&](int j) { return pd[j].R2; }));
+        ca.Rt = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Rt; }));
+        ca.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
+        ca.ldt = QC;
+        ca.row0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq; }));
+        coupling_launch(ca, na, st);
+      }
+    };
+    // Z = B W, then B-orthonormalise into Q[:, 0:8]
+    gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
+    cholqr2(all, act_vec(all, Wj), act_vec(all, Zj), n, act_vec(all, [&](int j) { return pd[j].Q; }),
+            act_vec(all, [&](int j) { return pd[j].UQ; }), false);
+    for (int j = 0; j < P; ++j) pr[j].mq = b;
+    // slice bookkeeping
+    std::vector<int64_t> n_exact(P + 1);
+    for (int s = 0; s <= P; ++s) {
+      const int64_t lo = s == 0 ? 0 : nu[s - 1];
+      const int64_t hi = s == P ? nu_top : nu[s];
+      n_exact[s] = hi - lo;
+    }
+    auto slice_done = [&](int s) {
+      int64_t cnt = 0;
+      if (s == 0) {
+        for (double v : pr[0].lock_lam) cnt += v < sig[0];
+      } else if (s == P) {
+        for (double v : pr[P - 1].lock_lam) cnt += v >= sig[P - 1] && v < top;
+      } else {
+        const double lo = sig[s - 1], hi = sig[s], tau = 0.5 * (lo + hi);
+        for (double v : pr[s - 1].lock_lam) cnt += v >= lo && v <= tau;
+        for (double v : pr[s].lock_lam) cnt += v > tau && v < hi;
+      }
+      return cnt >= n_exact[s];
+    };
+    const double lock_tol = o.tol / 100.0;
+    for (int cyc = 0; cyc < o.max_cycles; ++cyc) {
+      std::vector<int> act;
+      for (int j = 0; j < P; ++j)
+        if (pr[j].active) act.push_back(j);
+      if (act.empty()) break;
+      // ---- steps until every active probe's basis is full
+      while (true) {
+        std::vector<int> js;
+        for (int j : act)
+          if (pr[j].mq <= MB) js.push_back(j);  // the projected order mq - b stays <= MB
+        if (js.empty()) break;
+        const int na = (int)js.size();
+        block_steps += na;
+        for (int j : js) pr[j].steps++;
+        // a. W_j = (A - sigma_j B)^{-1} U_j[:, last block]
+        SolveArgs sa;
+        sa.n = n;
+        sa.nshift = na;
+        sa.nrhs = b;
+        sa.epoch = next_epoch(h);
+        sa.LD = ring.cptrs(act_vec(js, [&](int j) { return LD[j]; }));
+        sa.ldld = n;
+        sa.perm = ring.cptrs(act_vec(js, [&](int j) { return perm[j]; }));
+        sa.blk = ring.cptrs(act_vec(js, [&](int j) { return blk[j]; }));
+        sa.Linv = ring.cptrs(act_vec(js, [&](int j) { return Linv[j]; }));
+        sa.Y = ring.cptrs(act_vec(js, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
+        sa.ldy = n;
+        sa.X = ring.ptrs(act_vec(js, Wj));
+        sa.ldx = n;
+        sa.Z = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Zs; }));
+        sa.V = ring.ptrs(act_vec(js, [&](int j) { return pd[j].Vs; }));
+        sa.ldz = n;
+        sa.ctr = sync;
+        solve_launch(sa, st, 0);
+        bytes_solve += 8.0 * (double)n * (double)n * na;
+        // b. full B-reorthogonalisation, twice; T's new column block from the projections
+        const auto vb = std::vector<int>(na, b);
+        const auto vn = std::vector<int>(na, n);
+        const auto vmq = act_vec(js, [&](int j) { return pr[j].mq; });
+        const auto vnl = act_vec(js, [&](int j) { return pr[j].nl; });
+        const auto pW = act_vec(js, [&](int j) { return (const double*)Wj(j); });
+        const auto pWm = act_vec(js, Wj);
+        // one tall-skinny launch computes both projections (locked basis: CL = UL^T W,
+        // active basis: CQ = UQ^T W) and one applies W -= L CL + Q CQ
+        std::vector<int> m_lq(vnl);
+        m_lq.insert(m_lq.end(), vmq.begin(), vmq.end());
+        std::vector<int> ld_lq(na, LC);
+        ld_lq.insert(ld_lq.end(), na, QC);
+        std::vector<const double*> v_lq = act_vec(js, [&](int j) { return (const double*)pd[j].UL; });
+        for (int j : js) v_lq.push_back(pd[j].UQ);
+        std::vector<const double*> x_lq(pW);
+        x_lq.insert(x_lq.end(), pW.begin(), pW.end());
+        std::vector<double*> c_lq = act_vec(js, [&](int j) { return pd[j].CL; });
+        for (int j : js) c_lq.push_back(pd[j].CQ);
+        int mtot = 0;
+        for (int q = 0; q < na; ++q) mtot = std::max(mtot, vnl[q] + vmq[q]);
+        for (int pass = 0; pass < 2; ++pass) {
+          TsArgs ta;
+          ta.n = n;
+          ta.m = ring.vec(m_lq);
+          ta.V = ring.cptrs(v_lq);
+          ta.ldv = n;
+          ta.X = ring.cptrs(x_lq);
+          ta.ldx = n;
+          ta.C = ring.ptrs(c_lq);
+          ta.ldcb = ring.vec(ld_lq);
+          ta.partial = tspart;
+          tsmt_launch(ta, 2 * na, ts_mmax, st);
+          TsArgs tm;
+          tm.n = n;
+          tm.m = ring.vec(vnl);
+          tm.V = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].L; }));
+          tm.ldv = n;
+          tm.C = ring.ptrs(act_vec(js, [&](int j) { return pd[j].CL; }));
+          tm.ldc = LC;
+          tm.m2 = ring.vec(vmq);
+          tm.V2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].Q; }));
+          tm.ldv2 = n;
+          tm.C2 = ring.cptrs(act_vec(js, [&](int j) { return (const double*)pd[j].CQ; }));
+          tm.ldc2 = QC;
+          tm.Y = ring.ptrs(pWm);
+          tm.ldy = n;
+          tm.alpha = -1.0;
+          tm.beta = 1.0;
+          tsmm_launch(tm, na, mtot, st);
+          TWriteArgs tw;
+          tw.T = ring.ptrs(act_vec(js, [&](int j) { return pd[j].T; }));
+          tw.ldt = QC;
+          tw.S = ring.cptrs(act_vec(js, [&](int j) { return pd[j].CQ; }));
+          tw.lds = QC;
+          tw.rows = ring.vec(vmq);
+          tw.r0 = ring.vec(std::vector<int>(na, 0));
+          tw.c0 = ring.vec(act_vec(js, [&](int j) { return pr[j].mq - b; }));
+          tw.cols = b;
+          tw.add = pass;
+          twrite_launch(tw, na, st);
+        }
+        // c. Z = B W for every probe in one GEMM (inactive blocks are recomputed harmlessly)
+        gemm(c, false, false, {n}, {b * P}, {n}, {Bf}, n, {Wall}, n, {Zall}, n, 1.0, 0.0);
+        // d. CholeskyQR2 into the next block; coupling block of T
+        cholqr2(js, pWm, act_vec(js, Zj), n, act_vec(js, [&](int j) { return pd[j].Q + (size_t)pr[j].mq * n; }),
+                act_vec(js, [&](int j) { return pd[j].UQ + (size_t)pr[j].mq * n; }), true);
+        for (int j : js) pr[j].mq += b;
+      }
+      // ---- cycle end: Ritz pairs of T, estimates, locking and thick restart
+      const int na = (int)act.size();
+      const auto vmt = act_vec(act, [&](int j) { return pr[j].mq - b; });
+      int mtmax = 0;
+      for (int v : vmt) mtmax = std::max(mtmax, v);
+      EigArgs e;
+      e.m = ring.vec(vmt);
+      e.A = ring.cptrs(act_vec(act, [&](int j) { return pd[j].T; }));
+      e.lda = QC;
+      e.W = ring.ptrs(act_vec(act, [&](int j) { return pd[j].th; }));
+      e.V = ring.ptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+      e.ldv = QC;
+      eig_launch(e, na, mtmax, st);
+      RitzEstArgs re;
+      re.mt = ring.vec(vmt);
+      re.S = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+      re.lds = QC;
+      re.Rt = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Rt; }));
+      re.est = ring.ptrs(act_vec(act, [&](int j) { return pd[j].est; }));
+      ritz_est_launch(re, na, st);
+      std::vector<std::vector<double>> th(na, std::vector<double>(QC)), es(na, std::vector<double>(QC));
+      for (int q = 0; q < na; ++q) {
+        SL_HIP(hipMemcpyAsync(th[q].data(), pd[act[q]].th, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
+        SL_HIP(hipMemcpyAsync(es[q].data(), pd[act[q]].est, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
+      }
+      std::vector<int> hflags(P, 0);
+      SL_HIP(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipStreamSynchronize(st));
+      ring.synced();
+      std::vector<std::vector<int>> lk(na), kp(na);
+      std::vector<std::vector<double>> thk(na);
+      for (int q = 0; q < na; ++q) {
+        const int j = act[q];
+        auto& p = pr[j];
+        p.cycles++;
+        const int mt = vmt[q];
+        const double scale = (anorm + std::fabs(p.sigma) * bnorm) / anorm;
+        std::vector<int> rest;
+        for (int i = 0; i < mt; ++i) {
+          const double t = th[q][i];
+          if (t == 0.0 || !std::isfinite(t)) continue;
+          const double lam = p.sigma + 1.0 / t;
+          const double r = es[q][i] / std::fabs(t) * scale;
+          // Converged pairs are locked.  Inside the window they count toward the
+          // probe's slices.  Outside it they deflate: they are the pairs nearest to
+          // the shift and would otherwise fill the kept restart vectors for good,
+          // crowding out farther values the window still needs.  Room stays reserved
+          // for the values still missing from the window.
+          const bool inwin = lam > p.lo && lam < p.hi;
+          const int used = p.nl + (int)lk[q].size();
+          const int64_t missing = std::max<int64_t>(0, p.need - p.nin);
+          if (r <= lock_tol && inwin && used < LC) {
+            lk[q].push_back(i);
+            p.lock_lam.push_back(lam);
+            ++p.nin;
+          } else if (r <= lock_tol && !inwin && used + missing < LC) {
+            lk[q].push_back(i);
+            p.lock_lam.push_back(lam);
+          } else {
+            rest.push_back(i);
+          }
+        }
+        std::stable_sort(rest.begin(), rest.end(),
+                         [&](int x, int y) { return std::fabs(th[q][x]) > std::fabs(th[q][y]); });
+        const int kk = std::min<int>((int)rest.size(), kkeep_max);
+        kp[q].assign(rest.begin(), rest.begin() + kk);
+        for (int i : kp[q]) thk[q].push_back(th[q][i]);
+      }
+      // device: select columns, lock GEMMs, keep GEMMs, move newest block, reset T
+      std::vector<int> nlk(na), nkp(na), rows(na);
+      for (int q = 0; q < na; ++q) {
+        nlk[q] = (int)lk[q].size();
+        nkp[q] = (int)kp[q].size();
+        rows[q] = vmt[q];
+      }
+      std::vector<int*> il_ptr(na), ik_ptr(na);
+      for (int q = 0; q < na; ++q) {
+        il_ptr[q] = ring.vec(lk[q]);
+        ik_ptr[q] = ring.vec(kp[q]);
+      }
+      SelectArgs sl;
+      sl.count = ring.vec(nlk);
+      sl.rows = ring.vec(rows);
+      sl.in = ring.cptrs(act_vec(act, [&](int j) { return pd[j].S; }));
+      sl.ldi = QC;
+      sl.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SL; }));
+      sl.ldo = QC;
+      sl.idx = ring.cptrs(il_ptr);
+      select_launch(sl, na, (long)QC * QC, st);
+      SelectArgs sk = sl;
+      sk.count = ring.vec(nkp);
+      sk.out = ring.ptrs(act_vec(act, [&](int j) { return pd[j].SK; }));
+      sk.idx = ring.cptrs(ik_ptr);
+      select_launch(sk, na, (long)QC * QC, st);
+      const auto vn = std::vector<int>(na, n);
+      gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
+           act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
+           act_vec(act, [&](int j) { return pd[j].L + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
+      gemm(c, false, false, vn, nlk, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
+           act_vec(act, [&](int j) { return (const double*)pd[j].SL; }), QC,
+           act_vec(act, [&](int j) { return pd[j].UL + (size_t)pr[j].nl * n; }), n, 1.0, 0.0);
+      gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].Q; }), n,
+           act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
+           act_vec(act, [&](int j) { return pd[j].Xt; }), n, 1.0, 0.0);
+      gemm(c, false, false, vn, nkp, vmt, act_vec(act, [&](int j) { return (const double*)pd[j].UQ; }), n,
+           act_vec(act, [&](int j) { return (const double*)pd[j].SK; }), QC,
+           act_vec(act, [&](int j) { return pd[j].Ut; }), n, 1.0, 0.0);
+      CopyArgs cp;
+      cp.n = n;
+      cp.ncol = ring.vec(std::vector<int>(na, b));
+      cp.lds = n;
+      cp.ldd = n;
+      cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Q + (size_t)(pr[j].mq - b) * n; }));
+      cp.dst = ring.ptrs([&] {
+        std::vector<double*> v;
+        for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].Q + (size_t)nkp[q] * n);
+        return v;
+      }());
+      copy_launch(cp, na, b, st);
+      cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].UQ + (size_t)(pr[j].mq - b) * n; }));
+      cp.dst = ring.ptrs([&] {
+        std::vector<double*> v;
+        for (int q = 0; q < na; ++q) v.push_back(pd[act[q]].UQ + (size_t)nkp[q] * n);
+        return v;
+      }());
+      copy_launch(cp, na, b, st);
+      cp.ncol = ring.vec(nkp);
+      cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Xt; }));
+      cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].Q; }));
+      copy_launch(cp, na, kkeep_max, st);
+      cp.src = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Ut; }));
+      cp.dst = ring.ptrs(act_vec(act, [&](int j) { return pd[j].UQ; }));
+      copy_launch(cp, na, kkeep_max, st);
+      std::vector<double*> thp(na);
+      for (int q = 0; q < na; ++q) thp[q] = ring.vec(thk[q]);
+      TResetArgs tr;
+      tr.active = ring.vec(std::vector<int>(na, 1));
+      tr.T = ring.ptrs(act_vec(act, [&](int j) { return pd[j].T; }));
+      tr.ldt = QC;
+      tr.dim = QC;
+      tr.k = ring.vec(nkp);
+      tr.theta = ring.cptrs(thp);
+      treset_launch(tr, na, st);
+      for (int q = 0; q < na; ++q) {
+        auto& p = pr[act[q]];
+        p.nl += nlk[q];
+        p.mq = nkp[q] + b;
+      }
+      // probe activity from slice completion
+      std::vector<bool> done(P + 1);
+      for (int s = 0; s <= P; ++s) done[s] = slice_done(s);
+      for (int j = 0; j < P; ++j) {
+        pr[j].active = !(done[j] && done[j + 1]) && pr[j].nl < LC;
+        cycles_max = std::max(cycles_max, pr[j].cycles);
+      }
+    }
     SL_HIP(hipStreamSynchronize(st));
     ring.synced();
-    for (int q = 0; q < NC; ++q)
-      for (int i = 0; i < chunks[q].cnt; ++i) {
-        const int t = chunks[q].off + i;
-        vals[t] = ho[(size_t)q * kEigMax + i];
-        ress[t] = hr[t] / (anorm * std::sqrt(std::max(hx[t], 1e-300)));
+    t_lanczos = ms_since(t_l0);
+    // ---- 3. explicit Rayleigh-Ritz with A on the locked vectors, residuals
+    const auto t_r0 = Clock::now();
+    for (int j = 0; j < P; ++j) {
+      std::vector<int> ord(pr[j].nl);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return pr[j].lock_lam[x] < pr[j].lock_lam[y]; });
+      for (int s0 = 0; s0 < (int)ord.size(); s0 += kEigMax) {
+        Chunk ch;
+        ch.probe = j;
+        ch.off = NL;
+        ch.cnt = std::min<int>(kEigMax, (int)ord.size() - s0);
+        ch.cols.assign(ord.begin() + s0, ord.begin() + s0 + ch.cnt);
+        NL += ch.cnt;
+        chunks.push_back(std::move(ch));
       }
+    }
+    const int NC = (int)chunks.size();
+    vals.assign(NL, 0.0);
+    ress.assign(NL, 0.0);
+    double *Xa = nullptr, *AXa = nullptr, *BXa = nullptr, *AXf = nullptr, *BXf = nullptr,
+           *Hm = nullptr, *Om = nullptr, *Ym = nullptr, *rr = nullptr, *xn = nullptr;
+    constexpr int kRrMats = 6;  // G, its eigenvectors U, U w^{-1/2}, S = G^{-1/2}, S H, S H S
+    const size_t e2 = (size_t)kEigMax * kEigMax;
+    if (NL > 0) {
+      Sizer zr;
+      for (int q = 0; q < 6; ++q) zr.take<double>((size_t)n * NL);
+      zr.take<double>((size_t)NC * kEigMax * kEigMax);
+      zr.take<double>((size_t)NC * kEigMax);
+      zr.take<double>((size_t)NC * kEigMax * kEigMax);
+      zr.take<double>(NL);
+      zr.take<double>(NL);
+      zr.take<double>((size_t)NC * kRrMats * e2);
+      zr.take<double>((size_t)NC * kEigMax);
+      zr.take<double>((size_t)NC * e2);
+      Carver cr(ws_get(h, kBufEig, zr.off));
+      Xa = cr.take<double>((size_t)n * NL);
+      AXa = cr.take<double>((size_t)n * NL);
+      BXa = cr.take<double>((size_t)n * NL);
+      Xf = cr.take<double>((size_t)n * NL);
+      AXf = cr.take<double>((size_t)n * NL);
+      BXf = cr.take<double>((size_t)n * NL);
+      Hm = cr.take<double>((size_t)NC * kEigMax * kEigMax);
+      Om = cr.take<double>((size_t)NC * kEigMax);
+      Ym = cr.take<double>((size_t)NC * kEigMax * kEigMax);
+      rr = cr.take<double>(NL);
+      xn = cr.take<double>(NL);
+      double* Gm = cr.take<double>((size_t)NC * kRrMats * e2);
+      double* Gw = cr.take<double>((size_t)NC * kEigMax);
+      double* Y2 = cr.take<double>((size_t)NC * e2);
+      std::vector<int> cnts(NC), rowsn(NC, n);
+      std::vector<int*> idxp(NC);
+      for (int q = 0; q < NC; ++q) {
+        cnts[q] = chunks[q].cnt;
+        idxp[q] = ring.vec(chunks[q].cols);
+      }
+      SelectArgs sx;
+      sx.count = ring.vec(cnts);
+      sx.rows = ring.vec(rowsn);
+      sx.in = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return pd[ch.probe].L; }));
+      sx.ldi = n;
+      sx.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return Xa + (size_t)ch.off * n; }));
+      sx.ldo = n;
+      sx.idx = ring.cptrs(idxp);
+      select_launch(sx, NC, (long)n * kEigMax, st);
+      gemm(c, false, false, {n}, {NL}, {n}, {Af}, n, {Xa}, n, {AXa}, n, 1.0, 0.0);
+      gemm(c, false, false, {n}, {NL}, {n}, {Bf}, n, {Xa}, n, {BXa}, n, 1.0, 0.0);
+      auto cX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(Xa + (size_t)ch.off * n); });
+      auto cAX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(AXa + (size_t)ch.off * n); });
+      auto cBX = act_vec(chunks, [&](const Chunk& ch) { return (const double*)(BXa + (size_t)ch.off * n); });
+      std::vector<double*> pH(NC), pO(NC), pY(NC);
+      for (int q = 0; q < NC; ++q) {
+        pH[q] = Hm + (size_t)q * kEigMax * kEigMax;
+        pO[q] = Om + (size_t)q * kEigMax;
+        pY[q] = Ym + (size_t)q * kEigMax * kEigMax;
+      }
+      gemm(c, true, false, cnts, cnts, rowsn, cX, n, cAX, n, pH, kEigMax, 1.0, 0.0);
+      int cmax = 0;
+      for (int v : cnts) cmax = std::max(cmax, v);
+      // The locked vectors are B-orthonormal only up to the drift of many restart
+      // cycles (the deflation-locked ones in particular), and a standard
+      // Rayleigh-Ritz step would carry that drift into the residuals.  The
+      // symmetric orthonormalisation S = G^{-1/2} of G = X^T B X (from the
+      // eigenpairs of G, which is close to the identity) makes the step the exact
+      // generalized one: eig(S H S) = (Omega, Y), Ritz vectors X S Y.
+      std::vector<double*> pG(NC), pU(NC), pUs(NC), pS(NC), pT(NC), pH2(NC), pGw(NC), pY2(NC);
+      for (int q = 0; q < NC; ++q) {
+        double* g0 = Gm + (size_t)q * kRrMats * e2;
+        pG[q] = g0;
+        pU[q] = g0 + e2;
+        pUs[q] = g0 + 2 * e2;
+        pS[q] = g0 + 3 * e2;
+        pT[q] = g0 + 4 * e2;
+        pH2[q] = g0 + 5 * e2;
+        pGw[q] = Gw + (size_t)q * kEigMax;
+        pY2[q] = Y2 + (size_t)q * e2;
+      }
+      auto cc = [](const std::vector<double*>& v) { return std::vector<const double*>(v.begin(), v.end()); };
+      gemm(c, true, false, cnts, cnts, rowsn, cX, n, cBX, n, pG, kEigMax, 1.0, 0.0);
+      EigArgs eg;
+      eg.m = ring.vec(cnts);
+      eg.A = ring.cptrs(pG);
+      eg.lda = kEigMax;
+      eg.W = ring.ptrs(pGw);
+      eg.V = ring.ptrs(pU);
+      eg.ldv = kEigMax;
+      eig_launch(eg, NC, cmax, st);
+      for (int q = 0; q < NC; ++q)
+        scale_cols_launch(cnts[q], cnts[q], pGw[q], pU[q], kEigMax, pUs[q], kEigMax, nullptr, st);
+      gemm(c, false, true, cnts, cnts, cnts, cc(pUs), kEigMax, cc(pU), kEigMax, pS, kEigMax, 1.0, 0.0);
+      gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pH), kEigMax, pT, kEigMax, 1.0, 0.0);
+      gemm(c, false, false, cnts, cnts, cnts, cc(pT), kEigMax, cc(pS), kEigMax, pH2, kEigMax, 1.0, 0.0);
+      EigArgs e;
+      e.m = ring.vec(cnts);
+      e.A = ring.cptrs(pH2);
+      e.lda = kEigMax;
+      e.W = ring.ptrs(pO);
+      e.V = ring.ptrs(pY);
+      e.ldv = kEigMax;
+      eig_launch(e, NC, cmax, st);
+      gemm(c, false, false, cnts, cnts, cnts, cc(pS), kEigMax, cc(pY), kEigMax, pY2, kEigMax, 1.0, 0.0);
+      std::vector<const double*> cY(pY2.begin(), pY2.end());
+      gemm(c, false, false, rowsn, cnts, cnts, cX, n, cY, kEigMax,
+           act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+      gemm(c, false, false, rowsn, cnts, cnts, cAX, n, cY, kEigMax,
+           act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+      gemm(c, false, false, rowsn, cnts, cnts, cBX, n, cY, kEigMax,
+           act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }), n, 1.0, 0.0);
+      ColDotArgs r1;
+      r1.n = n;
+      r1.ncol = ring.vec(cnts);
+      r1.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return AXf + (size_t)ch.off * n; }));
+      r1.ldx = n;
+      r1.Y = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return BXf + (size_t)ch.off * n; }));
+      r1.ldy = n;
+      r1.w = ring.cptrs(pO);
+      r1.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return rr + ch.off; }));
+      r1.mode = 1;
+      r1.partial = static_cast<double*>(ws_get(h, kBufMisc, sizeof(double) * coldot_partial_size(n, NC, kEigMax)));
+      coldot_launch(r1, NC, cmax, st);
+      ColDotArgs r2 = r1;
+      r2.X = ring.cptrs(act_vec(chunks, [&](const Chunk& ch) { return Xf + (size_t)ch.off * n; }));
+      r2.Y = r2.X;
+      r2.ldy = n;
+      r2.out = ring.ptrs(act_vec(chunks, [&](const Chunk& ch) { return xn + ch.off; }));
+      r2.mode = 0;
+      coldot_launch(r2, NC, cmax, st);
+      std::vector<double> hr(NL), hx(NL), ho((size_t)NC * kEigMax);
+      SL_HIP(hipMemcpyAsync(hr.data(), rr, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipMemcpyAsync(hx.data(), xn, sizeof(double) * NL, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipMemcpyAsync(ho.data(), Om, sizeof(double) * NC * kEigMax, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipStreamSynchronize(st));
+      ring.synced();
+      for (int q = 0; q < NC; ++q)
+        for (int i = 0; i < chunks[q].cnt; ++i) {
+          const int t = chunks[q].off + i;
+          vals[t] = ho[(size_t)q * kEigMax + i];
+          ress[t] = hr[t] / (anorm * std::sqrt(std::max(hx[t], 1e-300)));
+        }
+    }
+    t_rr = ms_since(t_r0);
   }
-  const double t_rr = ms_since(t_r0);
-  // ---- 4. validation (host) and output
-  const auto t_h0 = Clock::now();
-  std::vector<int64_t> offs(P, 0), cnts(P, 0);
-  {
-    // probe j's values are the concatenation of its chunks
+  double flops_update = 0.0;
+  if (rep && o.profile) {
+    // algorithmic flops of the trailing updates from the panel starts of every shift
+    std::vector<int> ps((size_t)S1 * fp.npmax);
+    std::vector<FactorState> fs(S1);
+    SL_HIP(hipMemcpy(ps.data(), fp.pstart_base, sizeof(int) * ps.size(), hipMemcpyDeviceToHost));
+    SL_HIP(hipMemcpy(fs.data(), fp.d_state, sizeof(FactorState) * S1, hipMemcpyDeviceToHost));
+    for (int s = 0; s < S1; ++s) {
+      const int np = fs[s].npanel;
+      for (int q = 0; q < np; ++q) {
+        const int k0 = ps[(size_t)s * fp.npmax + q];
+        const int k1 = q + 1 < np ? ps[(size_t)s * fp.npmax + q + 1] : n;
+        const double m = (double)(n - k1);
+        flops_update += m * (m + 1.0) * (double)(k1 - k0);
+      }
+    }
+  }
+  // ---- 3b. missing eigenvalues (Sec. 3.3).  When a slice holds more eigenvalues
+  // than validated candidates, a density-of-states estimate (KPM) places new
+  // shifts at equal-count points inside that slice, about one per n_e / n_s
+  // eigenvalues; only the new probes run (the paper's subspace iteration, each
+  // on the window between its neighbours in the merged shift set), their Ritz
+  // pairs join the others and every slice is validated again.
+  // psig/pnu: the shifts of all probes (inserted ones included) and their
+  // inertias; origin: the original probe toward which a probe's values count
+  // (an inserted probe: the nearer of the two shifts bounding its slice).
+  std::vector<double> psig(sig);
+  std::vector<int64_t> pnu(nu);
+  std::vector<int> origin(P);
+  std::iota(origin.begin(), origin.end(), 0);
+  int n_inserted = 0, n_rounds = 0;
+  DevBuf merged_x, merged_tmp;
+  // probe m's values as one contiguous range [offs[m], offs[m] + cnts[m])
+  auto probe_ranges = [&](int PP, std::vector<int64_t>& offs, std::vector<int64_t>& cnts) {
+    offs.assign(PP, 0);
+    cnts.assign(PP, 0);
     for (const auto& ch : chunks) cnts[ch.probe] += ch.cnt;
     int64_t acc = 0;
-    for (int j = 0; j < P; ++j) {
+    for (int j = 0; j < PP; ++j) {
       offs[j] = acc;
       acc += cnts[j];
     }
+  };
+  {
+    std::vector<double> kmu;
+    double ka = 0.0, kb = 0.0;
+    std::vector<double> kg;
+    for (int round = 0; round < o.max_recovery; ++round) {
+      const int PP = (int)psig.size();
+      std::vector<int64_t> offs, cnts;
+      probe_ranges(PP, offs, cnts);
+      std::vector<int32_t> sc(PP + 1), se(PP + 1), sd(PP + 1), ch0(std::max(NL, 1), 0);
+      validate(PP, psig.data(), pnu.data(), top, nu_top, offs.data(), cnts.data(), vals.data(),
+               ress.data(), sc.data(), se.data(), sd.data(), ch0.data());
+      std::vector<int> miss;
+      for (int s = 0; s <= PP; ++s)
+        if (sc[s] == 1) miss.push_back(s);
+      if (miss.empty()) break;
+      // the probes' Ritz vectors leave the workspaces that the next steps reuse
+      merged_tmp.alloc(sizeof(double) * (size_t)n * std::max(NL, 1));
+      double* xold = static_cast<double*>(merged_tmp.p);
+      SL_HIP(hipMemcpyAsync(xold, Xf, sizeof(double) * (size_t)n * NL, hipMemcpyDeviceToDevice, st));
+      if (kmu.empty()) {
+        kmu.assign(o.kpm_moments, 0.0);
+        std::vector<double> s_tmp(n_s);
+        double t_tmp = 0.0, bnd[2];
+        const sislice_status ps = plan_impl(h, n, A, lda, B, ldb, n_e, n_s, o, s_tmp.data(), &t_tmp,
+                                            kmu.data(), bnd);
+        SL_CHECK_ARG(ps == SISLICE_OK, "density-of-states estimate for probe insertion failed");
+        ka = bnd[0];
+        kb = bnd[1];
+        kg.assign(o.kpm_moments, 0.0);
+        jackson(o.kpm_moments, kg.data());
+      }
+      auto Phi = [&](double w) { return kpm_cdos(kmu.data(), kg.data(), o.kpm_moments, ka, kb, n, w); };
+      const double K = std::max(1.0, (double)n_e / (double)n_s);
+      std::vector<double> newpts;
+      for (int s : miss) {
+        const double l = s == 0 ? std::min(ka, psig[0] - (psig.size() > 1 ? psig[1] - psig[0] : 1.0))
+                                : psig[s - 1];
+        const double u = s == PP ? top : psig[s];
+        const int q = std::max(1, (int)std::ceil((double)se[s] / K));
+        const double fl = Phi(l), fu = Phi(u);
+        for (int t = 1; t <= q; ++t) {
+          double w;
+          if (fu - fl > 1e-8) {
+            const double target = fl + t * (fu - fl) / (q + 1);
+            double lo = l, hi = u;
+            for (int it = 0; it < 100; ++it) {
+              const double mid = 0.5 * (lo + hi);
+              (Phi(mid) < target ? lo : hi) = mid;
+            }
+            w = 0.5 * (lo + hi);
+          } else {
+            w = l + t * (u - l) / (q + 1);  // the estimate sees nothing here: equal spacing
+          }
+          const double gap = 1e-9 * (std::fabs(u) + std::fabs(l) + 1.0);
+          if (w > l + gap && w < u - gap) newpts.push_back(w);
+        }
+      }
+      std::sort(newpts.begin(), newpts.end());
+      newpts.erase(std::unique(newpts.begin(), newpts.end()), newpts.end());
+      if (newpts.empty()) break;
+      const int Pn = (int)newpts.size();
+      // factor the new shifts (storage for LD, ipiv and the solve preparation)
+      const size_t per = Carver::round(sizeof(double) * (size_t)n * n) + Carver::round(sizeof(int32_t) * n) +
+                         2 * Carver::round(sizeof(int) * n) + Carver::round(sizeof(double) * solve_linv_size(n));
+      DevBuf fac;
+      fac.alloc(per * Pn + 256);
+      Carver cf(fac.p);
+      std::vector<double*> nLD(Pn), nLinv(Pn);
+      std::vector<int32_t*> nip(Pn);
+      std::vector<int*> nperm(Pn), nblk(Pn);
+      for (int i = 0; i < Pn; ++i) {
+        nLD[i] = cf.take<double>((size_t)n * n);
+        nip[i] = cf.take<int32_t>(n);
+        nperm[i] = cf.take<int>(n);
+        nblk[i] = cf.take<int>(n);
+        nLinv[i] = cf.take<double>(solve_linv_size(n));
+      }
+      const int nbf = o.nb > 0 ? std::min(o.nb, kMaxNb) : default_nb(n);
+      FactorPlan f = build_factor(h, kBufFactor, n, A, lda, B, ldb, Pn, newpts.data(), nLD.data(), n,
+                                  nip.data(), nbf, true);
+      factor_launch(f, st);
+      std::vector<int64_t> ni(3 * Pn);
+      SL_HIP(hipMemcpyAsync(ni.data(), f.d_inertia, sizeof(int64_t) * 3 * Pn, hipMemcpyDeviceToHost, st));
+      SL_HIP(hipStreamSynchronize(st));
+      ring.synced();
+      solve_prep_launch(n, Pn, reinterpret_cast<const int* const*>(ring.ptrs(nip)), ring.ptrs(nperm),
+                        ring.ptrs(nblk), ring.cptrs(nLD), n, ring.ptrs(nLinv), st);
+      // the merged shift set and the windows of the new probes in it
+      std::vector<std::pair<double, int>> all;  // (shift, index: < PP old probe, else PP + new)
+      for (int m = 0; m < PP; ++m) all.push_back({psig[m], m});
+      for (int i = 0; i < Pn; ++i)
+        if (ni[3 * i + 1] == 0) all.push_back({newpts[i], PP + i});  // an exact zero pivot: dropped
+      std::sort(all.begin(), all.end());
+      const int PM = (int)all.size();
+      std::vector<int64_t> mnu(PM);
+      std::vector<double> msig(PM);
+      for (int m = 0; m < PM; ++m) {
+        msig[m] = all[m].first;
+        mnu[m] = all[m].second < PP ? pnu[all[m].second] : ni[3 * (all[m].second - PP)];
+      }
+      std::vector<SubspaceProbe> sp;
+      std::vector<int> sp_at;  // merged index of each new probe
+      int64_t max_need = 0;
+      for (int m = 0; m < PM; ++m) {
+        if (all[m].second < PP) continue;
+        const int i = all[m].second - PP;
+        SubspaceProbe q;
+        q.sigma = msig[m];
+        q.lo = m > 0 ? msig[m - 1] : -std::numeric_limits<double>::infinity();
+        q.hi = m + 1 < PM ? msig[m + 1] : top;
+        q.need = (m + 1 < PM ? mnu[m + 1] : nu_top) - (m > 0 ? mnu[m - 1] : 0);
+        q.LD = nLD[i];
+        q.perm = nperm[i];
+        q.blk = nblk[i];
+        q.Linv = nLinv[i];
+        max_need = std::max(max_need, q.need);
+        sp.push_back(q);
+        sp_at.push_back(m);
+      }
+      if (sp.empty()) break;
+      const int kr = std::min(subspace_dim(max_need), n);
+      const auto t_i0 = Clock::now();
+      SubspaceOut so = subspace_probes(c, n, Af, Bf, sp, anorm, o, kr, o.subspace_iters, nullptr, 0, 0, n);
+      t_lanczos += ms_since(t_i0);
+      block_steps += so.applications;
+      cycles_max = std::max(cycles_max, so.rounds_max);
+      bytes_solve += so.bytes_solve;
+      // merge: every probe's values contiguous, in merged shift order
+      std::vector<int> src_new(PM, -1);  // new probe -> its position in sp
+      for (size_t q = 0; q < sp_at.size(); ++q) src_new[sp_at[q]] = (int)q;
+      std::vector<Chunk> mchunks;
+      std::vector<double> mvals, mress;
+      std::vector<const double*> csrc;
+      std::vector<int> ccnt;
+      std::vector<int64_t> coff;
+      int mNL = 0;
+      std::vector<int> morigin(PM);
+      for (int m = 0; m < PM; ++m) {
+        const int id = all[m].second;
+        int cnt;
+        if (id < PP) {
+          cnt = (int)cnts[id];
+          csrc.push_back(xold + (size_t)offs[id] * n);
+          for (int t = 0; t < cnt; ++t) {
+            mvals.push_back(vals[offs[id] + t]);
+            mress.push_back(ress[offs[id] + t]);
+          }
+          morigin[m] = origin[id];
+        } else {
+          const int q = src_new[m];
+          cnt = kr;
+          csrc.push_back(so.X + (size_t)q * n * kr);
+          for (int t = 0; t < kr; ++t) {
+            mvals.push_back(so.vals[(size_t)q * kr + t]);
+            mress.push_back(so.ress[(size_t)q * kr + t]);
+          }
+          // the original probe nearer to this shift among those bounding its slice
+          int lo_o = -1, hi_o = -1;
+          for (int mm = m - 1; mm >= 0; --mm)
+            if (all[mm].second < PP) {
+              lo_o = origin[all[mm].second];
+              break;
+            }
+          for (int mm = m + 1; mm < PM; ++mm)
+            if (all[mm].second < PP) {
+              hi_o = origin[all[mm].second];
+              break;
+            }
+          if (lo_o < 0) morigin[m] = hi_o;
+          else if (hi_o < 0) morigin[m] = lo_o;
+          else morigin[m] = std::fabs(msig[m] - sig[lo_o]) <= std::fabs(sig[hi_o] - msig[m]) ? lo_o : hi_o;
+        }
+        Chunk chm;
+        chm.probe = m;
+        chm.off = mNL;
+        chm.cnt = cnt;
+        mchunks.push_back(chm);
+        ccnt.push_back(cnt);
+        coff.push_back(mNL);
+        mNL += cnt;
+      }
+      merged_x.alloc(sizeof(double) * (size_t)n * std::max(mNL, 1));
+      double* xm = static_cast<double*>(merged_x.p);
+      {
+        std::vector<double*> dst(PM);
+        int cmax = 0;
+        for (int m = 0; m < PM; ++m) {
+          dst[m] = xm + (size_t)coff[m] * n;
+          cmax = std::max(cmax, ccnt[m]);
+        }
+        CopyArgs cp;
+        cp.n = n;
+        cp.ncol = ring.vec(ccnt);
+        cp.src = ring.cptrs(csrc);
+        cp.lds = n;
+        cp.dst = ring.ptrs(dst);
+        cp.ldd = n;
+        if (cmax > 0) copy_launch(cp, PM, cmax, st);
+      }
+      SL_HIP(hipStreamSynchronize(st));
+      ring.synced();
+      merged_tmp.release();
+      chunks = std::move(mchunks);
+      vals = std::move(mvals);
+      ress = std::move(mress);
+      NL = mNL;
+      Xf = xm;
+      psig = msig;
+      pnu = mnu;
+      origin = morigin;
+      n_inserted += (int)sp.size();
+      ++n_rounds;
+      if (rep) rep->factor_id = 0;  // the cached factorizations no longer match the probes
+    }
   }
-  std::vector<int32_t> scase(P + 1), sexact(P + 1), scand(P + 1), chosen(std::max(NL, 1), 0);
-  const int64_t nval = validate(P, sig.data(), nu.data(), top, nu_top, offs.data(), cnts.data(),
+  // ---- 4. validation (host) and output
+  const auto t_h0 = Clock::now();
+  const int PP = (int)psig.size();
+  std::vector<int64_t> offs, cnts;
+  probe_ranges(PP, offs, cnts);
+  std::vector<int32_t> scase(PP + 1), sexact(PP + 1), scand(PP + 1), chosen(std::max(NL, 1), 0);
+  const int64_t nval = validate(PP, psig.data(), pnu.data(), top, nu_top, offs.data(), cnts.data(),
                                 vals.data(), ress.data(), scase.data(), sexact.data(), scand.data(),
                                 chosen.data());
   // A value is taken from the probe whose shift is nearer, but both probes of a
@@ -1292,7 +1594,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   // refused when any other chosen value lies that close (a near-degenerate pair
   // must keep two distinct vectors).
   {
-    const double dmatch = 1e-9 * std::max(1.0, std::fabs(top) + std::fabs(sig[0]));
+    const double dmatch = 1e-9 * std::max(1.0, std::fabs(top) + std::fabs(psig[0]));
     std::vector<int> cidx;
     for (int t = 0; t < NL; ++t)
       if (chosen[t]) cidx.push_back(t);
@@ -1324,7 +1626,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   const int nout = (int)std::min<int64_t>(n_e, (int64_t)pick.size());
   int64_t nconv = 0;
   bool missing = nval < n_e || (int64_t)pick.size() < n_e;
-  for (int s = 0; s <= P; ++s) missing |= scase[s] == 1;
+  for (int s = 0; s <= PP; ++s) missing |= scase[s] == 1;
   if (nout > 0) {
     std::vector<const double*> src(nout);
     std::vector<int> scol(nout);
@@ -1338,7 +1640,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       v[q] = vals[pick[q]];
       r[q] = ress[pick[q]];
       nconv += r[q] <= o.tol;
-      if (probe_of) probe_of[q] = val_probe[pick[q]];
+      if (probe_of) probe_of[q] = origin[val_probe[pick[q]]];
     }
     GatherArgs g;
     g.n = n;
@@ -1362,22 +1664,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       rep->n_kern[q] = 0;
     }
     prof_collect(h, rep->t_kern_ms, rep->n_kern);
-    // algorithmic flops of the trailing updates from the panel starts of every shift
-    std::vector<int> ps((size_t)S1 * fp.npmax);
-    std::vector<FactorState> fs(S1);
-    SL_HIP(hipMemcpy(ps.data(), fp.pstart_base, sizeof(int) * ps.size(), hipMemcpyDeviceToHost));
-    SL_HIP(hipMemcpy(fs.data(), fp.d_state, sizeof(FactorState) * S1, hipMemcpyDeviceToHost));
-    double fl = 0.0;
-    for (int s = 0; s < S1; ++s) {
-      const int np = fs[s].npanel;
-      for (int q = 0; q < np; ++q) {
-        const int k0 = ps[(size_t)s * fp.npmax + q];
-        const int k1 = q + 1 < np ? ps[(size_t)s * fp.npmax + q + 1] : n;
-        const double m = (double)(n - k1);
-        fl += m * (m + 1.0) * (double)(k1 - k0);
-      }
-    }
-    rep->flops_update = fl;
+    rep->flops_update = flops_update;
     rep->bytes_solve = bytes_solve;
   }
   prof_reset(h);
@@ -1393,12 +1680,26 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     rep->t_host_ms = t_host;
     rep->t_total_ms = ms_since(t_start);
     (void)t_plan;
+    rep->probes_inserted = n_inserted;
+    rep->recovery_rounds = n_rounds;
+    // slices of the caller's shifts: a slice split by inserted probes reports the
+    // sums of its parts, and case 1 (missing) or else 2 (trimmed) if any part has it
+    std::vector<int32_t> oc(P + 1, 0), oe(P + 1, 0), od(P + 1, 0);
+    for (int t = 0; t <= PP; ++t) {
+      int s = 0;
+      if (t > 0)
+        while (s < P && sig[s] <= psig[t - 1]) ++s;
+      oe[s] += sexact[t];
+      od[s] += scand[t];
+      if (scase[t] == 1) oc[s] = 1;
+      else if (scase[t] == 2 && oc[s] == 0) oc[s] = 2;
+    }
     if (rep->slice_case)
-      for (int s = 0; s <= P; ++s) rep->slice_case[s] = scase[s];
+      for (int s = 0; s <= P; ++s) rep->slice_case[s] = oc[s];
     if (rep->slice_exact)
-      for (int s = 0; s <= P; ++s) rep->slice_exact[s] = sexact[s];
+      for (int s = 0; s <= P; ++s) rep->slice_exact[s] = oe[s];
     if (rep->slice_cand)
-      for (int s = 0; s <= P; ++s) rep->slice_cand[s] = scand[s];
+      for (int s = 0; s <= P; ++s) rep->slice_cand[s] = od[s];
   }
   if (missing) return SISLICE_MISSING_EIGS;
   if (nconv < n_e) return SISLICE_NOT_CONVERGED;
@@ -1475,6 +1776,60 @@ sislice_status sislice_solve(sislice_handle* h, int64_t n, const double* A, int6
                                          evals, evecs, ldx, resid, report, nullptr, nullptr);
     check_waits(h);
     return st;
+  } catch (const Error& e) {
+    std::fprintf(stderr, "sislice: %s\n", e.what());
+    return e.status;
+  }
+}
+
+sislice_status sislice_sisubit(sislice_handle* h, int64_t n, const double* A, int64_t lda,
+                               const double* B, int64_t ldb, double sigma, int64_t k,
+                               const double* V0, int64_t ldv, int32_t M, double* evals, double* X,
+                               int64_t ldx, double* resid) {
+  try {
+    check_handle(h);
+    SL_CHECK_ARG(n >= 32 && n <= 20000, "n must be in [32, 20000]");
+    SL_CHECK_ARG(k >= 1 && k <= kEigMax && k <= n, "k must be in [1, min(112, n)]");
+    SL_CHECK_ARG(M >= 1 && M <= 64, "M must be in [1, 64]");
+    SL_CHECK_ARG(A && B && lda >= n && ldb >= n, "bad matrix argument");
+    SL_CHECK_ARG(V0 && ldv >= n && evals && X && ldx >= n && resid, "bad vector argument");
+    const int nn = (int)n, kk = (int)k;
+    hipStream_t st = h->stream;
+    set_current_handle(h);
+    Ring ring(h);
+    Ctx c{h, st, &ring};
+    // the algorithm's second step: the LDL^T of A - sigma B (kept in the handle's
+    // factor cache like the solve's)
+    DriverWs dw = driver_factor(h, ring, nn, A, lda, B, ldb, {sigma}, default_nb(nn));
+    if (dw.inert[1] != 0) return SISLICE_SINGULAR_SHIFT;
+    solve_prep_launch(nn, 1, reinterpret_cast<const int* const*>(ring.ptrs(std::vector<int32_t*>{dw.ipv[0]})),
+                      ring.ptrs(std::vector<int*>{dw.perm[0]}), ring.ptrs(std::vector<int*>{dw.blk[0]}),
+                      ring.cptrs(std::vector<double*>{dw.LD[0]}), nn,
+                      ring.ptrs(std::vector<double*>{dw.Linv[0]}), st);
+    h->fc.prepped[0] = 1;
+    std::vector<int> one{1};
+    const double anorm = sym_norm2(c, nn, dw.Af, dw.nX, dw.nX + (size_t)nn * 8, dw.nsmall,
+                                   dw.nsmall + 64, dw.nsmall + 128, dw.nsmall + 192,
+                                   dw.nsmall + 256, dw.nflag, ring.vec(one), 0);
+    SubspaceProbe p;
+    p.sigma = sigma;
+    p.lo = -std::numeric_limits<double>::infinity();
+    p.hi = std::numeric_limits<double>::infinity();
+    p.LD = dw.LD[0];
+    p.perm = dw.perm[0];
+    p.blk = dw.blk[0];
+    p.Linv = dw.Linv[0];
+    sislice_opts o;
+    sislice_default_opts(&o);
+    SubspaceOut so = subspace_probes(c, nn, dw.Af, dw.Bf, {p}, anorm, o, kk, M, V0, kk, 1, ldv);
+    SL_HIP(hipMemcpyAsync(evals, so.vals.data(), sizeof(double) * kk, hipMemcpyHostToDevice, st));
+    SL_HIP(hipMemcpyAsync(resid, so.ress.data(), sizeof(double) * kk, hipMemcpyHostToDevice, st));
+    SL_HIP(hipMemcpy2DAsync(X, sizeof(double) * ldx, so.X, sizeof(double) * nn, sizeof(double) * nn,
+                            kk, hipMemcpyDeviceToDevice, st));
+    SL_HIP(hipStreamSynchronize(st));
+    ring.synced();
+    check_waits(h);
+    return SISLICE_OK;
   } catch (const Error& e) {
     std::fprintf(stderr, "sislice: %s\n", e.what());
     return e.status;

@@ -252,6 +252,10 @@ void sislice_default_opts(sislice_opts* o) {
   o->top_margin = 2.0;
   o->seed = 0;
   o->profile = 0;
+  o->driver = 0;
+  o->subspace_iters = 4;
+  o->max_recovery = 2;
+  o->reserved = 0;
 }
 
 const char* sislice_status_string(sislice_status s) {

@@ -27,7 +27,9 @@
 #include "driver_util.hpp"
 #include "handle.hpp"
 #include "lanczos.hpp"
+#include "eig.hpp"
 #include "planner.hpp"
+#include "sisubit.hpp"
 
 struct sislice_scf {
   sislice_handle* h = nullptr;
@@ -84,13 +86,14 @@ double partial_trace(sislice_scf* s, Ctx& c, const double* A, long lda) {
   return t;
 }
 
-// Warm-start blocks of the migrated probes (ascending shift order).  A probe must
+// Warm-start blocks of the migrated probes (ascending shift order), `b` columns
+// each (the Lanczos block, or the subspace iteration's basis).  A probe must
 // lock every eigenvalue of its window (sigma_{j-1}, sigma_{j+1}) (the lower probe
 // of each slice takes its values up to tau), so it starts from the previous
 // eigenvectors of all the previous values inside that window, not only those of
-// the cluster that moved it.
-void build_starts(sislice_scf* s, Ctx& c, const ScfMigration& mg) {
-  const int n = s->n, b = kLanczosBlock, P = (int)mg.shifts.size();
+// the cluster that moved it.  Returns the largest number of such values.
+int build_starts(sislice_scf* s, Ctx& c, const ScfMigration& mg, int b) {
+  const int n = s->n, P = (int)mg.shifts.size();
   std::vector<std::vector<int>> mem(P);
   for (int r = 0; r < P; ++r) {
     const double lo = r > 0 ? mg.shifts[r - 1] : -1e300;
@@ -154,6 +157,9 @@ void build_starts(sislice_scf* s, Ctx& c, const ScfMigration& mg) {
       gemm(c, false, false, {gm[q]}, {gn[q]}, {gk[q]}, {ga[q]}, n, {G + coff[q]}, gk[q], {gc[q]}, n,
            1.0, 0.0);
   }
+  int most = 0;
+  for (int r = 0; r < P; ++r) most = std::max(most, cnt[r]);
+  return most;
 }
 
 }  // namespace
@@ -196,7 +202,8 @@ sislice_status sislice_scf_create(sislice_handle* h, int64_t n, int64_t n_e, int
       alloc(&s->prev_X, nn * n_e);
       alloc(&s->Afull, nn * nn);
       alloc(&s->AX, nn * n_e);
-      alloc(&s->start, nn * kLanczosBlock * n_s);
+      // start blocks: the Lanczos block, or up to kEigMax columns of a subspace basis
+      alloc(&s->start, nn * (s->o.driver == 1 ? kEigMax : kLanczosBlock) * n_s);
       alloc(&s->Xg, nn * 3 * n_e);
       alloc(&s->dots, (size_t)n_e);
     } catch (...) {
@@ -238,6 +245,7 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
     r.step = s->step;
     bool dos = !s->have_prev;
     const double* start = nullptr;
+    int start_cols = kLanczosBlock;
     {
       Ring ring(h);
       Ctx c{h, h->stream, &ring};
@@ -268,7 +276,10 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
           r.deleted = mg.deleted;
           r.inserted = mg.inserted;
           s->shifts = mg.shifts;
-          build_starts(s, c, mg);
+          // Algorithm 2 is seeded with the previous eigenvectors themselves
+          // (Sec. 2.1): up to kEigMax leading columns of each probe's basis
+          start_cols = s->o.driver == 1 ? kEigMax : kLanczosBlock;
+          build_starts(s, c, mg, start_cols);
           start = s->start;
           // The top boundary of a warm step sits two local spacings above the
           // previous n_e-th value: the planner's boundary holds a margin of values
@@ -301,10 +312,11 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
       std::memset(&sr, 0, sizeof(sr));
       const auto ts = Clock::now();
       st = solve_impl(h, n, A, lda, B, ldb, n_e, n_s, s->shifts.data(), &s->top, s->o, evals, evecs,
-                      ldx, resid, &sr, start, probe_of.data());
+                      ldx, resid, &sr, start, probe_of.data(), start_cols);
       r.t_solve_ms += ms_since(ts);
       r.block_steps += sr.block_steps;
       r.cycles_max = std::max(r.cycles_max, sr.cycles_max);
+      r.probes_inserted += sr.probes_inserted;
       if ((st == SISLICE_MISSING_EIGS || st == SISLICE_SINGULAR_SHIFT) && !dos) {
         dos = true;  // the migrated shifts missed eigenvalues: repeat with DOS shifts
         r.replanned = 2;

@@ -54,21 +54,53 @@ def test_sequence_migrates_and_warm_starts(gpu_lib):
     seq.close()
 
 
+def test_sequence_with_subspace_iteration_warm_starts(gpu_lib):
+    """The paper's own driver: Algorithm 2 seeded with the previous eigenvectors
+    (Sec. 2.1) needs fewer shift-invert applications than the cold first step."""
+    api = gpu_lib
+    n, n_e, n_s = 600, 60, 6
+    P = inputs.pencil_scf(n, n_e, seed=33)
+    A = P.A.copy()
+    B = dev(P.B)
+    seq = api.ScfSequence(n, n_e, n_s, opts=api.default_opts(driver=1))
+    steps = []
+    for k in range(3):
+        if k > 0:
+            A = A + inputs.sym_perturbation(n, 200 + k, 1e-3)
+        print(f"scf subspace step {k}", flush=True)
+        out = seq.step(dev(A), B)
+        check_step(out, A, P.B, n_e)
+        steps.append(out["report"])
+    assert steps[0]["replanned"] == 1
+    for r in steps[1:]:
+        assert r["replanned"] == 0
+        assert r["block_steps"] < steps[0]["block_steps"]
+    seq.close()
+
+
 def test_trace_monitor_and_missing_eigenvalue_fallback(gpu_lib):
     # A + c B moves every eigenvalue by c: the partial trace jumps by n_e c, which
     # sends the step to the DOS planner; with the monitor disabled, the migrated
     # shifts miss eigenvalues and the step is repeated with DOS shifts
+    # with probe insertion switched off (max_recovery = 0).  With it on, the
+    # slices that miss eigenvalues first receive new probes (Sec. 3.3); here that
+    # cannot suffice, because A + c B keeps every eigenvector: the warm-start
+    # blocks are invariant subspaces of the new pencil, so several Lanczos probes
+    # break down without converging, and the step still ends with DOS shifts
     api = gpu_lib
     n, n_e, n_s = 500, 50, 5
     P = inputs.pencil_scf(n, n_e, seed=32)
     B = dev(P.B)
-    for eta_tol, expect in ((0.05, 1), (1e9, 2)):
-        seq = api.ScfSequence(n, n_e, n_s, eta_tol=eta_tol)
+    for eta_tol, rec, expect in ((0.05, 2, 1), (1e9, 0, 2), (1e9, 2, 2)):
+        print(f"monitor/fallback: eta_tol={eta_tol} max_recovery={rec}", flush=True)
+        seq = api.ScfSequence(n, n_e, n_s, opts=api.default_opts(max_recovery=rec), eta_tol=eta_tol)
         seq.step(dev(P.A), B)
         A1 = P.A + 1.0 * P.B
         out = seq.step(dev(A1), B)
         check_step(out, A1, P.B, n_e)
-        assert out["report"]["replanned"] == expect, out["report"]
+        r = out["report"]
+        assert r["replanned"] == expect, r
+        assert (r["probes_inserted"] > 0) == (eta_tol > 1 and rec > 0), r
         seq.close()
 
 
