@@ -213,26 +213,59 @@ def batched_leg(api, inputs, torch, workers=8, reps=2):
         conv_plain += int(o["report"]["n_converged"]) if o["status"] in (0, 2) else 0
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    _, rep0 = api.solve_batched(pens, opts=opts, workers=workers, check=False)  # tunes
-    best = None
-    for _ in range(reps):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        outs, rep = api.solve_batched(pens, opts=opts, workers=workers, check=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if best is None or dt < best[0]:
-            best = (dt, rep)
-    dt, rep = best
+    _, rep0 = api.solve_batched(pens, opts=opts, workers=workers, check=False)  # tunes, captures
+    _, _ = api.solve_batched(pens, opts=api.default_opts(graphs=0), workers=workers, check=False)
+
+    def timed(o):
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            outs, rep = api.solve_batched(pens, opts=o, workers=workers, check=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, rep)
+        return best
+
+    dt, rep = timed(opts)
+    dt_ng, rep_ng = timed(api.default_opts(graphs=0))
     return {
         "workload": f"batched: {len(sizes)} pencils, N = 512 + 256 U{{0..10}} (sum N = {sum(sizes)}), "
                     f"n_e = N/10, 8 KPM shifts each, SCF-shaped spectra",
         "value": rep["n_converged"] / dt, "plain_value": conv_plain / t_plain, "unit": "eigenpairs/s",
         "ratio_vs_plain": (rep["n_converged"] / dt) / (conv_plain / t_plain),
         "ms_batched": 1e3 * dt, "ms_plain_loop": 1e3 * t_plain, "workers": rep["workers"],
+        "graph_replays": rep["graph_replays"],
+        "no_graphs": {"value": rep_ng["n_converged"] / dt_ng, "ms_batched": 1e3 * dt_ng},
         "pencils_ok": rep["n_ok"], "tune_ms_first_call": rep0["t_tune_ms"],
-        "tuned_nb": {str(n): api.tuned_nb(n) for n in sorted(set(sizes))},
+        "graphs_built_first_call": rep0["graphs_built"],
+        "tuned": {str(n): api.tuned_factor(n) for n in sorted(set(sizes))},
     }
+
+
+def driver_leg(api, torch, A, B, n_e, n_s, steps=2):
+    """The plain workload with the paper's per-probe iteration (Algorithm 2, shift-invert
+    subspace iteration, opts.driver = 1) in place of block Lanczos: same KPM shifts."""
+    opts = api.default_opts(driver=1)
+    plan = api.plan_shifts_kpm(A, B, n_e, n_s, opts)
+    api.solve(A, B, n_e, n_s, sigmas=plan["sigmas"], omega_top=plan["omega_top"], opts=opts, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    conv = 0
+    rep = None
+    for _ in range(steps):
+        plan = api.plan_shifts_kpm(A, B, n_e, n_s, opts)
+        o = api.solve(A, B, n_e, n_s, sigmas=plan["sigmas"], omega_top=plan["omega_top"], opts=opts,
+                      check=False)
+        conv += int(o["report"]["n_converged"]) if o["status"] in (0, 2) else 0
+        rep = o["report"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"value": conv / dt, "unit": "eigenpairs/s", "ms_per_step": 1e3 * dt / steps,
+            "status": o["status"], "rounds_max": int(rep["cycles_max"]),
+            "applications": int(rep["block_steps"]),
+            "ms_iteration": float(rep["t_lanczos_ms"]), "ms_factor": float(rep["t_factor_ms"])}
 
 
 def planner_leg(api, A, B, n_e, n_s, reps=2):
@@ -267,7 +300,7 @@ def planner_leg(api, A, B, n_e, n_s, reps=2):
     return out
 
 
-def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10):
+def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10, driver=0, gradient=True):
     """SCF-shaped sequence A_k = A_{k-1} + E_k (||E_k||_2 = 1e-3, B fixed; the spectrum with
     a gap of 0.05 above lambda_{n_e} so that the density loss is defined): every step
     solved by the SCF driver (migrated shifts, warm starts) with the gradient of
@@ -276,7 +309,7 @@ def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10):
     A, B, _ = inputs.make_pencil_device(
         n, lambda r, m: inputs.spectrum_scf(r, m, n_e, forced_gap_at=n_e, forced_gap=0.05), 0, "cuda")
     W = inputs.sym_gaussian_device(n, 77, "cuda")
-    seq = api.ScfSequence(n, n_e, n_s)
+    seq = api.ScfSequence(n, n_e, n_s, opts=api.default_opts(driver=driver))
     recs = []
     t_all = 0.0
     conv_all = 0
@@ -289,8 +322,12 @@ def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         lam, X = out["evals"], out["evecs"]
-        GA, GB, rep = api.adjoint(A, B, lam, X, 2.0 * lam, 2.0 * (W @ X), out["sigmas"],
-                                  out["omega_top"], out["report"]["factor_id"], check=False)
+        if gradient:
+            GA, GB, rep = api.adjoint(A, B, lam, X, 2.0 * lam, 2.0 * (W @ X), out["sigmas"],
+                                      out["omega_top"], out["report"]["factor_id"], check=False)
+        else:
+            GA = GB = None
+            rep = {"status": None, "iterations": 0}
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         # pairs that meet the tolerance, as the plain metric counts them
@@ -312,8 +349,9 @@ def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10):
     warm = [x["ms_solve"] for x in recs[1:] if x["replanned"] == 0]
     return {
         "workload": f"SCF sequence: {steps} pencils N={n}, n_e={n_e}, {n_s} shifts, ||E_k||_2=1e-3, "
-                    f"per-step gradient of sum lam^2 + tr(W X X^T)",
-        "value": conv_all / t_all, "unit": "eigenpairs/s (with gradients)",
+                    f"per-step gradient of sum lam^2 + tr(W X X^T); per-probe iteration: "
+                    + ("block Lanczos" if driver == 0 else "subspace iteration (Algorithm 2), M=4"),
+        "value": conv_all / t_all, "unit": "eigenpairs/s" + (" (with gradients)" if gradient else ""),
         "plain_step_ms": recs[0]["ms_solve"],
         "warm_step_ms_mean": float(np.mean(warm)) if warm else None,
         "steps": recs,
@@ -440,9 +478,12 @@ def main():
         line["batched"] = batched_leg(api, inputs, torch)
     if not args.no_planners:
         line["planners"] = planner_leg(api, A, B, n_e, n_s)
+        line["subspace_driver"] = driver_leg(api, torch, A, B, n_e, n_s)
     if not args.no_scf:
         ns = max(8, 48 * args.scf_n // 12288)
         line["scf"] = scf_leg(api, inputs, torch, n=args.scf_n, n_e=args.scf_n * 1200 // 12288, n_s=ns)
+        line["scf_subspace"] = scf_leg(api, inputs, torch, n=args.scf_n, n_e=args.scf_n * 1200 // 12288,
+                                       n_s=ns, steps=2, driver=1, gradient=False)
     if args.calibrate_copy:
         src = torch.empty(256 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

@@ -68,7 +68,11 @@ typedef struct {
   int32_t subspace_iters;/* M of Algorithm 2: applications per round (4)               */
   int32_t max_recovery;  /* rounds of probe insertion into slices that miss
                             eigenvalues (Sec. 3.3) before SISLICE_MISSING_EIGS (2)    */
-  int32_t reserved;      /* 0                                                          */
+  int32_t graphs;        /* 1: the factorization's panel/update step sequence is
+                            captured once per order, shift count and panel
+                            parameters into a HIP graph and replayed (on streams
+                            other than the null stream, which cannot be
+                            captured); 0: launched directly (1)                      */
 } sislice_opts;
 
 /* Per-solve report, host memory owned by the caller.  Array members are optional
@@ -329,6 +333,8 @@ typedef struct {
   int64_t n_converged;   /* returned eigenpairs meeting opts->tol, summed        */
   double t_total_ms;
   double t_tune_ms;      /* autotuning time inside t_total_ms                    */
+  int64_t graph_replays; /* factorizations run as replays of captured graphs     */
+  int64_t graphs_built;  /* graphs captured by this call                          */
 } sislice_batch_report;
 
 /* Many independent pencils of possibly different orders (the paper's probes
@@ -336,10 +342,14 @@ typedef struct {
  * (sislice_plan_shifts_kpm) and solved (sislice_solve) exactly as alone, with
  * `workers` pencils in flight at a time (<= 0: 4; at most 16), each on a
  * worker handle with its own stream and workspaces that the handle keeps, the
- * largest orders first.  Unless opts->nb fixes it, the factorization panel
- * width is autotuned per order on the first pencil of that order (the
- * lock-step factorization of its planned points timed for widths 32, 48, 64)
- * and cached in the handle.  status: host int32[count] out, one sislice_status
+ * largest orders first.  Unless opts->nb fixes it, the factorization's
+ * parameters are autotuned per order on the first pencil of that order (the
+ * lock-step factorization of its planned points timed by coordinate descent
+ * over the panel width 32, 48, 64, the pivoting-panel width 16, 32 and the
+ * trailing order 512, 1024, 2048 from which the update takes 128x128 tiles)
+ * and cached in the handle.  With opts->graphs every worker replays captured
+ * factorization sequences (sislice_opts.graphs; the report counts the
+ * replays).  status: host int32[count] out, one sislice_status
  * per problem.  Returns SISLICE_OK when every problem did, else the most
  * severe status (negative before positive).  Synchronises; inputs must be
  * complete on the handle's stream. */
@@ -350,6 +360,10 @@ sislice_status sislice_solve_batched(sislice_handle *h, int64_t count,
 
 /* Panel width the autotuner cached for order n on this handle (0: none). */
 int32_t sislice_tuned_nb(sislice_handle *h, int64_t n);
+/* All three cached factorization parameters for order n (host int32 out, any
+ * may be NULL): returns 1, or 0 when order n has not been tuned. */
+int32_t sislice_tuned_factor(sislice_handle *h, int64_t n, int32_t *nb, int32_t *nbpiv,
+                             int32_t *wide_min);
 
 /* Shift migration by k-means (Sec. 3.2), host only: Lloyd iterations on the 1-D
  * set `ritz` (host double[n]) from the initial centroids `prev_shifts` (host

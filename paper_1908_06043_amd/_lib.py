@@ -24,7 +24,7 @@ class Opts(C.Structure):
                 ("bounds_steps", C.c_int32), ("nb", C.c_int32), ("profile", C.c_int32),
                 ("tol", C.c_double), ("top_margin", C.c_double), ("seed", C.c_uint64),
                 ("driver", C.c_int32), ("subspace_iters", C.c_int32), ("max_recovery", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("graphs", C.c_int32)]
 
 
 class Report(C.Structure):
@@ -63,7 +63,8 @@ class Problem(C.Structure):
 
 class BatchReport(C.Structure):
     _fields_ = [("workers", C.c_int32), ("n_ok", C.c_int32), ("n_tuned", C.c_int32),
-                ("n_converged", C.c_int64), ("t_total_ms", C.c_double), ("t_tune_ms", C.c_double)]
+                ("n_converged", C.c_int64), ("t_total_ms", C.c_double), ("t_tune_ms", C.c_double),
+                ("graph_replays", C.c_int64), ("graphs_built", C.c_int64)]
 
 
 _SIGS = {
@@ -106,6 +107,7 @@ _SIGS = {
     "sislice_solve_batched": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(Problem), C.POINTER(Opts),
                                         C.c_int32, c_int32_p, C.POINTER(BatchReport)]),
     "sislice_tuned_nb": (C.c_int32, [C.c_void_p, C.c_int64]),
+    "sislice_tuned_factor": (C.c_int32, [C.c_void_p, C.c_int64, c_int32_p, c_int32_p, c_int32_p]),
     "sislice_scf_create": (C.c_int, [C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.POINTER(Opts),
                                      C.c_double, C.POINTER(C.c_void_p)]),
     "sislice_scf_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,

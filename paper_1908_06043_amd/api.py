@@ -350,6 +350,13 @@ class ScfSequence:
             pass
 
 
+def tuned_factor(n, device=None):
+    """(nb, nbpiv, wide_min) the autotuner cached for order n, or None."""
+    v = [C.c_int32(), C.c_int32(), C.c_int32()]
+    ok = _lib.load().sislice_tuned_factor(handle(device), int(n), *[C.byref(x) for x in v])
+    return tuple(int(x.value) for x in v) if ok else None
+
+
 def tuned_nb(n, device=None):
     """Panel width the batch autotuner cached for order n (0: none yet)."""
     return int(_lib.load().sislice_tuned_nb(handle(device), int(n)))

@@ -517,7 +517,7 @@ DriverWs driver_factor(sislice_handle* h, Ring& ring, int n, const double* A, lo
   sym_full_launch(n, B, ldb, w.Bf, n, st);
   w.fp = build_factor(h, kBufFactor, n, A, lda, B, ldb, S1, pts.data(), w.LD.data(), n, w.ipv.data(),
                       nb, true);
-  factor_launch(w.fp, st);
+  factor_run(h, w.fp, st);
   w.inert.assign(3 * S1, 0);
   SL_HIP(hipMemcpyAsync(w.inert.data(), w.fp.d_inertia, sizeof(int64_t) * 3 * S1,
                         hipMemcpyDeviceToHost, st));
@@ -558,6 +558,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   set_current_handle(h);
   prof_reset(h);
   h->prof = o.profile != 0;
+  h->use_graphs = o.graphs != 0;
   const int b = kLanczosBlock;
   hipStream_t st = h->stream;
   std::vector<double> sig(P);

@@ -947,16 +947,32 @@ __global__ __launch_bounds__(256) void k_factor_finalize(int n, const int* const
 
 // ------------------------------------------------------------------ host side
 
-// Trailing order from which the update runs on 128x128 tiles (below it, the
-// 64x64 tiles keep more workgroups in flight).
-constexpr long kUpdateWideMin = 1024;
+void factor_prepare() {
+  static std::once_flag attr_set;
+  std::call_once(attr_set, [] {
+    SL_HIP(hipFuncSetAttribute((const void*)k_left_gather,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    SL_HIP(hipFuncSetAttribute((const void*)k_perm_suffix,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  });
+}
+
+void factor_shift_form_launch(const FactorPlan& fp, hipStream_t st) {
+  if (fp.nshift <= 0 || fp.n <= 0) return;
+  SL_LAUNCH(k_shift_form, dim3(fp.n, fp.nshift), dim3(256), 0, st, fp.n, fp.A, fp.lda, fp.B, fp.ldb,
+            fp.d_sigmas, fp.d_LD, fp.ldld);
+  SL_LAUNCH_CHECK();
+}
 
 void factor_launch(const FactorPlan& fp, hipStream_t st) {
+  factor_shift_form_launch(fp, st);
+  factor_steps_launch(fp, st, true);
+}
+
+void factor_steps_launch(const FactorPlan& fp, hipStream_t st, bool readback) {
   const int n = fp.n, S = fp.nshift, nb = fp.nb;
   if (S <= 0 || n <= 0) return;
-  SL_LAUNCH(k_shift_form, dim3(n, S), dim3(256), 0, st, n, fp.A, fp.lda, fp.B, fp.ldb,
-                     fp.d_sigmas, fp.d_LD, fp.ldld);
-  SL_LAUNCH_CHECK();
+  factor_prepare();
   SL_LAUNCH(k_factor_init, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
                      fp.d_state, fp.d_perm, fp.d_sw);
   SL_LAUNCH_CHECK();
@@ -965,11 +981,14 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
   const int min_kb = factor_min_panel(nb, fp.nbpiv, fp.fast != 0);
   // Panel widths depend on the pivots: launch chunks of panel steps and read the
   // per-shift progress back between chunks (kmin = least factored prefix).
-  constexpr int kChunk = 8;
-  FactorState* hs = static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S));
+  // Without readback (a sequence captured into a graph) every step up to the
+  // bound is launched; steps past a shift's end return at once.
+  const int step_cap = factor_npanel_max(n, nb, fp.nbpiv, fp.fast != 0);
+  const int kChunk = readback ? 8 : step_cap;
+  FactorState* hs =
+      readback ? static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S)) : nullptr;
   long kmin = 0;
   int steps = 0;
-  const int step_cap = factor_npanel_max(n, nb, fp.nbpiv, fp.fast != 0);
   SL_CHECK_ARG(step_cap <= fp.npmax, "panel bookkeeping smaller than the step bound");
   while (kmin < n && steps < step_cap) {
     for (int q = 0; q < kChunk && steps < step_cap; ++q, ++steps) {
@@ -1024,7 +1043,7 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       const long k1_lb = std::min<long>(n, k0_lb + min_kb);
       if (k1_lb >= n) continue;
       const int tu = prof_begin(ph, kProfUpdate);
-      if (n - k1_lb >= kUpdateWideMin) {
+      if (n - k1_lb >= fp.wide_min) {
         const long T = ceil_div(n - k1_lb, 128);
         SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st, n,
                   fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
@@ -1036,20 +1055,14 @@ void factor_launch(const FactorPlan& fp, hipStream_t st) {
       SL_LAUNCH_CHECK();
       prof_end(ph, tu);
     }
+    if (!readback) break;
     SL_HIP(hipMemcpyAsync(hs, fp.d_state, sizeof(FactorState) * S, hipMemcpyDeviceToHost, st));
     SL_HIP(hipStreamSynchronize(st));
     kmin = n;
     for (int q = 0; q < S; ++q) kmin = std::min<long>(kmin, hs[q].done ? n : hs[q].k0 + hs[q].kb);
   }
-  SL_CHECK_ARG(kmin >= n, "factorization did not complete");
+  SL_CHECK_ARG(!readback || kmin >= n, "factorization did not complete");
   if (fp.pivot) {
-    static std::once_flag attr_set;
-    std::call_once(attr_set, [] {
-      SL_HIP(hipFuncSetAttribute((const void*)k_left_gather,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-      SL_HIP(hipFuncSetAttribute((const void*)k_perm_suffix,
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    });
     SL_LAUNCH(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
                        fp.d_pstart, fp.d_state, fp.d_snap);
     SL_LAUNCH_CHECK();

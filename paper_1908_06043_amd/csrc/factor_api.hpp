@@ -16,4 +16,10 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
                         double* const* LD_host, long ldld, int32_t* const* ipiv_host, int nb,
                         bool pivot);
 
+// Runs the factorization of a plan: directly (factor_launch), or, with the
+// handle's graphs on and a pivoting plan, the shift-form followed by the replay
+// of the captured step sequence for the plan's shape and workspace (captured on
+// first use).
+void factor_run(sislice_handle* h, const FactorPlan& fp, hipStream_t st);
+
 }  // namespace sislice

@@ -145,7 +145,8 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
                         double* const* LD_host, long ldld, int32_t* const* ipiv_host, int nb,
                         bool pivot) {
   const FactorPlan defaults;
-  const int npmax = factor_npanel_max(n, nb, defaults.nbpiv, defaults.fast != 0);
+  const int nbpiv = h->cur_nbpiv > 0 ? h->cur_nbpiv : defaults.nbpiv;
+  const int npmax = factor_npanel_max(n, nb, nbpiv, defaults.fast != 0);
   const long ldw = n;
   Sizer z;
   z.take<double>(S);                          // sigmas
@@ -217,7 +218,73 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   fp.d_ipiv = reinterpret_cast<int* const*>(tab + 8 * S);
   fp.d_Lp = reinterpret_cast<double* const*>(tab + 9 * S);
   fp.d_aux = reinterpret_cast<double* const*>(tab + 10 * S);
+  fp.nbpiv = nbpiv;
+  if (h->cur_wide_min > 0) fp.wide_min = h->cur_wide_min;
   return fp;
+}
+
+void factor_run(sislice_handle* h, const FactorPlan& fp, hipStream_t st) {
+  // (the null stream cannot be captured)
+  if (!h->use_graphs || h->stream == nullptr || !fp.pivot || fp.n <= 0 || fp.nshift <= 0) {
+    factor_launch(fp, st);
+    return;
+  }
+  factor_shift_form_launch(fp, st);
+  sislice_handle::FactorGraph* g = nullptr;
+  for (auto& q : h->fgraphs)
+    if (q.n == fp.n && q.S == fp.nshift && q.nb == fp.nb && q.nbpiv == fp.nbpiv &&
+        q.wide_min == fp.wide_min && q.ldld == fp.ldld && q.state == fp.d_state)
+      g = &q;
+  if (!g) {
+    factor_prepare();
+    flush_uploads();  // nothing staged may become a node of the graph
+    auto fn = h->flush_fn;
+    const bool prof = h->prof;
+    h->flush_fn = nullptr;
+    h->prof = false;
+    sislice_handle::FactorGraph ng;
+    ng.n = fp.n;
+    ng.S = fp.nshift;
+    ng.nb = fp.nb;
+    ng.nbpiv = fp.nbpiv;
+    ng.wide_min = fp.wide_min;
+    ng.ldld = fp.ldld;
+    ng.state = fp.d_state;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        factor_steps_launch(fp, st, false);
+      } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(st, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        h->flush_fn = fn;
+        h->prof = prof;
+        throw;
+      }
+      e = hipStreamEndCapture(st, &ng.graph);
+    }
+    h->flush_fn = fn;
+    h->prof = prof;
+    SL_HIP(e);
+    SL_HIP(hipGraphInstantiate(&ng.exec, ng.graph, nullptr, nullptr, 0));
+    // a graph of the same shape over a workspace that has moved is stale
+    for (auto it = h->fgraphs.begin(); it != h->fgraphs.end();) {
+      if (it->n == ng.n && it->S == ng.S && it->nb == ng.nb && it->nbpiv == ng.nbpiv &&
+          it->wide_min == ng.wide_min) {
+        (void)hipGraphExecDestroy(it->exec);
+        (void)hipGraphDestroy(it->graph);
+        it = h->fgraphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    h->fgraphs.push_back(ng);
+    g = &h->fgraphs.back();
+    ++h->graphs_built;
+  }
+  SL_HIP(hipGraphLaunch(g->exec, st));
+  ++h->graph_replays;
 }
 
 }  // namespace sislice
@@ -255,7 +322,7 @@ void sislice_default_opts(sislice_opts* o) {
   o->driver = 0;
   o->subspace_iters = 4;
   o->max_recovery = 2;
-  o->reserved = 0;
+  o->graphs = 1;
 }
 
 const char* sislice_status_string(sislice_status s) {
@@ -317,6 +384,10 @@ sislice_status sislice_destroy(sislice_handle* h) {
   if (h->sync) hipFree(h->sync);
   if (h->wait_word) hipFree(h->wait_word);
   if (h->ring_host) hipHostFree(h->ring_host);
+  for (auto& g : h->fgraphs) {
+    hipGraphExecDestroy(g.exec);
+    hipGraphDestroy(g.graph);
+  }
   for (auto e : h->evpool) hipEventDestroy(e);
   for (auto& e : h->ev)
     if (e) hipEventDestroy(e);

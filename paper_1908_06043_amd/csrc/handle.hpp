@@ -59,10 +59,29 @@ struct sislice_handle {
   } fc;
   uint64_t fc_counter = 0;
   // Batched solves: worker handles (each with its own stream and workspaces)
-  // and the factorization panel width chosen by the autotuner per order n.
+  // and the factorization parameters chosen by the autotuner per order n.
   std::vector<sislice_handle*> workers;
   std::vector<hipStream_t> worker_streams;  // created by the library, owned
-  std::map<int, int> tuned_nb;
+  struct FactorTune {
+    int nb = 0, nbpiv = 0, wide_min = 0;
+  };
+  std::map<int, FactorTune> tuned;
+  // panel parameters for the next factorizations (0: the library defaults)
+  int cur_nbpiv = 0, cur_wide_min = 0;
+  // Captured factorization sequences (panel/update steps, interchanges, inertia)
+  // replayed with hipGraphLaunch when graphs are on: one per (order, shift
+  // count, panel parameters) and factorization workspace.
+  struct FactorGraph {
+    int n = 0, S = 0, nb = 0, nbpiv = 0, wide_min = 0;
+    long ldld = 0;
+    const void* state = nullptr;  // the workspace the graph's kernels address
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<FactorGraph> fgraphs;
+  bool use_graphs = false;
+  int64_t graph_replays = 0;
+  int64_t graphs_built = 0;
 };
 
 namespace sislice {

@@ -36,9 +36,21 @@ struct FactorPlan {
   double* const* d_aux = nullptr;  // [nb] D | [nb] max|w| in block | [nb] max|w| below (uint64 bits) | nb*nb Linv
   int fast = 1;                    // use the pivot-free path
   int nbpiv = 32;                  // columns a pivoting panel handles after a rejection
+  int wide_min = 1024;             // trailing order from which the update takes 128x128 tiles
 };
 
+// The whole factorization: shift-form, then the panel/update steps with the
+// per-shift progress read back every few steps, the deferred interchanges and
+// the inertia.
 void factor_launch(const FactorPlan& fp, hipStream_t st);
+// The two parts on their own.  With readback == false every step up to the bound
+// factor_npanel_max is launched and nothing synchronises (a sequence that a HIP
+// graph can capture: its kernels read the shifted matrices through the plan's
+// device tables only).
+void factor_shift_form_launch(const FactorPlan& fp, hipStream_t st);
+void factor_steps_launch(const FactorPlan& fp, hipStream_t st, bool readback);
+// One-time kernel attributes of the factorization (outside any capture).
+void factor_prepare();
 
 // Narrowest panel that is not the last one: a pivoting panel stops at nb - 1
 // columns (room for a closing 2x2 pivot) and, behind the pivot-free path, after

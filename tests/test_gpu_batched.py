@@ -60,11 +60,21 @@ def test_small_batch_matches_construction_and_plain(gpu_lib):
         ev = check(o, P.lam, ne, B, A)
         plain = api.solve(A, B, ne, 8)
         assert np.max(np.abs(plain["evals"].cpu().numpy() - ev)) <= 1e-12 * np.max(np.abs(P.lam))
-    # the autotuner cached one width per order; a second call tunes nothing
+    # the workers replayed captured factorization sequences
+    assert rep["graph_replays"] >= len(sizes) and rep["graphs_built"] >= 1
+    # the autotuner cached one configuration per order; a second call tunes nothing
     for n in sizes:
         assert api.tuned_nb(n) in (32, 48, 64)
-    _, rep2 = api.solve_batched([(A, B, ne, 8) for _, A, B, ne in pens], workers=2)
+        nb, nbpiv, wide = api.tuned_factor(n)
+        assert nb in (32, 48, 64) and nbpiv in (16, 32) and wide in (512, 1024, 2048)
+    outs2, rep2 = api.solve_batched([(A, B, ne, 8) for _, A, B, ne in pens], workers=2)
     assert rep2["n_tuned"] == 0 and rep2["status"] == 0
+    # the same kernels with and without graphs: identical eigenvalues
+    outs3, rep3 = api.solve_batched([(A, B, ne, 8) for _, A, B, ne in pens], workers=2,
+                                    opts=api.default_opts(graphs=0))
+    assert rep3["status"] == 0 and rep3["graph_replays"] == 0
+    for o2, o3 in zip(outs2, outs3):
+        assert torch.equal(o2["evals"], o3["evals"])
 
 
 def test_restart_keeps_projected_order_bounded(gpu_lib):
