@@ -334,6 +334,8 @@ def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10, driver=0, g
         conv = int((out["resid"] <= 1e-10).sum().item()) if out["status"] in (0, 2) else 0
         r = out["report"]
         recs.append({"ms_solve": 1e3 * (t1 - t0), "ms_gradient": 1e3 * (t2 - t1),
+                     "ms_factor": float(r["t_factor_ms"]),
+                     "factor_tflops": float(r["flops_factor"]) / max(float(r["t_factor_ms"]), 1e-9) / 1e9,
                      "status": out["status"], "replanned": int(r["replanned"]),
                      "block_steps": int(r["block_steps"]), "cycles_max": int(r["cycles_max"]),
                      "merged_deleted_inserted": [int(r["merged"]), int(r["deleted"]), int(r["inserted"])],
@@ -354,6 +356,8 @@ def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10, driver=0, g
         "value": conv_all / t_all, "unit": "eigenpairs/s" + (" (with gradients)" if gradient else ""),
         "plain_step_ms": recs[0]["ms_solve"],
         "warm_step_ms_mean": float(np.mean(warm)) if warm else None,
+        "factor_tflops": (sum(x["ms_factor"] * x["factor_tflops"] for x in recs)
+                          / max(sum(x["ms_factor"] for x in recs), 1e-9)),
         "steps": recs,
     }
 

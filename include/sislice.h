@@ -433,6 +433,9 @@ typedef struct {
   int32_t cycles_max;    /* largest number of Lanczos restart cycles of a probe        */
   int32_t probes_inserted; /* probes inserted by the solve into slices that missed
                               eigenvalues (Sec. 3.3)                                 */
+  double t_factor_ms;    /* factorizations of the step's solves (shift-form, LDL^T,
+                            inertia)                                                   */
+  double flops_factor;   /* n^3/3 per factorization, summed                           */
 } sislice_scf_report;
 
 sislice_status sislice_scf_create(sislice_handle *h, int64_t n, int64_t n_e, int64_t n_s,

@@ -52,7 +52,8 @@ class ScfReport(C.Structure):
                 ("deleted", C.c_int32), ("inserted", C.c_int32), ("status_solve", C.c_int32),
                 ("eta_prev", C.c_double), ("eta_new", C.c_double), ("block_steps", C.c_int64),
                 ("factor_id", C.c_uint64), ("t_solve_ms", C.c_double), ("t_total_ms", C.c_double),
-                ("cycles_max", C.c_int32), ("probes_inserted", C.c_int32)]
+                ("cycles_max", C.c_int32), ("probes_inserted", C.c_int32),
+                ("t_factor_ms", C.c_double), ("flops_factor", C.c_double)]
 
 
 class Problem(C.Structure):

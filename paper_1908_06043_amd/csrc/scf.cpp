@@ -317,6 +317,8 @@ sislice_status sislice_scf_step(sislice_scf* s, const double* A, int64_t lda, co
       r.block_steps += sr.block_steps;
       r.cycles_max = std::max(r.cycles_max, sr.cycles_max);
       r.probes_inserted += sr.probes_inserted;
+      r.t_factor_ms += sr.t_factor_ms;
+      r.flops_factor += sr.flops_factor;
       if ((st == SISLICE_MISSING_EIGS || st == SISLICE_SINGULAR_SHIFT) && !dos) {
         dos = true;  // the migrated shifts missed eigenvalues: repeat with DOS shifts
         r.replanned = 2;
