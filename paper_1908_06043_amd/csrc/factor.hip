@@ -70,17 +70,17 @@ __device__ __forceinline__ void block_argmax(double& v, int& i, double* rv, int*
 
 // ------------------------------------------------------------------ kernels
 
-// LD[i, j] = A[i, j] - sigma_s B[i, j] on the lower triangle (Algorithm 2, step 2).
-__global__ __launch_bounds__(256) void k_shift_form(int n, const double* __restrict__ A, long lda,
-                                                    const double* __restrict__ B, long ldb,
-                                                    const double* __restrict__ sigmas,
+// LD[i, j] = A[i, j] - sigma_s B[i, j] on the lower triangle (Algorithm 2, step 2)
+// for every shift s: column j per workgroup, A and B read once for all shifts.
+__global__ __launch_bounds__(256) void k_shift_form(int n, int S, const double* __restrict__ A,
+                                                    long lda, const double* __restrict__ B,
+                                                    long ldb, const double* __restrict__ sigmas,
                                                     double* const* LDs, long ldld) {
   const int j = blockIdx.x;
-  const int s = blockIdx.y;
-  const double sg = sigmas[s];
-  double* LD = LDs[s];
-  for (int i = j + threadIdx.x; i < n; i += blockDim.x)
-    LD[i + (long)j * ldld] = A[i + (long)j * lda] - sg * B[i + (long)j * ldb];
+  for (int i = j + threadIdx.x; i < n; i += blockDim.x) {
+    const double a = A[i + (long)j * lda], b = B[i + (long)j * ldb];
+    for (int s = 0; s < S; ++s) LDs[s][i + (long)j * ldld] = a - sigmas[s] * b;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states, int* const* perms,
@@ -872,6 +872,247 @@ __global__ __launch_bounds__(1024) void k_trailing_update_lds(int n, double* con
   }
 }
 
+// Persistent form of the 128x128-tile update for large trailing matrices.  A
+// launch has one 1024-thread workgroup per CU.  The (shift, tile) items of every
+// shift are numbered shift by shift, tile rows in order, and each workgroup takes
+// one contiguous run of them (the runs of the workgroups of one XCD adjacent), so
+// consecutive items of a workgroup mostly lie in one tile row and share its L
+// rows.  The rank-kb (<= 64) operand panels of a tile sit in LDS whole (L and -W,
+// [k][row] with rows padded to 132 doubles: 135 KB), so a tile needs no barrier
+// between its MFMAs; the L panel is reloaded only when the tile row changes.  The
+// work is software-pipelined across a workgroup's items: while the MFMAs of item t
+// run, the C tile and the W panel of item t + 1 are in flight into registers and
+// the stores of item t - 1 drain.  Memory goes through buffer instructions whose
+// out-of-range offsets read zero and drop stores, so rows and columns past n,
+// operand columns past kb and the upper half of a diagonal tile need no branch:
+// every item issues the same loads and stores, and the wait for the next item's
+// loads does not wait for the stores issued after them (loads and stores retire
+// in issue order).  The accumulation order per element is that of
+// k_trailing_update_lds.
+constexpr int kPipeMaxShifts = 256;
+constexpr int kPipeK = kMaxNb;  // widest panel (update rank) the persistent update takes
+// An offset past every buffer's range (the host keeps the kernel's buffers below
+// it), low enough that the end of an 8-byte access does not wrap.
+constexpr unsigned kPipeOob = 0xFFFFFF00u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pipe_rsrc(const double* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), (short)0, (int)bytes, 0x00020000);
+}
+typedef unsigned int pipe_u2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double pipe_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void pipe_st(__amdgpu_buffer_rsrc_t r, unsigned off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(pipe_u2, v), r, (int)off, 0, 0);
+}
+// `off` where `ok`, else an offset out of range, without a branch (a branch that
+// skipped the memory operation would make the count of outstanding operations
+// differ between paths, and the waits would then wait for everything).
+__device__ __forceinline__ unsigned pipe_off(bool ok, unsigned off) {
+  const unsigned m = (unsigned)ok - 1u;
+  return (off & ~m) | (kPipeOob & m);
+}
+// A pointer that every lane holds, as a scalar value.
+__device__ __forceinline__ double* pipe_uniform(double* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (double*)(((unsigned long long)hi << 32) | lo);
+}
+
+__global__ __launch_bounds__(1024) void k_trailing_update_pipe(int n, double* const* LDs, long ldld,
+                                                              double* const* Wps, long ldw,
+                                                              const FactorState* states, int S) {
+  constexpr int TB = 128;
+  __shared__ double sL[kPipeK * kUpdLd];
+  __shared__ double sW[kPipeK * kUpdLd];
+  __shared__ int pre[kPipeMaxShifts + 1];
+  // per-shift panel start and width and matrix / panel pointers, read from LDS
+  // (never through the vector memory counter that the pipeline's waits count)
+  __shared__ int sk0[kPipeMaxShifts], skb[kPipeMaxShifts];
+  __shared__ double* sLD[kPipeMaxShifts];
+  __shared__ double* sWp[kPipeMaxShifts];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < S; q += 1024) {
+    sk0[q] = states[q].k0;
+    skb[q] = states[q].kb;
+    sLD[q] = LDs[q];
+    sWp[q] = Wps[q];
+  }
+  // items per shift (tiles of its trailing lower triangle) and their prefix sums
+  if (tid < 64) {
+    int base = 0;
+    for (int q0 = 0; q0 < S; q0 += 64) {
+      const int q = q0 + tid;
+      int c = 0;
+      if (q < S) {
+        const int kb = states[q].kb, k1 = states[q].k0 + kb;
+        if (kb > 0 && k1 < n) {
+          const int T = (n - k1 + TB - 1) / TB;
+          c = T * (T + 1) / 2;
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(c, off);
+        if (tid >= off) c += o;
+      }
+      if (q < S) pre[q + 1] = base + c;
+      base += __shfl(c, 63);
+    }
+    if (tid == 0) pre[0] = 0;
+  }
+  __syncthreads();
+  const int M = pre[S];
+  const int G = gridDim.x, b = blockIdx.x;
+  const int slot = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int i_begin = (int)((long)M * slot / G), i_end = (int)((long)M * (slot + 1) / G);
+  if (i_begin >= i_end) return;
+
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+  const int wi = (w & 3) * 32, wj = (w >> 2) * 32;
+  const int lr = l & 15, lk = l >> 4;
+  const int sr = tid & 127, sc = tid >> 7;  // staging: row sr of k-columns sc + 8j
+  const unsigned ld8 = (unsigned)ldld * 8u, lw8 = (unsigned)ldw * 8u;
+  const unsigned bytes_ld = (unsigned)((size_t)ldld * n * 8);
+  const unsigned bytes_w = (unsigned)((size_t)ldw * (kPipeK + 2) * 8);
+
+  struct Item {
+    int s, k0, kb, ti, row0, col0;
+    bool diag;
+  };
+  int s_cur = 0;
+  auto decode = [&](int item, Item& it) {
+    while (pre[s_cur + 1] <= item) ++s_cur;
+    const int s = __builtin_amdgcn_readfirstlane(s_cur);
+    const int lin = item - pre[s];
+    int ti = (int)((sqrt(8.0 * lin + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > lin) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= lin) ++ti;
+    const int tj = lin - ti * (ti + 1) / 2;
+    it.s = s;
+    it.k0 = __builtin_amdgcn_readfirstlane(sk0[s]);
+    it.kb = __builtin_amdgcn_readfirstlane(skb[s]);
+    const int k1 = it.k0 + it.kb;
+    it.ti = __builtin_amdgcn_readfirstlane(ti);
+    it.row0 = k1 + it.ti * TB;
+    it.col0 = __builtin_amdgcn_readfirstlane(k1 + tj * TB);
+    it.diag = (it.ti == tj);
+  };
+  double cn[2][2][4];
+  double wn[kPipeK / 8];
+  auto prefetch = [&](const Item& it) {
+    const __amdgpu_buffer_rsrc_t rLD = pipe_rsrc(pipe_uniform(sLD[it.s]), bytes_ld);
+    const __amdgpu_buffer_rsrc_t rW = pipe_rsrc(pipe_uniform(sWp[it.s]), bytes_w);
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      const int i = it.row0 + wi + 16 * x + lr;
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = it.col0 + wj + 16 * y + lk + 4 * r;
+          cn[x][y][r] = pipe_ld(rLD, pipe_off((i < n) & (j < n), (unsigned)i * 8u + (unsigned)j * ld8));
+        }
+    }
+    const int wr = it.col0 + sr;
+#pragma unroll
+    for (int jj = 0; jj < kPipeK / 8; ++jj) {
+      const int k = sc + 8 * jj;
+      wn[jj] = pipe_ld(rW, pipe_off((k < it.kb) & (wr < n), (unsigned)wr * 8u + (unsigned)k * lw8));
+    }
+  };
+
+  Item cur, nxt;
+  int item = i_begin;
+  decode(item, nxt);
+  prefetch(nxt);
+  {
+    // the loop's sixteen stores, dropped (out of range): the loads above then have
+    // as many younger memory operations on entry as on the back edge, so the wait
+    // for them at the top of the loop does not wait for the stores
+    const __amdgpu_buffer_rsrc_t rLD = pipe_rsrc(pipe_uniform(sLD[nxt.s]), bytes_ld);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pipe_st(rLD, kPipeOob + 8u * q, 0.0);
+  }
+  int row_s = -1, row_t = -1;  // tile row whose L panel is in LDS
+  d4 acc[2][2];
+  for (;;) {
+    cur = nxt;
+    __syncthreads();  // every wavefront is done with the previous item's operands
+    if (cur.s != row_s || cur.ti != row_t) {
+      const __amdgpu_buffer_rsrc_t rLD = pipe_rsrc(pipe_uniform(sLD[cur.s]), bytes_ld);
+      const int li = cur.row0 + sr;
+      double lv[kPipeK / 8];
+#pragma unroll
+      for (int jj = 0; jj < kPipeK / 8; ++jj) {
+        const int k = sc + 8 * jj;
+        lv[jj] = pipe_ld(rLD, pipe_off((k < cur.kb) & (li < n), (unsigned)li * 8u + (unsigned)(cur.k0 + k) * ld8));
+      }
+#pragma unroll
+      for (int jj = 0; jj < kPipeK / 8; ++jj) sL[(sc + 8 * jj) * kUpdLd + sr] = lv[jj];
+      row_s = cur.s;
+      row_t = cur.ti;
+    }
+#pragma unroll
+    for (int jj = 0; jj < kPipeK / 8; ++jj) sW[(sc + 8 * jj) * kUpdLd + sr] = -wn[jj];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[x][y][r] = cn[x][y][r];
+    __syncthreads();
+    // the next item's loads go out before this item's MFMAs and stores; past the
+    // last item the current one is loaded again (unused), so every iteration
+    // issues the same memory operations
+    const bool more = item + 1 < i_end;
+    if (more) decode(item + 1, nxt);
+    prefetch(more ? nxt : cur);
+    const bool active = !(cur.diag && wi + 31 < wj);
+    if (active) {
+      const double* L0 = sL + wi + lr;
+      const double* W0 = sW + wj + lr;
+      // k-steps of 4 in pairs (the operands past kb are zero in LDS)
+      const int npair = (cur.kb + 7) >> 3;
+      for (int u = 0; u < npair; ++u) {
+        double lo[2][2], wo[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int kk = (8 * u + 4 * h + lk) * kUpdLd;
+#pragma unroll
+          for (int x = 0; x < 2; ++x) lo[h][x] = L0[kk + 16 * x];
+#pragma unroll
+          for (int y = 0; y < 2; ++y) wo[h][y] = W0[kk + 16 * y];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) acc[x][y] = mfma16x16x4(wo[h][y], lo[h][x], acc[x][y]);
+      }
+    }
+    {
+      const __amdgpu_buffer_rsrc_t rLD = pipe_rsrc(pipe_uniform(sLD[cur.s]), bytes_ld);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int i = cur.row0 + wi + 16 * x + lr;
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j = cur.col0 + wj + 16 * y + lk + 4 * r;
+            pipe_st(rLD, pipe_off(active & (i < n) & (j < n) & (i >= j), (unsigned)i * 8u + (unsigned)j * ld8),
+                    acc[x][y][r]);
+          }
+      }
+    }
+    if (!more) break;
+    ++item;
+  }
+}
+
 // Suffix compositions of the interchanges: for the panel ending at e, Q_e[v] is
 // the final row of the entry found at row v (v >= e) when that panel finished.
 __global__ __launch_bounds__(256) void k_perm_suffix(int n, const int* const* swps,
@@ -906,11 +1147,13 @@ __global__ __launch_bounds__(256) void k_perm_suffix(int n, const int* const* sw
 }
 
 // Apply the later panels' interchanges to the rows of each finished L column.
-__global__ __launch_bounds__(256) void k_left_gather(int n, double* const* LDs, long ldld,
-                                                     const int* const* colpanels,
-                                                     const int* const* pstarts,
-                                                     const FactorState* states,
-                                                     const int* const* snaps) {
+// The column is staged in LDS (up to n doubles), which allows one workgroup per
+// CU: 1024 threads, each with four rows' loads in flight per round.
+__global__ __launch_bounds__(1024) void k_left_gather(int n, double* const* LDs, long ldld,
+                                                      const int* const* colpanels,
+                                                      const int* const* pstarts,
+                                                      const FactorState* states,
+                                                      const int* const* snaps) {
   extern __shared__ double col[];
   const int c = blockIdx.x, s = blockIdx.y;
   const int P = colpanels[s][c];
@@ -920,9 +1163,22 @@ __global__ __launch_bounds__(256) void k_left_gather(int n, double* const* LDs, 
   if (e >= n) return;
   double* LD = LDs[s] + (long)c * ldld;
   const int* q = snaps[s] + (long)P * n;
-  for (int v = e + threadIdx.x; v < n; v += blockDim.x) col[q[v] - e] = LD[v];
+  constexpr int U = 4;
+  for (int v0 = e + threadIdx.x; v0 < n; v0 += U * 1024) {
+    double x[U];
+    int t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + u * 1024;
+      x[u] = v < n ? LD[v] : 0.0;
+      t[u] = v < n ? q[v] : e;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (v0 + u * 1024 < n) col[t[u] - e] = x[u];
+  }
   __syncthreads();
-  for (int i = e + threadIdx.x; i < n; i += blockDim.x) LD[i] = col[i - e];
+  for (int i = e + threadIdx.x; i < n; i += 1024) LD[i] = col[i - e];
 }
 
 // ipiv in the documented format and the inertia triple of every shift.
@@ -959,14 +1215,136 @@ void factor_prepare() {
 
 void factor_shift_form_launch(const FactorPlan& fp, hipStream_t st) {
   if (fp.nshift <= 0 || fp.n <= 0) return;
-  SL_LAUNCH(k_shift_form, dim3(fp.n, fp.nshift), dim3(256), 0, st, fp.n, fp.A, fp.lda, fp.B, fp.ldb,
+  SL_LAUNCH(k_shift_form, dim3(fp.n), dim3(256), 0, st, fp.n, fp.nshift, fp.A, fp.lda, fp.B, fp.ldb,
             fp.d_sigmas, fp.d_LD, fp.ldld);
   SL_LAUNCH_CHECK();
+}
+
+// The persistent update addresses each shifted matrix and panel buffer with
+// 32-bit offsets below kPipeOob and keeps the per-shift table in LDS.
+static bool pipe_fits(const FactorPlan& fp) {
+  return fp.nshift <= kPipeMaxShifts && (double)fp.ldld * fp.n * 8.0 < (double)kPipeOob &&
+         fp.nb <= kPipeK && (double)fp.ldw * (kPipeK + 2) * 8.0 < (double)kPipeOob;
 }
 
 void factor_launch(const FactorPlan& fp, hipStream_t st) {
   factor_shift_form_launch(fp, st);
   factor_steps_launch(fp, st, true);
+}
+
+// The plan of shifts [s0, s0 + cnt): every per-shift device table offset.
+static FactorPlan factor_subplan(const FactorPlan& fp, int s0, int cnt) {
+  FactorPlan f = fp;
+  f.nshift = cnt;
+  f.d_sigmas = fp.d_sigmas ? fp.d_sigmas + s0 : nullptr;
+  f.d_LD = fp.d_LD + s0;
+  f.d_W = fp.d_W + s0;
+  f.d_perm = fp.d_perm + s0;
+  f.d_sw = fp.d_sw + s0;
+  f.d_blk = fp.d_blk + s0;
+  f.d_colpanel = fp.d_colpanel + s0;
+  f.d_pstart = fp.d_pstart + s0;
+  f.d_snap = fp.d_snap + s0;
+  f.d_ipiv = fp.d_ipiv + s0;
+  f.d_state = fp.d_state + s0;
+  f.d_inertia = fp.d_inertia + 3 * (size_t)s0;
+  f.d_Lp = fp.d_Lp ? fp.d_Lp + s0 : nullptr;
+  f.d_aux = fp.d_aux ? fp.d_aux + s0 : nullptr;
+  return f;
+}
+
+// One panel step of every shift of `fp` on stream `st`: the speculative
+// pivot-free panel, the pivoting panel and the trailing update.  k0_lb is a lower
+// bound on the step's first column (it sizes the update grid).  `after_panel`,
+// when given, is recorded once the pivoting panel is enqueued.
+static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislice_handle* ph,
+                        hipEvent_t after_panel) {
+  const int n = fp.n, S = fp.nshift, nb = fp.nb;
+  const int nbpiv = fp.fast ? fp.nbpiv : nb;
+  const int min_kb = factor_min_panel(nb, fp.nbpiv, fp.fast != 0);
+  if (fp.fast) {
+    const int tf = prof_begin(ph, kProfPanel, st);
+    const long rows = n - k0_lb - 1;
+    if (nb > 32) {
+      SL_LAUNCH(k_fast_diag4<64>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
+                fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+      SL_LAUNCH_CHECK();
+      if (rows > 0) {
+        SL_LAUNCH(k_fast_trsm<64>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                  fp.d_state, nb);
+        SL_LAUNCH_CHECK();
+      }
+    } else {
+      SL_LAUNCH(k_fast_diag4<32>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
+                fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+      SL_LAUNCH_CHECK();
+      if (rows > 0) {
+        SL_LAUNCH(k_fast_trsm<32>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
+                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                  fp.d_state, nb);
+        SL_LAUNCH_CHECK();
+      }
+    }
+    if (fp.pivot)
+      SL_LAUNCH(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+                (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
+                fp.d_colpanel, fp.d_state, nb);
+    else
+      SL_LAUNCH(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
+                (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
+                fp.d_colpanel, fp.d_state, nb);
+    SL_LAUNCH_CHECK();
+    prof_end(ph, tf, st);
+  }
+  const int tp = prof_begin(ph, kProfPanel, st);
+  if (fp.pivot)
+    SL_LAUNCH(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
+              fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart, fp.d_state, nb, nbpiv);
+  else
+    SL_LAUNCH(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
+              fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart, fp.d_state, nb, nbpiv);
+  SL_LAUNCH_CHECK();
+  prof_end(ph, tp, st);
+  if (after_panel) SL_HIP(hipEventRecord(after_panel, st));
+  const long k1_lb = std::min<long>(n, k0_lb + min_kb);
+  if (k1_lb >= n) return;
+  const int tu = prof_begin(ph, kProfUpdate, st);
+  if (n - k1_lb >= fp.wide_min && fp.update_pipe && pipe_fits(fp)) {
+    // one workgroup per CU, at most one per item (an upper bound on the items
+    // from the least advanced shift), a multiple of the 8 XCDs when it can be
+    const long T = ceil_div(n - k1_lb, 128);
+    long G = std::min<long>(std::max(fp.cus, 8), T * (T + 1) / 2 * S);
+    if (G >= 8) G -= G % 8;
+    SL_LAUNCH(k_trailing_update_pipe, dim3((unsigned)G), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
+              fp.d_W, fp.ldw, fp.d_state, S);
+  } else if (n - k1_lb >= fp.wide_min) {
+    const long T = ceil_div(n - k1_lb, 128);
+    SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st, n,
+              fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+  } else {
+    const long T = ceil_div(n - k1_lb, 64);
+    SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
+              fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+  }
+  SL_LAUNCH_CHECK();
+  prof_end(ph, tu, st);
+}
+
+// The deferred interchanges and the inertia of every shift of `fp`.
+static void factor_tail(const FactorPlan& fp, hipStream_t st) {
+  const int n = fp.n, S = fp.nshift;
+  if (fp.pivot) {
+    SL_LAUNCH(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
+              fp.d_pstart, fp.d_state, fp.d_snap);
+    SL_LAUNCH_CHECK();
+    SL_LAUNCH(k_left_gather, dim3(n, S), dim3(1024), (size_t)n * sizeof(double), st, n, fp.d_LD,
+              fp.ldld, fp.d_colpanel, fp.d_pstart, fp.d_state, fp.d_snap);
+    SL_LAUNCH_CHECK();
+  }
+  SL_LAUNCH(k_factor_finalize, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n, fp.d_perm,
+            fp.d_blk, fp.d_ipiv, fp.d_state, fp.d_inertia);
+  SL_LAUNCH_CHECK();
 }
 
 void factor_steps_launch(const FactorPlan& fp, hipStream_t st, bool readback) {
@@ -977,102 +1355,79 @@ void factor_steps_launch(const FactorPlan& fp, hipStream_t st, bool readback) {
                      fp.d_state, fp.d_perm, fp.d_sw);
   SL_LAUNCH_CHECK();
   sislice_handle* ph = current_handle();
-  const int nbpiv = fp.fast ? fp.nbpiv : nb;
   const int min_kb = factor_min_panel(nb, fp.nbpiv, fp.fast != 0);
-  // Panel widths depend on the pivots: launch chunks of panel steps and read the
-  // per-shift progress back between chunks (kmin = least factored prefix).
-  // Without readback (a sequence captured into a graph) every step up to the
-  // bound is launched; steps past a shift's end return at once.
   const int step_cap = factor_npanel_max(n, nb, fp.nbpiv, fp.fast != 0);
-  const int kChunk = readback ? 8 : step_cap;
-  FactorState* hs =
-      readback ? static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S)) : nullptr;
-  long kmin = 0;
-  int steps = 0;
   SL_CHECK_ARG(step_cap <= fp.npmax, "panel bookkeeping smaller than the step bound");
-  while (kmin < n && steps < step_cap) {
-    for (int q = 0; q < kChunk && steps < step_cap; ++q, ++steps) {
-      // lower bound of this step's first column: kmin + q * min_kb
-      const long k0_lb = std::min<long>(n, kmin + (long)q * min_kb);
-      if (fp.fast) {
-        const int tf = prof_begin(ph, kProfPanel);
-        const long rows = n - k0_lb - 1;
-        if (nb > 32) {
-          SL_LAUNCH(k_fast_diag4<64>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
-                    fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
-          SL_LAUNCH_CHECK();
-          if (rows > 0) {
-            SL_LAUNCH(k_fast_trsm<64>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
-                      (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
-                      fp.d_state, nb);
-            SL_LAUNCH_CHECK();
-          }
-        } else {
-          SL_LAUNCH(k_fast_diag4<32>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
-                    fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
-          SL_LAUNCH_CHECK();
-          if (rows > 0) {
-            SL_LAUNCH(k_fast_trsm<32>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
-                      (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
-                      fp.d_state, nb);
-            SL_LAUNCH_CHECK();
-          }
-        }
-        if (fp.pivot)
-          SL_LAUNCH(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
-                             (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
-                             fp.d_blk, fp.d_colpanel, fp.d_state, nb);
-        else
-          SL_LAUNCH(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
-                             (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux,
-                             fp.d_blk, fp.d_colpanel, fp.d_state, nb);
-        SL_LAUNCH_CHECK();
-        prof_end(ph, tf);
+  if (!readback) {
+    // a fixed sequence (for graph capture): every step up to the bound; steps
+    // past a shift's end return at once
+    for (int q = 0; q < step_cap; ++q)
+      factor_step(fp, st, std::min<long>(n, (long)q * min_kb), ph, nullptr);
+    factor_tail(fp, st);
+    return;
+  }
+  // Panel widths depend on the pivots: launch chunks of steps and read the
+  // per-shift progress back between chunks (kmin = least factored prefix of a
+  // group).  The shifts run in G groups, each on its own stream, so that the
+  // latency-bound panels of one group run while another group's updates use the
+  // memory system; group g + 1 starts once group g's first pivoting panel is
+  // enqueued, which staggers the groups by about one panel.
+  const int G = ph ? std::max(1, std::min(fp.groups, S / 2)) : 1;
+  std::vector<FactorPlan> sub(G);
+  std::vector<hipStream_t> gs(G);
+  std::vector<long> kmin(G, 0);
+  std::vector<int> steps(G, 0);
+  std::vector<char> launched(G, 0);
+  for (int g = 0; g < G; ++g) {
+    const int s0 = (int)((long)S * g / G), s1 = (int)((long)S * (g + 1) / G);
+    sub[g] = factor_subplan(fp, s0, s1 - s0);
+    // a persistent update would hold every CU for its whole launch and keep the
+    // other groups' panels waiting: grouped runs take the workgroup-per-tile form
+    if (G > 1) sub[g].update_pipe = 0;
+    gs[g] = g == 0 ? st : group_stream(ph, g - 1);
+  }
+  FactorState* hs = static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S));
+  if (G > 1) {
+    if (ph->flush_fn) ph->flush_fn(ph->flush_ctx);  // staged tables reach the device first
+    SL_HIP(hipEventRecord(group_event(ph, 0), st));
+    for (int g = 1; g < G; ++g) SL_HIP(hipStreamWaitEvent(gs[g], group_event(ph, 0), 0));
+  }
+  constexpr int kChunk = 8;
+  for (bool first = true;; first = false) {
+    bool any = false;
+    for (int g = 0; g < G; ++g) {
+      launched[g] = kmin[g] < n && steps[g] < step_cap;
+      if (!launched[g]) continue;
+      any = true;
+      for (int q = 0; q < kChunk && steps[g] < step_cap; ++q, ++steps[g]) {
+        hipEvent_t mark = (first && q == 0 && g + 1 < G) ? group_event(ph, g + 1) : nullptr;
+        factor_step(sub[g], gs[g], std::min<long>(n, kmin[g] + (long)q * min_kb), ph, mark);
+        if (mark) SL_HIP(hipStreamWaitEvent(gs[g + 1], mark, 0));
       }
-      const int tp = prof_begin(ph, kProfPanel);
-      if (fp.pivot)
-        SL_LAUNCH(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W,
-                           fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart,
-                           fp.d_state, nb, nbpiv);
-      else
-        SL_LAUNCH(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld,
-                           fp.d_W, fp.ldw, fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel,
-                           fp.d_pstart, fp.d_state, nb, nbpiv);
-      SL_LAUNCH_CHECK();
-      prof_end(ph, tp);
-      const long k1_lb = std::min<long>(n, k0_lb + min_kb);
-      if (k1_lb >= n) continue;
-      const int tu = prof_begin(ph, kProfUpdate);
-      if (n - k1_lb >= fp.wide_min) {
-        const long T = ceil_div(n - k1_lb, 128);
-        SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st, n,
-                  fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
-      } else {
-        const long T = ceil_div(n - k1_lb, 64);
-        SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
-                  fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
-      }
-      SL_LAUNCH_CHECK();
-      prof_end(ph, tu);
+      const FactorPlan& f = sub[g];
+      SL_HIP(hipMemcpyAsync(hs + (f.d_state - fp.d_state), f.d_state, sizeof(FactorState) * f.nshift,
+                            hipMemcpyDeviceToHost, gs[g]));
     }
-    if (!readback) break;
-    SL_HIP(hipMemcpyAsync(hs, fp.d_state, sizeof(FactorState) * S, hipMemcpyDeviceToHost, st));
-    SL_HIP(hipStreamSynchronize(st));
-    kmin = n;
-    for (int q = 0; q < S; ++q) kmin = std::min<long>(kmin, hs[q].done ? n : hs[q].k0 + hs[q].kb);
+    if (!any) break;
+    for (int g = 0; g < G; ++g) {
+      if (!launched[g]) continue;
+      SL_HIP(hipStreamSynchronize(gs[g]));
+      const FactorPlan& f = sub[g];
+      const FactorState* h0 = hs + (f.d_state - fp.d_state);
+      long km = n;
+      for (int q = 0; q < f.nshift; ++q) km = std::min<long>(km, h0[q].done ? n : h0[q].k0 + h0[q].kb);
+      kmin[g] = km;
+    }
   }
-  SL_CHECK_ARG(!readback || kmin >= n, "factorization did not complete");
-  if (fp.pivot) {
-    SL_LAUNCH(k_perm_suffix, dim3(S), dim3(256), (size_t)n * sizeof(int), st, n, fp.d_sw,
-                       fp.d_pstart, fp.d_state, fp.d_snap);
-    SL_LAUNCH_CHECK();
-    SL_LAUNCH(k_left_gather, dim3(n, S), dim3(256), (size_t)n * sizeof(double), st, n,
-                       fp.d_LD, fp.ldld, fp.d_colpanel, fp.d_pstart, fp.d_state, fp.d_snap);
-    SL_LAUNCH_CHECK();
+  for (int g = 0; g < G; ++g)
+    SL_CHECK_ARG(kmin[g] >= n, "factorization did not complete");
+  for (int g = 0; g < G; ++g) factor_tail(sub[g], gs[g]);
+  if (G > 1) {
+    for (int g = 1; g < G; ++g) {
+      SL_HIP(hipEventRecord(group_event(ph, g), gs[g]));
+      SL_HIP(hipStreamWaitEvent(st, group_event(ph, g), 0));
+    }
   }
-  SL_LAUNCH(k_factor_finalize, dim3((unsigned)ceil_div(n, 256), S), dim3(256), 0, st, n,
-                     fp.d_perm, fp.d_blk, fp.d_ipiv, fp.d_state, fp.d_inertia);
-  SL_LAUNCH_CHECK();
 }
 
 }  // namespace sislice

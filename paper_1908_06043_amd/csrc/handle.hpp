@@ -8,6 +8,7 @@
 
 struct sislice_handle {
   int device = 0;
+  int cus = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   hipEvent_t ev[8] = {};
   struct Buf {
@@ -62,6 +63,11 @@ struct sislice_handle {
   // and the factorization parameters chosen by the autotuner per order n.
   std::vector<sislice_handle*> workers;
   std::vector<hipStream_t> worker_streams;  // created by the library, owned
+  // Extra streams of a factorization run in shift groups (created by the
+  // library, owned) and the events that fork them from and join them to the
+  // handle's stream.
+  std::vector<hipStream_t> group_streams;
+  std::vector<hipEvent_t> group_events;
   struct FactorTune {
     int nb = 0, nbpiv = 0, wide_min = 0;
   };
@@ -148,8 +154,14 @@ inline unsigned next_epoch(sislice_handle* h) { return ++h->epoch; }
 // handle's stream and returns a ticket; prof_end records the closing event.
 // prof_collect (after a stream synchronisation) sums durations per class.
 enum ProfCat { kProfPanel = 0, kProfUpdate = 1, kProfSolve = 2, kProfGemm = 3, kProfEig = 4, kProfOther = 5 };
-int prof_begin(sislice_handle* h, int cat);
-void prof_end(sislice_handle* h, int ticket);
+// With a stream argument the events go on that stream (work launched on a
+// stream other than the handle's).
+int prof_begin(sislice_handle* h, int cat, hipStream_t on = nullptr);
+void prof_end(sislice_handle* h, int ticket, hipStream_t on = nullptr);
+// The handle's g-th group stream (non-blocking, default priority; created on
+// first use) and its g-th fork/join event.
+hipStream_t group_stream(sislice_handle* h, int g);
+hipEvent_t group_event(sislice_handle* h, int g);
 void prof_collect(sislice_handle* h, double* ms, int64_t* count);
 void prof_reset(sislice_handle* h);
 

@@ -37,6 +37,9 @@ struct FactorPlan {
   int fast = 1;                    // use the pivot-free path
   int nbpiv = 32;                  // columns a pivoting panel handles after a rejection
   int wide_min = 1024;             // trailing order from which the update takes 128x128 tiles
+  int update_pipe = 1;             // 128x128 updates by the persistent pipelined kernel
+  int cus = 256;                   // compute units of the device (its persistent grid)
+  int groups = 1;                  // shift groups run on separate streams (with readback)
 };
 
 // The whole factorization: shift-form, then the panel/update steps with the
