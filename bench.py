@@ -300,6 +300,49 @@ def planner_leg(api, A, B, n_e, n_s, reps=2):
     return out
 
 
+def factor_leg(api, inputs, torch, n=12288, n_s=48, reps=3, cache=None):
+    """The lock-step Bunch-Kaufman factorization alone at the SCF size: the pencil of
+    the SCF sequence (n_e = n/10.24), its n_s KPM shifts and the top boundary, i.e.
+    n_s + 1 factorizations of order n per call (shift-form, LDL^T, inertia; the
+    factors go to caller-owned buffers).  Rate = (n_s + 1) n^3/3 flops over the mean
+    of `reps` calls after one untimed call; the inertias are compared with the
+    construction's eigenvalue counts.  `cache` (a directory) keeps the pencil as .npy
+    files: a run that finds them loads them instead of building the pencil (a run
+    under a counter-collecting profiler then avoids the construction's library
+    calls)."""
+    import numpy as np
+    n_e = n * 1200 // 12288
+    names = [os.path.join(cache, f"pencil{n}_{x}.npy") for x in ("A", "B", "lam")] if cache else []
+    if names and all(os.path.exists(f) for f in names):
+        A = torch.from_numpy(np.load(names[0])).cuda()
+        B = torch.from_numpy(np.load(names[1])).cuda()
+        lam = np.load(names[2])
+    else:
+        A, B, lam = inputs.make_pencil_device(
+            n, lambda r, m: inputs.spectrum_scf(r, m, n_e, forced_gap_at=n_e, forced_gap=0.05), 0, "cuda")
+        if names:
+            os.makedirs(cache, exist_ok=True)
+            for f, x in zip(names, (A.cpu().numpy(), B.cpu().numpy(), lam)):
+                np.save(f, x)
+    plan = api.plan_shifts_kpm(A, B, n_e, n_s)
+    pts = [float(x) for x in plan["sigmas"]] + [float(plan["omega_top"])]
+    times = []
+    ok = True
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fs = api.ldlt_factor_multi(A, B, pts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        ok = ok and all(f.inertia[0] == int(np.sum(lam < p)) for f, p in zip(fs, pts))
+        del fs
+    ms = 1e3 * float(np.mean(times[1:]))
+    flops = len(pts) * float(n) ** 3 / 3.0
+    return {"workload": f"{len(pts)} factorizations of order {n} (SCF pencil, {n_s} KPM shifts + top boundary)",
+            "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12, "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_FP64,
+            "inertia_matches_construction": bool(ok), "reps": reps}
+
+
 def scf_leg(api, inputs, torch, n=12288, n_e=1200, n_s=48, steps=10, driver=0, gradient=True):
     """SCF-shaped sequence A_k = A_{k-1} + E_k (||E_k||_2 = 1e-3, B fixed; the spectrum with
     a gap of 0.05 above lambda_{n_e} so that the density loss is defined): every step
@@ -376,6 +419,12 @@ def main():
     ap.add_argument("--no-planners", action="store_true", help="skip the planner comparison")
     ap.add_argument("--no-scf", action="store_true", help="skip the SCF-sequence leg")
     ap.add_argument("--scf-n", type=int, default=12288)
+    ap.add_argument("--factor-only", action="store_true",
+                    help="time only the lock-step factorization at the SCF size (--scf-n, 48 shifts + "
+                         "the top boundary) and print its own JSON line")
+    ap.add_argument("--pencil-cache", default=None,
+                    help="with --factor-only: directory where the pencil is saved on the first run "
+                         "and loaded from on later runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the steps, fill a 2 GiB buffer and copy it with one elementwise kernel "
                          "(reads and writes 2 GiB, beyond the last-level cache): the reference that "
@@ -394,6 +443,11 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 2
+    if args.factor_only:
+        ns = max(8, 48 * args.scf_n // 12288)
+        print(json.dumps({"factor": factor_leg(api, inputs, torch, n=args.scf_n, n_s=ns,
+                                               cache=args.pencil_cache)}), flush=True)
+        return 0
     n, n_e, n_s = args.n, args.ne, args.ns
     P = inputs.pencil_scf(n, n_e, seed=0)
     A = torch.from_numpy(P.A).cuda()
@@ -494,7 +548,14 @@ def main():
         torch.cuda.synchronize()
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        line["calibration_copy_bytes"] = {"read": src.numel() * 8, "written": dst.numel() * 8}
+        # the same copy timed: the read + write bandwidth that a streaming kernel gets
+        t0 = time.perf_counter()
+        for _ in range(5):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        line["calibration_copy_bytes"] = {"read": src.numel() * 8, "written": dst.numel() * 8,
+                                          "read_plus_write_GBps": 2 * src.numel() * 8 / dt / 1e9}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(P, state["prev"], n_e, n_s)
     print(json.dumps(line), flush=True)
