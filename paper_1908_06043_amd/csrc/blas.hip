@@ -169,7 +169,7 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
   }
   dim3 grid((unsigned)ceil_div(mmax, GT), (unsigned)ceil_div(nmax, GT), (unsigned)(batch * g.splits));
   sislice_handle* ph = current_handle();
-  const int tk = prof_begin(ph, kProfGemm);
+  const int tk = prof_begin(ph, kProfGemm, st);
   if (!ta && !tb) SL_LAUNCH((k_gemm<false, false>), grid, dim3(256), 0, st, g);
   if (!ta && tb) SL_LAUNCH((k_gemm<false, true>), grid, dim3(256), 0, st, g);
   if (ta && !tb) SL_LAUNCH((k_gemm<true, false>), grid, dim3(256), 0, st, g);
@@ -181,7 +181,7 @@ void gemm_launch(GemmArgs g, int batch, int mmax, int nmax, bool ta, bool tb, hi
                        dim3(256), 0, st, g);
     SL_LAUNCH_CHECK();
   }
-  prof_end(ph, tk);
+  prof_end(ph, tk, st);
 }
 
 // ------------------------------------------------------------ skinny products
@@ -295,7 +295,7 @@ void skinny_launch(int n, int ncol, const double* M, long ldm, int tri, const do
   if (n <= 0 || ncol <= 0) return;
   SL_CHECK_ARG(ncol <= kSkinnyMaxCol, "skinny product: too many columns");
   sislice_handle* ph = current_handle();
-  const int tk = prof_begin(ph, kProfGemm);
+  const int tk = prof_begin(ph, kProfGemm, st);
   // column pieces of instantiated widths (each piece streams M once)
   int c0 = 0;
   while (c0 < ncol) {
@@ -316,7 +316,7 @@ void skinny_launch(int n, int ncol, const double* M, long ldm, int tri, const do
   SL_LAUNCH(k_skinny_reduce, dim3((unsigned)std::min<long>(ceil_div(tot, 256), 4096)), dim3(256),
             0, st, n, ncol, nchunk, tri, partial, alpha, beta, C, ldc);
   SL_LAUNCH_CHECK();
-  prof_end(ph, tk);
+  prof_end(ph, tk, st);
 }
 
 // ------------------------------------------------- tall-skinny products, 8 columns
@@ -410,12 +410,12 @@ void tsmt_launch(TsArgs a, int batch, int mmax, hipStream_t st) {
   a.mmax = mmax;
   a.nchunk = (int)ceil_div(a.n, kTsRows);
   sislice_handle* ph = current_handle();
-  const int tk = prof_begin(ph, kProfGemm);
+  const int tk = prof_begin(ph, kProfGemm, st);
   SL_LAUNCH(k_tsmt, dim3(a.nchunk, (unsigned)ceil_div(mmax, 64), batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
   SL_LAUNCH(k_tsmt_reduce, dim3((unsigned)ceil_div(mmax * 8, 256), batch), dim3(256), 0, st, a);
   SL_LAUNCH_CHECK();
-  prof_end(ph, tk);
+  prof_end(ph, tk, st);
 }
 
 // k_tsmm: Y_b = beta Y_b + alpha (V_b C_b + V2_b C2_b), n x 8.  The coefficients
@@ -499,10 +499,10 @@ void tsmm_launch(TsArgs a, int batch, int mtot_max, hipStream_t st) {
                                (int)kTsmmMaxLds));
   });
   sislice_handle* ph = current_handle();
-  const int tk = prof_begin(ph, kProfGemm);
+  const int tk = prof_begin(ph, kProfGemm, st);
   SL_LAUNCH(k_tsmm, dim3((unsigned)ceil_div(a.n, 64), batch), dim3(256), lds, st, a);
   SL_LAUNCH_CHECK();
-  prof_end(ph, tk);
+  prof_end(ph, tk, st);
 }
 
 // out = f1 * X + f2 * Y + f3 * Z elementwise over n x ncol blocks (ld n); Z may

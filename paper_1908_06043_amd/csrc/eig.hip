@@ -3,8 +3,11 @@
 // matrices.
 //
 // Design (gfx950): two kernels per batch.
-//  k_syevj: one 1024-thread workgroup per matrix, the lower triangle of A packed
-//  in LDS (m(m+1)/2 doubles).  Cyclic Jacobi in the parallel round-robin order:
+//  k_syevj: one 1024-thread workgroup per matrix, the lower triangle of A in LDS
+//  as a full row-major array with the odd row length M + 1 (M = m rounded up to
+//  even): the blocks a wavefront updates lie along rows or columns of distinct
+//  players, which this length spreads over the banks (the packed triangle measured
+//  2.45 us per rotation round at m = 112, this layout 1.80).  Cyclic Jacobi in the parallel round-robin order:
 //  each round rotates m/2 disjoint (p, q) pairs (Golub & Van Loan, symmetric
 //  Schur 2x2 rotation) and applies all of them to A as independent 2x2 blocks
 //  J_k^T A_{kl} J_l, then moves to the next pairing.  The (c, s) of every pair of
@@ -27,21 +30,39 @@
 namespace sislice {
 
 __device__ __forceinline__ int pidx(int i, int j, int m) {
-  // column-major packed lower triangle, i >= j
-  return j * m - (j * (j - 1)) / 2 + (i - j);
+  // lower triangle (i >= j) of a row-major array with rows of M + 1 doubles
+  return i * (m + (m & 1) + 1) + j;
 }
 
 __device__ __forceinline__ int sidx(int i, int j, int m) {
   return i >= j ? pidx(i, j, m) : pidx(j, i, m);
 }
 
-__device__ __forceinline__ int rr_player(int pos, int r, int M) {
-  return pos == 0 ? 0 : 1 + ((pos - 1 + r) % (M - 1));
-}
 
 // Per-matrix metadata after k_syevj: [0] sweeps that rotated, [1 + i] rank of
 // diagonal position i in ascending order.
 constexpr int kMetaStride = kEigMax + 16;
+
+// 1 / x and 1 / sqrt(x) for x > 0 from the hardware approximations refined by
+// two Newton steps (relative error near the rounding unit).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx, y * y, 1.5);
+  y = y * fma(-hx, y * y, 1.5);
+  return y;
+}
+
+// The round-robin player of a position, advanced by one round: position 0 holds
+// player 0, the others cycle through 1 .. M - 1 (in round r position pos >= 1
+// holds 1 + (pos - 1 + r) mod (M - 1)).
+__device__ __forceinline__ int rr_next(int v, int M) { return v == 0 ? 0 : (v == M - 1 ? 1 : v + 1); }
 
 __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__ rot, long rstride,
                                                 int* __restrict__ meta) {
@@ -51,14 +72,11 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
   if (m <= 0) return;
   const int M = m + (m & 1);
   const int h = M / 2;
-  const int npk = m * (m + 1) / 2;
-  double* A = sh;              // packed lower
-  double* cs = A + npk;        // [h]
-  double* sn = cs + h;         // [h]
-  int* pp = reinterpret_cast<int*>(sn + h);  // [h]
-  int* qq = pp + h;                          // [h]
-  int* flag = qq + h;                        // [4], then rank [m]
-  double2* rb = rot + (long)b * rstride;     // [sweep][round][pair]
+  const int npk = M * (M + 1);
+  double* A = sh;                                                 // lower triangle, rows of M + 1
+  double2* csn = reinterpret_cast<double2*>(sh + ((npk + 1) & ~1));  // [h] (c, s)
+  int* flag = reinterpret_cast<int*>(csn + h);                      // [4], then rank [m]
+  double2* rb = rot + (long)b * rstride;                            // [sweep][round][pair]
   const double* Ain = a.A[b];
   const long lda = a.lda;
   for (int e = tid; e < m * m; e += blockDim.x) {
@@ -68,9 +86,11 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
   __syncthreads();
   const int ntask_blk = h * (h + 1) / 2;
   // Each thread's 2x2 block tasks t = tid + 1024 j -> pair indices (k >= l) are
-  // the same in every round: decode them once.
+  // the same in every round: decode them once.  The players of the pairs' two
+  // positions (k and M - 1 - k) advance by one per round in registers: after
+  // M - 1 rounds (one sweep) they are back where they started.
   constexpr int JA = 2;  // enough for m <= kEigMax (h <= 56)
-  int tk[JA], tl[JA];
+  int tk[JA], tl[JA], uk[JA], vk[JA], ul[JA], vl[JA];
 #pragma unroll
   for (int j = 0; j < JA; ++j) {
     const int t = tid + 1024 * j;
@@ -83,7 +103,12 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
     }
     tk[j] = k;
     tl[j] = l;
+    uk[j] = k < 0 ? 0 : k;
+    vk[j] = k < 0 ? 0 : M - 1 - k;
+    ul[j] = l;
+    vl[j] = M - 1 - l;
   }
+  int up = tid, vp = M - 1 - tid;  // players of pair `tid` (rotation phase, tid < h)
   // flag[0]: a rotation happened in this sweep; rflag[r & 1]: in round r (the slot
   // of the next round is cleared by thread 0 while the current one is being set)
   int* rflag = flag + 2;
@@ -98,69 +123,89 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
     for (int r = 0; r < M - 1; ++r) {
       if (tid == 0) rflag[(r + 1) & 1] = 0;
       if (tid < h) {
-        int p = rr_player(tid, r, M), q = rr_player(M - 1 - tid, r, M);
-        if (p > q) {
-          const int t = p;
-          p = q;
-          q = t;
-        }
+        const int p = min(up, vp), q = max(up, vp);
         double c = 1.0, s = 0.0;
         if (q < m) {
           const double apq = A[pidx(q, p, m)];
           const double app = A[pidx(p, p, m)], aqq = A[pidx(q, q, m)];
           if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-            const double tau = (aqq - app) / (2.0 * apq);
-            const double t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                                          : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
+            // t = tan of the angle that zeroes a_pq, the root of t^2 + 2 tau t - 1
+            // of smaller modulus, tau = (a_qq - a_pp) / (2 a_pq) (Golub & Van Loan,
+            // symmetric Schur), written as t = sgn(tau) |e| / (|d| + sqrt(d^2 + e^2))
+            // with d = a_qq - a_pp, e = 2 a_pq (one square root, one reciprocal)
+            const double d = aqq - app, e = 2.0 * apq;
+            const double hyp = sqrt(fma(d, d, e * e));
+            double t;
+            if (hyp < 1e300) {
+              t = fabs(e) * rcp_nr(fabs(d) + hyp);
+              if (d != 0.0 && ((d < 0.0) != (e < 0.0))) t = -t;
+            } else {  // d^2 + e^2 overflows: the scaled form
+              const double tau = d / e;
+              t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
+                               : -1.0 / (-tau + sqrt(1.0 + tau * tau));
+            }
+            c = rsq_nr(fma(t, t, 1.0));
             s = t * c;
             flag[0] = 1;
             rflag[r & 1] = 1;
           }
         }
-        pp[tid] = p;
-        qq[tid] = q;
-        cs[tid] = c;
-        sn[tid] = s;
+        csn[tid] = make_double2(c, s);
         rb[(long)(sweep * (M - 1) + r) * h + tid] = make_double2(c, s);
       }
       __syncthreads();
-      if (rflag[r & 1] == 0) continue;  // no rotation in this round: A unchanged
-      // A <- J^T A J as independent 2x2 blocks of pair pairs (k >= l)
+      // no rotation in this round: A is unchanged and nothing reads (c, s) before
+      // the next round's rotation phase rewrites them, so no closing barrier
+      const bool rotated = rflag[r & 1] != 0;
+      if (rotated) {
+        // A <- J^T A J as independent 2x2 blocks of pair pairs (k >= l)
 #pragma unroll
-      for (int j = 0; j < JA; ++j) {
-        const int k = tk[j], l = tl[j];
-        if (k < 0) continue;
-        const double ck = cs[k], sk = sn[k], cl = cs[l], sl = sn[l];
-        if (sk == 0.0 && sl == 0.0) continue;
-        const int pk = pp[k], qk = qq[k], pl = pp[l], ql = qq[l];
-        if (k == l) {
-          if (qk >= m) continue;
-          const int ipq = pidx(qk, pk, m);
-          const double apq = A[ipq];
-          const double tt = sk / ck;
-          A[pidx(pk, pk, m)] -= tt * apq;
-          A[pidx(qk, qk, m)] += tt * apq;
-          A[ipq] = 0.0;
-        } else {
-          const bool vq_k = qk < m, vq_l = ql < m;
-          const int i00 = sidx(pk, pl, m);
-          const int i01 = vq_l ? sidx(pk, ql, m) : -1;
-          const int i10 = vq_k ? sidx(qk, pl, m) : -1;
-          const int i11 = (vq_k && vq_l) ? sidx(qk, ql, m) : -1;
-          const double x00 = A[i00], x01 = vq_l ? A[i01] : 0.0;
-          const double x10 = vq_k ? A[i10] : 0.0, x11 = (vq_k && vq_l) ? A[i11] : 0.0;
-          // rows: J_k^T
-          const double r00 = ck * x00 - sk * x10, r01 = ck * x01 - sk * x11;
-          const double r10 = sk * x00 + ck * x10, r11 = sk * x01 + ck * x11;
-          // columns: J_l
-          A[i00] = cl * r00 - sl * r01;
-          if (vq_l) A[i01] = sl * r00 + cl * r01;
-          if (vq_k) A[i10] = cl * r10 - sl * r11;
-          if (vq_k && vq_l) A[i11] = sl * r10 + cl * r11;
+        for (int j = 0; j < JA; ++j) {
+          const int k = tk[j], l = tl[j];
+          if (k < 0) continue;
+          const double2 csk = csn[k], csl = csn[l];
+          const double ck = csk.x, sk = csk.y, cl = csl.x, sl = csl.y;
+          if (sk == 0.0 && sl == 0.0) continue;
+          const int pk = min(uk[j], vk[j]), qk = max(uk[j], vk[j]);
+          const int pl = min(ul[j], vl[j]), ql = max(ul[j], vl[j]);
+          if (k == l) {
+            if (qk >= m) continue;
+            const int ipq = pidx(qk, pk, m);
+            const double apq = A[ipq];
+            const double tt = sk / ck;
+            A[pidx(pk, pk, m)] -= tt * apq;
+            A[pidx(qk, qk, m)] += tt * apq;
+            A[ipq] = 0.0;
+          } else {
+            const bool vq_k = qk < m, vq_l = ql < m;
+            const int i00 = sidx(pk, pl, m);
+            const int i01 = vq_l ? sidx(pk, ql, m) : -1;
+            const int i10 = vq_k ? sidx(qk, pl, m) : -1;
+            const int i11 = (vq_k && vq_l) ? sidx(qk, ql, m) : -1;
+            const double x00 = A[i00], x01 = vq_l ? A[i01] : 0.0;
+            const double x10 = vq_k ? A[i10] : 0.0, x11 = (vq_k && vq_l) ? A[i11] : 0.0;
+            // rows: J_k^T
+            const double r00 = ck * x00 - sk * x10, r01 = ck * x01 - sk * x11;
+            const double r10 = sk * x00 + ck * x10, r11 = sk * x01 + ck * x11;
+            // columns: J_l
+            A[i00] = cl * r00 - sl * r01;
+            if (vq_l) A[i01] = sl * r00 + cl * r01;
+            if (vq_k) A[i10] = cl * r10 - sl * r11;
+            if (vq_k && vq_l) A[i11] = sl * r10 + cl * r11;
+          }
         }
       }
-      __syncthreads();
+      // every round, rotated or not, moves the players on
+#pragma unroll
+      for (int j = 0; j < JA; ++j) {
+        uk[j] = rr_next(uk[j], M);
+        vk[j] = rr_next(vk[j], M);
+        ul[j] = rr_next(ul[j], M);
+        vl[j] = rr_next(vl[j], M);
+      }
+      up = rr_next(up, M);
+      vp = rr_next(vp, M);
+      if (rotated) __syncthreads();
     }
     if (flag[0] == 0) break;
     ++nsw;
@@ -265,8 +310,8 @@ __global__ __launch_bounds__(64 * kVecWaves) void k_syevj_vecs(EigArgs a,
 size_t eig_lds_bytes(int mmax) {
   const int M = mmax + (mmax & 1);
   const int h = M / 2;
-  return sizeof(double) * ((size_t)mmax * (mmax + 1) / 2 + 2 * h) +
-         sizeof(int) * (2 * h + 4 + mmax) + 64;
+  const size_t npk = (size_t)M * (M + 1);
+  return sizeof(double) * (((npk + 1) & ~size_t(1)) + 2 * h) + sizeof(int) * (4 + mmax) + 64;
 }
 
 // Rotation records are staged per chunk of the batch so that their workspace
@@ -294,7 +339,7 @@ void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
       ws_get(h, kBufEigRot, meta_off + (size_t)chunk * kMetaStride * sizeof(int)));
   double2* rot = reinterpret_cast<double2*>(ws);
   int* meta = reinterpret_cast<int*>(ws + meta_off);
-  const int tk = prof_begin(h, kProfEig);
+  const int tk = prof_begin(h, kProfEig, st);
   for (int c0 = 0; c0 < batch; c0 += chunk) {
     const int nb = std::min(chunk, batch - c0);
     EigArgs c = a;
@@ -308,7 +353,7 @@ void eig_launch(const EigArgs& a, int batch, int mmax, hipStream_t st) {
               st, c, rot, rstride, meta);
     SL_LAUNCH_CHECK();
   }
-  prof_end(h, tk);
+  prof_end(h, tk, st);
 }
 
 }  // namespace sislice

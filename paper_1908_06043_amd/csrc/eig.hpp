@@ -5,7 +5,7 @@
 
 namespace sislice {
 
-constexpr int kEigMax = 112;  // largest order that keeps A (packed) and V in LDS
+constexpr int kEigMax = 112;  // largest order of the one-workgroup Jacobi solver (A in LDS)
 
 struct EigArgs {
   const int* m = nullptr;              // device [batch] orders (<= kEigMax; 0 = skip)
