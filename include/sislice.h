@@ -491,11 +491,23 @@ uint64_t sislice_splitmix64(uint64_t seed, uint64_t i);
  * column-major with leading dimension lda, lower triangle read.  W device
  * double[batch*m] eigenvalues ascending; V device batch*(m x m) eigenvectors
  * (leading dimension m).  The rotations are recorded in a workspace of the
- * handle (about 4 MB per matrix of order 112, batches above 64 such matrices
- * are processed in chunks); it grows on the first call that needs more, and a
- * failed growth returns SISLICE_ERR_ALLOC.  Asynchronous. */
+ * handle (about 4 MB per matrix of order 112, batches of more than 67 such
+ * matrices are processed in chunks); it grows on the first call that needs
+ * more, and a failed growth returns SISLICE_ERR_ALLOC.  Returns after the work
+ * has completed (the host staging of the per-matrix tables is reused). */
 sislice_status sislice_sym_eig(sislice_handle *h, int32_t m, int32_t batch, const double *A,
                                int64_t lda, double *W, double *V);
+
+/* The same solver for a batch of matrices of different orders, as the solve
+ * path launches it: matrix b, of order m[b] (host int32, 0 <= m[b] <= mmax <=
+ * 112; 0 skips it), is the leading m[b] x m[b] block at A + b*lda*mmax (device,
+ * column-major, leading dimension lda >= mmax, lower triangle read).  Its
+ * eigenvalues go to W + b*mmax (ascending) and its eigenvectors to
+ * V + b*mmax*mmax (leading dimension mmax, column j for eigenvalue j); entries
+ * past m[b] are not written.  Returns after the work has completed. */
+sislice_status sislice_sym_eig_var(sislice_handle *h, int32_t batch, const int32_t *m,
+                                   int32_t mmax, const double *A, int64_t lda, double *W,
+                                   double *V);
 
 #ifdef __cplusplus
 }

@@ -131,6 +131,8 @@ _SIGS = {
     "sislice_kpm_place": (C.c_int, [c_double_p, C.c_int32, C.c_double, C.c_double, C.c_int64,
                                     C.c_int64, C.c_int64, C.c_double, c_double_p, c_double_p]),
     "sislice_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+    "sislice_sym_eig_var": (C.c_int, [C.c_void_p, C.c_int32, c_int32_p, C.c_int32, C.c_void_p,
+                                      C.c_int64, C.c_void_p, C.c_void_p]),
     "sislice_sym_eig": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
                                   C.c_void_p, C.c_void_p]),
 }

@@ -137,6 +137,26 @@ def sym_eig(M):
     return (W[0], Vm[0]) if M.dim() == 2 else (W, Vm)
 
 
+def sym_eig_var(mats):
+    """Eigen-decompositions of a batch of small symmetric matrices of different orders
+    (a list of square tensors on one device, orders <= 112), in one launch.  Returns a
+    list of (W, V) with W ascending and V[:, j] the eigenvector of W[j]."""
+    orders = [int(x.shape[0]) for x in mats]
+    batch, mmax = len(mats), max(orders) if mats else 0
+    dev = mats[0].device
+    Ap = torch.zeros((batch, mmax, mmax), dtype=torch.float64, device=dev)
+    for b, x in enumerate(mats):
+        Ap[b, :orders[b], :orders[b]] = x.t()   # column-major blocks: Ap[b, j, i] = A_b(i, j)
+    W = torch.zeros((batch, mmax), dtype=torch.float64, device=dev)
+    V = torch.zeros((batch, mmax, mmax), dtype=torch.float64, device=dev)   # V[b, j, i] = vec j, comp i
+    m = np.ascontiguousarray(np.asarray(orders, dtype=np.int32))
+    lib = _lib.load()
+    st = lib.sislice_sym_eig_var(handle(dev.index), batch, m.ctypes.data_as(_lib.c_int32_p), mmax,
+                                 Ap.data_ptr(), mmax, W.data_ptr(), V.data_ptr())
+    _check(st, "sislice_sym_eig_var")
+    return [(W[b, :orders[b]], V[b, :orders[b], :orders[b]].t()) for b in range(batch)]
+
+
 def sisubit(A, B, sigma, V0, M):
     """The paper's Algorithm 2 from the start basis V0 (n x k): M shift-invert
     applications with CholeskyQR, then Rayleigh-Ritz.  Returns (evals, X, resid)."""
