@@ -193,10 +193,12 @@ def full():
 def test_full_size_gradient_and_central_differences(gpu_lib, full):
     # the adjoint workload (N = 2048, n_e = 200): the dense oracle gradient to 1e-6
     # relative, and central differences (h = 1e-6) of the GPU forward solve on 50
-    # symmetric directions.  At this size the differences are limited by the FP64
-    # rounding of the forward loss itself: a loss of magnitude
-    # C = sum lam^2 + n_e ||W||_2 carries noise of order u C, which the quotient
-    # divides by h; the bound adds 100 u C / h to the 1e-6 relative bar.
+    # symmetric directions.  At this size the differences are limited by the noise of
+    # the forward loss itself (its FP64 rounding and the solver's residual tolerance),
+    # which the quotient divides by h.  That noise is measured: the loss at the
+    # unperturbed pencil from three more Lanczos start seeds spreads by `noise`, and a
+    # central difference of two such evaluations errs by at most about noise / h; the
+    # bound adds 3 noise / h to the 1e-6 relative bar.
     api = gpu_lib
     P, sig, top, W = full
     n, n_e = P.n, 200
@@ -217,10 +219,21 @@ def test_full_size_gradient_and_central_differences(gpu_lib, full):
     assert rel_max(GA, RA) <= 1e-6 and rel_max(GB, RB) <= 1e-6
     h = 1e-6
     fd, an = _fd_directions(api, P, W, sig, out["omega_top"], n_e, (GA, GB), 50, 123, h)
+
+    def loss_seed(seed):
+        o = api.solve(A, B, n_e, len(sig), sigmas=sig, omega_top=out["omega_top"],
+                      opts=api.default_opts(tol=1e-12, seed=seed))
+        assert o["status"] == 0
+        l, x = o["evals"], o["evecs"]
+        return float((l ** 2).sum() + ((Wd @ x) * x).sum())
+
+    ls = [loss_seed(sd) for sd in (0, 1, 2, 3)]
+    noise = max(abs(v - ls[0]) for v in ls[1:])
     u = np.finfo(np.float64).eps / 2
     C = float(np.sum(lo ** 2) + n_e * np.linalg.norm(W, 2))
-    floor = 100 * u * C / h
+    floor = 3.0 * max(noise, u * C) / h
     err = np.abs(fd - an)
     print(f"central differences n=2048: relative error {np.linalg.norm(fd - an) / np.linalg.norm(an):.2e}, "
-          f"max abs {err.max():.2e}, rounding floor {floor:.2e}", flush=True)
+          f"max abs {err.max():.2e}; loss spread over seeds {noise:.2e} (u C = {u * C:.2e}), "
+          f"floor {floor:.2e}", flush=True)
     assert np.all(err <= 1e-6 * np.abs(an) + floor)
