@@ -68,6 +68,45 @@ def test_multi_shift_random_n1300_wide_update(gpu_lib):
         assert backward_error(Cs, f.LD.cpu().numpy(), f.ipiv.cpu().numpy()) <= 100 * n * U
 
 
+def test_heavy_pivoting_random_n2560_six_shifts(gpu_lib):
+    """A random symmetric matrix pivots on most columns: 2x2 pivots, interchanges and
+    pivoting panels throughout, ragged update ranks through the persistent 128x128
+    update (orders above 1024), six shifts in lock step."""
+    n = 2560
+    C = inputs.random_symmetric(n, 17)
+    w = np.linalg.eigvalsh(C)
+    sig = inputs.safe_shifts(w, np.quantile(w, [0.0, 0.1, 0.35, 0.5, 0.8, 1.0]) + [-0.5, 0, 0, 0, 0, 0.5])
+    facs = gpu_lib.ldlt_factor_multi(dev(C), dev(np.eye(n)), sig)
+    assert [f.inertia[0] for f in facs] == [int(np.sum(w < s)) for s in sig]
+    assert all(sum(f.inertia) == n and f.inertia[1] == 0 for f in facs)
+    for s, f in zip(sig[2:4], facs[2:4]):
+        LD, ip = f.LD.cpu().numpy(), f.ipiv.cpu().numpy()
+        assert backward_error(C - s * np.eye(n), LD, ip) <= 100 * n * U
+        L, D, perm, blocks = decode_factor(LD, ip)
+        assert inertia_of(D) == f.inertia
+        assert sum(1 for b in blocks if b == 2) > n // 20  # the 2x2 pivots are exercised
+
+
+def test_grouped_factorization_equals_lockstep_bitwise_n8192(gpu_lib):
+    """From order 8192 and 8 shifts the shifts run in two groups on two streams with
+    the workgroup-per-tile update; one shift alone runs in lock step with the
+    persistent pipelined update.  Both accumulate every element in the same order, so
+    the factors must agree bit for bit."""
+    n = 8192
+    C = inputs.random_symmetric(n, 19)
+    rng = np.random.default_rng(19)
+    sig = list(rng.uniform(-20.0, 20.0, 8))
+    A, I = dev(C), dev(np.eye(n))
+    facs = gpu_lib.ldlt_factor_multi(A, I, sig)
+    for s, f in zip(sig, facs):
+        g = gpu_lib.ldlt_factor(A, I, s)
+        assert g.inertia == f.inertia
+        assert torch.equal(g.ipiv, f.ipiv)
+        assert torch.equal(torch.tril(g.LD), torch.tril(f.LD))
+        del g
+    assert all(sum(f.inertia) == n and f.inertia[1] == 0 for f in facs)
+
+
 def test_pencil_n200_inertia_matches_construction_and_oracle(gpu_lib):
     P = inputs.pencil_clusters4(200, 0)
     sig = inputs.safe_shifts(P.lam, np.linspace(-2.1, 2.1, 15))
