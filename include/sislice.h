@@ -55,7 +55,10 @@ typedef struct {
   int32_t kpm_vectors;   /* Rademacher probe vectors (20)                                */
   int32_t bounds_steps;  /* Lanczos steps of the spectral-bounds estimate (30)           */
   int32_t nb;            /* factorization panel width (0 = library default)             */
-  int32_t profile;       /* 1: time kernel classes with HIP events into the report (0)  */
+  int32_t profile;       /* time kernel classes with HIP events into the report (0):   */
+                         /* 1 every class; 0x100 | m only the classes whose bit is set */
+                         /* in m (bit c: class c of t_kern_ms), e.g. to time one class */
+                         /* at a few events per step                                   */
   double tol;            /* residual ||Ax - lambda Bx|| / (||A||_2 ||x||) target (1e-10) */
   double top_margin;     /* top boundary at the CDOS root of n_e + top_margin*n_e/n_s (2) */
   uint64_t seed;         /* SplitMix64 seed of every random draw (0)                     */

@@ -558,6 +558,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
   set_current_handle(h);
   prof_reset(h);
   h->prof = o.profile != 0;
+  h->prof_mask = (o.profile & 0x100) ? (unsigned)(o.profile & 0x3F) : 0x3Fu;
   h->use_graphs = o.graphs != 0;
   const int b = kLanczosBlock;
   hipStream_t st = h->stream;

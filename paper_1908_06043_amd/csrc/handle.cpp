@@ -121,7 +121,7 @@ hipEvent_t group_event(sislice_handle* h, int g) {
 }
 
 int prof_begin(sislice_handle* h, int cat, hipStream_t on) {
-  if (!h || !h->prof) return -1;
+  if (!h || !h->prof || !((h->prof_mask >> cat) & 1u)) return -1;
   if (h->evnext + 2 > h->evpool.size()) {
     const size_t grow = std::max<size_t>(256, h->evpool.size());
     for (size_t q = 0; q < grow; ++q) {

@@ -34,6 +34,7 @@ struct sislice_handle {
   void* flush_ctx = nullptr;
   // kernel-class timing with HIP events (enabled per call)
   bool prof = false;
+  unsigned prof_mask = 0x3F;  // bit c: kernel class c is timed
   std::vector<hipEvent_t> evpool;
   size_t evnext = 0;
   struct ProfRec {
