@@ -181,14 +181,16 @@ __device__ __forceinline__ bool wait_expired(const WaitBound& wb, unsigned& poll
   return true;
 }
 
-// sX[c][rr] = block rows rr < rows of column c of B (ld ldb), once none is the
-// sentinel; rows past `rows` read as zero.  A block that is already complete (the
-// common case for a workgroup that started after its predecessors) is read in one
-// round trip.  Otherwise one lane waits on a single element first (the last one of
-// the block), so the waiting workgroups do not stream the whole block from the
-// coherence point on every poll; the block is then loaded and checked in full
+// sx[c * kLdx + rr] = block rows rr < rows of column c of B (ld ldb), once none is
+// the sentinel; rows past `rows` read as zero.  A block that is already complete
+// (the common case for a workgroup that started after its predecessors) is read in
+// one round trip.  Otherwise one lane waits on a single element first (the last
+// one of the block), so the waiting workgroups do not stream the whole block from
+// the coherence point on every poll; the block is then loaded and checked in full
 // (other lanes' stores may still be on their way).
-__device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, long ldb, int nrhs,
+constexpr int kLdx = SB + 4;  // LDS column stride of a vector block (bank spread)
+
+__device__ __forceinline__ void poll_block(double* sx, const double* B, long ldb, int nrhs,
                                            int rows, const WaitBound& wb) {
   {
     int ok = 1;
@@ -199,7 +201,7 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
         v = ld_shared_blk(B + rr + (long)c * ldb);
         if (is_sentinel(v)) ok = 0;
       }
-      sX[c][rr] = v;
+      sx[c * kLdx + rr] = v;
     }
     if (__syncthreads_and(ok)) return;
   }
@@ -228,7 +230,7 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
         v = ld_shared_blk(B + rr + (long)c * ldb);
         if (is_sentinel(v)) ok = 0;
       }
-      sX[c][rr] = v;
+      sx[c * kLdx + rr] = v;
     }
     // a wait that already expired, or one that expires here, goes on with what it read
     // (the decision is uniform: `expired` and the poll count are the same in every lane)
@@ -240,22 +242,37 @@ __device__ __forceinline__ void poll_block(double (*sX)[SB], const double* B, lo
 // The critical hand-off (a block waiting for its immediate predecessor): at most
 // one or two workgroups per shift wait here at a time, so every lane spins on its
 // own elements and the block is complete one round trip after it lands, instead
-// of one round trip for the probe element and another for the block.
-__device__ __forceinline__ void poll_block_spin(double (*sX)[SB], const double* B, long ldb,
-                                                int nrhs, int rows, const WaitBound& wb) {
-  for (int e = threadIdx.x; e < nrhs * SB; e += 256) {
-    const int rr = e & 63, c = e >> 6;
-    double v = 0.0;
-    if (rr < rows) {
-      const double* p = B + rr + (long)c * ldb;
-      v = ld_shared_blk(p);
-      unsigned polls = 0;
-      while (is_sentinel(v) && !wait_expired(wb, polls)) {
-        __builtin_amdgcn_s_sleep(1);
-        v = ld_shared_blk(p);
-      }
+// of one round trip for the probe element and another for the block.  A lane
+// re-polls all of its still-missing elements together.
+template <int NR>
+__device__ __forceinline__ void poll_block_spin(double* sx, const double* B, long ldb, int nrhs,
+                                                int rows, const WaitBound& wb) {
+  constexpr int E = NR * SB / 256;  // elements per lane
+  double v[E];
+  bool live[E];
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = threadIdx.x + 256 * k, rr = e & 63, c = e >> 6;
+    live[k] = c < nrhs && rr < rows;
+    v[k] = live[k] ? ld_shared_blk(B + rr + (long)c * ldb) : 0.0;
+  }
+  unsigned polls = 0;
+  for (;;) {
+    bool missing = false;
+#pragma unroll
+    for (int k = 0; k < E; ++k) missing |= live[k] && is_sentinel(v[k]);
+    if (!missing || wait_expired(wb, polls)) break;
+    __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = threadIdx.x + 256 * k, rr = e & 63, c = e >> 6;
+      if (live[k] && is_sentinel(v[k])) v[k] = ld_shared_blk(B + rr + (long)c * ldb);
     }
-    sX[c][rr] = v;
+  }
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const int e = threadIdx.x + 256 * k, rr = e & 63, c = e >> 6;
+    if (c < nrhs) sx[c * kLdx + rr] = v[k];
   }
   __syncthreads();
 }
@@ -285,19 +302,79 @@ __device__ __forceinline__ int solve_shift_of(int g, int nshift) {
   return s < nshift ? s : -1;
 }
 
-// Forward sweep: Z = L^{-1} P Y.  256 threads; thread (i = tid % 64, q = tid / 64)
-// owns rows i of columns q, q+4, ... of the block.  The L blocks do not depend on
-// other workgroups, so the next one is prefetched into registers while the
-// current result block is awaited.  The contributions of blocks 0 .. b-2 are
-// accumulated as they appear, P_b = Linv_b acc is formed before block b-1 is
-// available, and after the hand-off only Z_b = P_b - Mf_b Z_{b-1} remains.
+// The sweeps' 64x64 block products run on FP64 MFMA (v_mfma_f64_16x16x4).  Wavefront
+// w owns rows 16w .. 16w+15 of the block; with j = lane % 16 and g = lane / 16, a
+// product R = M X (M a 64x64 matrix, X a 64 x nrhs vector block) is accumulated as
+// R^T = X^T M^T in 16-column tiles u: step t supplies X(4t + g, 16u + j) as the A
+// operand (from LDS) and M(16w + j, 4t + g) as the B operand (from registers), and
+// accumulator element r of the lane ends up holding R(16w + j, 16u + g + 4r).  A
+// product is subtracted by negating the accumulator around it (y - M x computed as
+// -(M x + (-y)), the same rounding), so the matrices are loaded as they are, with
+// no arithmetic between a load and its use.  Columns past nrhs are padding: their A
+// operands come from zeroed LDS and their results are never stored.
+template <int NT>
+__device__ __forceinline__ void mfma_block(const double* sx, const double (&mfr)[16], d4 (&acc)[NT]) {
+  const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[u] = mfma16x16x4(sx[(16 * u + j) * kLdx + 4 * t + g], mfr[t], acc[u]);
+}
+
+// The same product as two independent multiply-add chains (even and odd steps),
+// for the products on the critical path.
+template <int NT>
+__device__ __forceinline__ void mfma_block2(const double* sx, const double (&mfr)[16], d4 (&acc)[NT]) {
+  const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    d4 h = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int t = 0; t < 16; t += 2) {
+      acc[u] = mfma16x16x4(sx[(16 * u + j) * kLdx + 4 * t + g], mfr[t], acc[u]);
+      h = mfma16x16x4(sx[(16 * u + j) * kLdx + 4 * t + 4 + g], mfr[t + 1], h);
+    }
+    acc[u] += h;
+  }
+}
+
+// The product with M in LDS instead of registers: M(m, k) at sm[m * kLdx + k].
+template <int NT>
+__device__ __forceinline__ void mfma_block_lds(const double* sx, const double* sm, d4 (&acc)[NT]) {
+  const int tid = threadIdx.x, l = tid & 63, j = l & 15, g = l >> 4, rw = 16 * (tid >> 6) + j;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const double bm = sm[rw * kLdx + 4 * t + g];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) acc[u] = mfma16x16x4(sx[(16 * u + j) * kLdx + 4 * t + g], bm, acc[u]);
+  }
+}
+
+// B-operand fragments of a column-major 64x64 matrix M (ld 64): M(16w + j, 4t + g),
+// or of its transpose.
+template <bool TRANS>
+__device__ __forceinline__ void load_frag(const double* M, double (&f)[16]) {
+  const int tid = threadIdx.x, l = tid & 63, rw = 16 * (tid >> 6) + (l & 15), g = l >> 4;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) f[t] = TRANS ? M[(4 * t + g) + 64 * rw] : M[rw + 64 * (4 * t + g)];
+}
+
+template <int NT>
+__device__ __forceinline__ void negate(d4 (&x)[NT]) {
+#pragma unroll
+  for (int u = 0; u < NT; ++u) x[u] = -x[u];
+}
+
+// Forward sweep: Z = L^{-1} P Y.  The L blocks do not depend on other workgroups,
+// so the next one is prefetched into registers while the current result block is
+// awaited.  The contributions of blocks 0 .. b-3 are accumulated as they appear,
+// P_b = Linv_b acc is formed before block b-2 is available, and after the last
+// hand-off only Z_b = P_b - Mf_b Z_{b-1} remains (the look-ahead blocks Mf^1, Mf^2).
 template <int NR>
 __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
-  constexpr int Q = SB * SB / 256;
-  __shared__ double sM[SB][SB + 1];
-  __shared__ double sZ[NR][SB];
-  const int tid = threadIdx.x;
-  const int i = tid & 63, q0 = tid >> 6;
+  constexpr int NT = (NR + 15) / 16;
+  __shared__ double sx[16 * NT * kLdx];
+  const int tid = threadIdx.x, l = tid & 63, j = l & 15, g = l >> 4;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
@@ -308,140 +385,92 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   const double* Y = a.Y[s];
   double* Z = a.Z[s];
   const int r0 = b * SB;
-  const int row = r0 + i;
+  const int row = r0 + 16 * (tid >> 6) + j;
+  for (int e = tid; e < 16 * NT * kLdx; e += 256) sx[e] = 0.0;
   // everything that does not depend on other blocks is issued first
-  double inv[Q], mf[Q];
   const double* Lbase = a.Linv[s];
+  double inv[16];
+  load_frag<false>(Lbase + (long)b * SB * SB, inv);
+  d4 acc[NT];  // -(P Y - contributions so far)
+  {
+    const int pr = row < n ? perm[row] : 0;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) inv[q] = Lbase[(long)b * SB * SB + tid + 256 * q];
-  if (b > 0) {
+    for (int u = 0; u < NT; ++u)
 #pragma unroll
-    for (int q = 0; q < Q; ++q) mf[q] = Lbase[((long)nblk + b) * SB * SB + tid + 256 * q];
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * u + g + 4 * r;
+        acc[u][r] = (c < nrhs && row < n) ? -Y[pr + (long)c * a.ldy] : 0.0;
+      }
   }
-  double acc[NR / 4];
-#pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    acc[m] = (c < nrhs && row < n) ? Y[perm[row] + (long)c * a.ldy] : 0.0;
-  }
-  // L block (rows of this block, columns of block cb): element e -> (e & 63, e >> 6)
-  double lnext[Q];
+  // L(row, c0 + 4t + g) of block cb, the B operand of its contribution.  Rows past n
+  // (last block only) read row n - 1: they only reach this block's rows past n,
+  // which are cleared before P_b.
+  double lcur[16], lnext[16];
+  const int rowc = min(row, n - 1);
   auto load_L = [&](int cb) {
-    const int c0 = cb * SB;
+    const long c0 = (long)cb * SB;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      const int rr = e & 63, kk = e >> 6;
-      lnext[q] = (r0 + rr < n) ? LD[r0 + rr + (long)(c0 + kk) * a.ldld] : 0.0;
-    }
+    for (int t = 0; t < 16; ++t) lnext[t] = LD[rowc + (c0 + 4 * t + g) * a.ldld];
   };
   if (b > 2) load_L(0);
+  __syncthreads();
   for (int cb = 0; cb + 2 < b; ++cb) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = lnext[q];
-    }
+    for (int t = 0; t < 16; ++t) lcur[t] = lnext[t];
     if (cb + 3 < b) load_L(cb + 1);
-    poll_block(sZ, Z + cb * SB, a.ldz, nrhs, SB, wb);
-#pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double t = acc[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
-        acc[m] = t;
-      }
-    }
+    poll_block(sx, Z + cb * SB, a.ldz, nrhs, SB, wb);
+    mfma_block<NT>(sx, lcur, acc);
     __syncthreads();
   }
-  // the depth-2 block is loaded while P_b = Linv_b acc is formed
-  if (b >= 2) {
+  // the look-ahead blocks load while P_b = Linv_b acc is formed
+  double mf2[16], mf[16];
+  if (b >= 2) load_frag<false>(Lbase + (3L * nblk + b) * SB * SB, mf2);
+  if (b >= 1) load_frag<false>(Lbase + (1L * nblk + b) * SB * SB, mf);
+  const int rw = 16 * (tid >> 6) + j;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lnext[q] = Lbase[(3L * nblk + b) * SB * SB + tid + 256 * q];
-  }
+  for (int u = 0; u < NT; ++u)
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + 256 * q;
-    sM[e & 63][e >> 6] = inv[q];
-  }
-#pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    if (c < nrhs) sZ[c][i] = acc[m];
-  }
+    for (int r = 0; r < 4; ++r) sx[(16 * u + g + 4 * r) * kLdx + rw] = row < n ? -acc[u][r] : 0.0;
   __syncthreads();
-  double pb[NR / 4];
+  d4 pb[NT];
 #pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    double t = 0.0;
-    if (c < nrhs)
-      for (int k = 0; k <= i; ++k) t += sM[i][k] * sZ[c][k];
-    pb[m] = t;
-  }
+  for (int u = 0; u < NT; ++u) pb[u] = d4{0.0, 0.0, 0.0, 0.0};
+  mfma_block<NT>(sx, inv, pb);
+  negate<NT>(pb);
   if (b >= 2) {  // P_b -= Mf^2_b Z_{b-2}
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = lnext[q];
-    }
-    poll_block_spin(sZ, Z + (b - 2) * SB, a.ldz, nrhs, SB, wb);
-#pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double t = pb[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
-        pb[m] = t;
-      }
-    }
+    poll_block_spin<NR>(sx, Z + (b - 2) * SB, a.ldz, nrhs, SB, wb);
+    mfma_block2<NT>(sx, mf2, pb);
   }
-  if (b > 0) {
+  if (b >= 1) {
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = mf[q];
-    }
-    poll_block_spin(sZ, Z + (b - 1) * SB, a.ldz, nrhs, SB, wb);
-#pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double t = pb[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) t -= sM[i][k] * sZ[c][k];
-        pb[m] = t;
-      }
-    }
+    poll_block_spin<NR>(sx, Z + (b - 1) * SB, a.ldz, nrhs, SB, wb);
+    mfma_block2<NT>(sx, mf, pb);
   }
 #pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    if (c < nrhs && row < n) st_shared_blk(Z + row + (long)c * a.ldz, pb[m]);
-  }
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * u + g + 4 * r;
+      if (c < nrhs && row < n) st_shared_blk(Z + row + (long)c * a.ldz, -pb[u][r]);
+    }
 }
 
 // Backward sweep: X = P^T L^{-T} D^{-1} Z, from the last block up, with the same
 // look-ahead: V_b = P_b - Mb_b V_{b+1}, P_b = Linv_b^T (D^{-1} Z_b - contributions
-// of blocks b+2 ..).
+// of blocks b+3 ..) - Mb^2_b V_{b+2}.
 template <int NR>
 __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
-  constexpr int Q = SB * SB / 256;
-  __shared__ double sM[SB][SB + 1];
-  __shared__ double sV[NR][SB];
-  const int tid = threadIdx.x;
-  const int i = tid & 63, q0 = tid >> 6;
+  constexpr int NT = (NR + 15) / 16;
+  __shared__ double sx[16 * NT * kLdx];
+  __shared__ double sl[SB * kLdx];  // sl[m * kLdx + k] = L(c0 + k, r0 + m) of the block in use
+  const int tid = threadIdx.x, l = tid & 63, j = l & 15, g = l >> 4;
   const int n = a.n, nrhs = a.nrhs, nblk = (n + SB - 1) / SB;
   const int s = solve_shift_of(blockIdx.x, a.nshift);
   if (s < 0) return;
   const WaitBound wb{a.wait_err, a.wait_limit};
-  const int t = (int)ticket(a.ctr + s, nblk);
-  const int b = nblk - 1 - t;
+  const int tk = (int)ticket(a.ctr + s, nblk);
+  const int b = nblk - 1 - tk;
   const double* LD = a.LD[s];
   const int* blk = a.blk[s];
   const int* perm = a.perm[s];
@@ -449,16 +478,13 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   double* V = a.V[s];
   double* X = a.X[s];
   const int r0 = b * SB;
-  const int row = r0 + i;
-  double inv[Q], mb[Q];
+  const int rw = 16 * (tid >> 6) + j;
+  const int row = r0 + rw;
+  for (int e = tid; e < 16 * NT * kLdx; e += 256) sx[e] = 0.0;
   const double* Lbase = a.Linv[s];
-#pragma unroll
-  for (int q = 0; q < Q; ++q) inv[q] = Lbase[(long)b * SB * SB + tid + 256 * q];
-  if (b + 1 < nblk) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) mb[q] = Lbase[(2L * nblk + b) * SB * SB + tid + 256 * q];
-  }
-  double acc[NR / 4];
+  double inv[16];  // Linv_b^T
+  load_frag<true>(Lbase + (long)b * SB * SB, inv);
+  d4 acc[NT];  // -(D^{-1} Z_b - contributions so far)
   // D^{-1} on this block's rows
   {
     double d11 = 1.0, d21 = 0.0, d22 = 1.0;
@@ -477,131 +503,92 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
       }
     }
 #pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      double v = 0.0;
-      if (c < nrhs && row < n) {
-        const double z = Z[row + (long)c * a.ldz];
-        if (!a.applyD) {
-          v = z;
-        } else if (bt == 1) {
-          v = (d11 != 0.0) ? z / d11 : 0.0;
-        } else {
-          const double zp = Z[partner + (long)c * a.ldz];
-          // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
-          const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
-          const double aa = d11 / d21, gg = d22 / d21;
-          const double tt = 1.0 / (d21 * (aa * gg - 1.0));
-          v = bt == 2 ? tt * (gg * z1 - z2) : tt * (aa * z2 - z1);
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * u + g + 4 * r;
+        double v = 0.0;
+        if (c < nrhs && row < n) {
+          const double z = Z[row + (long)c * a.ldz];
+          if (!a.applyD) {
+            v = z;
+          } else if (bt == 1) {
+            v = (d11 != 0.0) ? z / d11 : 0.0;
+          } else {
+            const double zp = Z[partner + (long)c * a.ldz];
+            // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
+            const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
+            const double aa = d11 / d21, gg = d22 / d21;
+            const double tt = 1.0 / (d21 * (aa * gg - 1.0));
+            v = bt == 2 ? tt * (gg * z1 - z2) : tt * (aa * z2 - z1);
+          }
         }
+        acc[u][r] = -v;
       }
-      acc[m] = v;
-    }
   }
-  // L block (rows of block cb, columns of this block): element e -> (kk = e & 63, rr = e >> 6)
+  // L_{cb,b}^T, the B operand of block cb's contribution, is read along L's columns
+  // (element e: row c0 + (e & 63), column r0 + (e >> 6)) and transposed through
+  // LDS; the poll's barrier orders those writes before the products.  Rows of L past
+  // n (the ragged last block) read row n - 1: they meet the zero rows of that
+  // block's V.  A block that accumulates has all its rows below n.
+  constexpr int Q = SB * SB / 256;
   double lnext[Q];
   auto load_L = [&](int cb) {
     const int c0 = cb * SB;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
-      const int kk = e & 63, rr = e >> 6;
-      lnext[q] = (c0 + kk < n) ? LD[c0 + kk + (long)(r0 + rr) * a.ldld] : 0.0;
+      lnext[q] = LD[min(c0 + (e & 63), n - 1) + (long)(r0 + (e >> 6)) * a.ldld];
     }
   };
   if (b + 3 < nblk) load_L(nblk - 1);
+  __syncthreads();
   for (int cb = nblk - 1; cb > b + 2; --cb) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int e = tid + 256 * q;
-      // sM[kk][rr] = L(c0 + kk, r0 + rr)
-      sM[e & 63][e >> 6] = lnext[q];
+      sl[(e >> 6) * kLdx + (e & 63)] = lnext[q];
     }
     if (cb - 1 > b + 2) load_L(cb - 1);
-    poll_block(sV, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB), wb);
-#pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double tt = acc[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) tt -= sM[k][i] * sV[c][k];
-        acc[m] = tt;
-      }
-    }
+    poll_block(sx, V + cb * SB, a.ldz, nrhs, min(SB, n - cb * SB), wb);
+    mfma_block_lds<NT>(sx, sl, acc);
     __syncthreads();
   }
-  // the depth-2 block is loaded while P_b = Linv_b^T acc is formed
-  if (b + 2 < nblk) {
+  // the look-ahead blocks load while P_b = Linv_b^T acc is formed
+  double mb2[16], mb[16];
+  if (b + 2 < nblk) load_frag<false>(Lbase + (4L * nblk + b) * SB * SB, mb2);
+  if (b + 1 < nblk) load_frag<false>(Lbase + (2L * nblk + b) * SB * SB, mb);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) lnext[q] = Lbase[(4L * nblk + b) * SB * SB + tid + 256 * q];
-  }
+  for (int u = 0; u < NT; ++u)
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int e = tid + 256 * q;
-    sM[e & 63][e >> 6] = inv[q];
-  }
-#pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    if (c < nrhs) sV[c][i] = acc[m];
-  }
+    for (int r = 0; r < 4; ++r) sx[(16 * u + g + 4 * r) * kLdx + rw] = -acc[u][r];
   __syncthreads();
-  double pb[NR / 4];
+  d4 pb[NT];
 #pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    double tt = 0.0;
-    if (c < nrhs)
-      for (int k = i; k < SB; ++k) tt += sM[k][i] * sV[c][k];
-    pb[m] = tt;
-  }
+  for (int u = 0; u < NT; ++u) pb[u] = d4{0.0, 0.0, 0.0, 0.0};
+  mfma_block<NT>(sx, inv, pb);
+  negate<NT>(pb);
   if (b + 2 < nblk) {  // P_b -= Mb^2_b V_{b+2}
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = lnext[q];
-    }
-    poll_block_spin(sV, V + (b + 2) * SB, a.ldz, nrhs, min(SB, n - (b + 2) * SB), wb);
-#pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double tt = pb[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) tt -= sM[i][k] * sV[c][k];
-        pb[m] = tt;
-      }
-    }
+    poll_block_spin<NR>(sx, V + (b + 2) * SB, a.ldz, nrhs, min(SB, n - (b + 2) * SB), wb);
+    mfma_block2<NT>(sx, mb2, pb);
   }
   if (b + 1 < nblk) {
     __syncthreads();
+    poll_block_spin<NR>(sx, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB), wb);
+    mfma_block2<NT>(sx, mb, pb);
+  }
+  const int px = row < n ? perm[row] : 0;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int e = tid + 256 * q;
-      sM[e & 63][e >> 6] = mb[q];
-    }
-    poll_block_spin(sV, V + (b + 1) * SB, a.ldz, nrhs, min(SB, n - (b + 1) * SB), wb);
+  for (int u = 0; u < NT; ++u)
 #pragma unroll
-    for (int m = 0; m < NR / 4; ++m) {
-      const int c = q0 + 4 * m;
-      if (c < nrhs) {
-        double tt = pb[m];
-#pragma unroll 16
-        for (int k = 0; k < SB; ++k) tt -= sM[i][k] * sV[c][k];
-        pb[m] = tt;
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * u + g + 4 * r;
+      if (c < nrhs && row < n) {
+        st_shared_blk(V + row + (long)c * a.ldz, -pb[u][r]);
+        X[px + (long)c * a.ldx] = -pb[u][r];
       }
     }
-  }
-#pragma unroll
-  for (int m = 0; m < NR / 4; ++m) {
-    const int c = q0 + 4 * m;
-    if (c < nrhs && row < n) {
-      st_shared_blk(V + row + (long)c * a.ldz, pb[m]);
-      X[perm[row] + (long)c * a.ldx] = pb[m];
-    }
-  }
 }
 
 // Li (ldli, zero elsewhere) receives the 64x64 inverses of L's diagonal blocks on
