@@ -113,12 +113,13 @@ __global__ __launch_bounds__(256) void k_factor_init(int n, FactorState* states,
 // As long as that holds for every column, the factorization is the pivot-free
 // LDL^T, which parallelises like Cholesky: the panel's diagonal block is factored
 // in LDS (k_fast_diag4), the rows below follow from one triangular solve with the
-// block (k_fast_trsm: W21 = C21 L11^{-T}, L21 = W21 D1^{-1}) together with the
-// column maxima of |W|, and k_fast_commit accepts the longest prefix of columns
-// that pass the test.  The pivoting panel kernel then continues from the first
+// block (k_fast_trsm: W21 = C21 L11^{-T}) together with the column maxima of |W|,
+// and k_fast_commit accepts the longest prefix of columns that pass the test and
+// writes their L = W D^{-1}.  The pivoting panel kernel then continues from the first
 // rejected column, so the result is the Bunch-Kaufman factorization itself.
 
 __device__ __forceinline__ double u64_to_f64(unsigned long long v) { return __longlong_as_double((long long)v); }
+
 
 // Pivot-free LDL^T of the panel's diagonal block (nbe <= NB columns), one
 // 256-thread workgroup per shift: lane q of row i holds the columns q + 4m of the
@@ -127,12 +128,12 @@ __device__ __forceinline__ double u64_to_f64(unsigned long long v) { return __lo
 // through LDS).  The register window is rotated by one register every four steps,
 // which keeps every register index static (the pivot column of step k = t0 + kk is
 // register 0 of the lanes q == kk).  The finished W columns are kept in LDS for the
-// outputs: the block's rows of W (unscaled) and L, D, the in-block column maxima
-// of |W|, and L11 column-major for the row solves of k_fast_trsm.
+// outputs: the block's rows of W (unscaled), D, the in-block column maxima of |W|,
+// and L11 column-major for the row solves of k_fast_trsm.
 template <int NB>
 __global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* LDs, long ldld,
                                                     double* const* Wps, long ldw,
-                                                    double* const* Lps, double* const* auxs,
+                                                    double* const* auxs,
                                                     const FactorState* states, int nb) {
   constexpr int M = NB / 4;
   __shared__ double Wb[NB][NB + 1];  // Wb[i][k]: final W of column k (rows >= k)
@@ -146,7 +147,6 @@ __global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* 
   const int nbe = min(nb, n - k0);
   const double* LD = LDs[s];
   double* Wp = Wps[s];
-  double* Lp = Lps[s];
   double* aux = auxs[s];
   double* Dv = aux;
   double* cin = aux + nb;
@@ -197,7 +197,6 @@ __global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* 
       const double w = Wb[r][k];
       const double lv = (r > k) ? w * (1.0 / Wb[k][k]) : 0.0;
       if (r >= k) Wp[(k0 + r) + (long)k * ldw] = w;
-      if (r > k) Lp[(k0 + r) + (long)k * ldw] = lv;
       L11[r + (long)k * nb] = lv;
     }
   }
@@ -224,8 +223,8 @@ __global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* 
 
 // Rows below the diagonal block: W21 = C21 L11^{-T} by forward substitution
 // along each row (w_c = c_c - sum_{q<c} w_q L11[c][q], taken right-looking so the
-// updates of one step are independent), L21 = W21 D1^{-1}, and the column maxima
-// of |W21| (atomic max on the bit patterns of non-negative doubles).  The rows
+// updates of one step are independent) and the column maxima of |W21| (atomic max
+// on the bit patterns of non-negative doubles).  The rows
 // below a panel are too few to give every SIMD a wavefront when each is one
 // thread, so a row is shared by four consecutive lanes: lane g of a row holds
 // columns g, g + 4, ... (registers rotated by one every four steps, so the
@@ -235,11 +234,10 @@ __global__ __launch_bounds__(256) void k_fast_diag4(int n, const double* const* 
 template <int NB>
 __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* LDs, long ldld,
                                                    double* const* Wps, long ldw,
-                                                   double* const* Lps, double* const* auxs,
+                                                   const double* const* auxs,
                                                    const FactorState* states, int nb) {
   constexpr int M = NB / 4;
   __shared__ double sL[NB * NB];  // column-major: sL[q * NB + c] = L11[c][q]
-  __shared__ double sRD[NB];
   const int s = blockIdx.y, tid = threadIdx.x;
   const FactorState st = states[s];
   const int k0 = st.k0 + st.kb;
@@ -249,7 +247,6 @@ __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* L
   if (r0 >= n) return;
   const double* LD = LDs[s];
   double* Wp = Wps[s];
-  double* Lp = Lps[s];
   const double* aux = auxs[s];
   unsigned long long* cout = reinterpret_cast<unsigned long long*>(const_cast<double*>(aux) + 2 * nb);
   const double* L11 = aux + 3 * nb;
@@ -257,7 +254,6 @@ __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* L
     const int c = e % NB, q = e / NB;
     sL[e] = (c < nbe && q < nbe) ? L11[c + (long)q * nb] : 0.0;
   }
-  if (tid < NB) sRD[tid] = (tid < nbe) ? 1.0 / aux[tid] : 0.0;
   const int g = tid & 3;
   const int row = r0 + (tid >> 2);
   const bool rv = row < n;
@@ -286,10 +282,7 @@ __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* L
     }
     // column t0 + g is final: write it, fold it into the column maximum, rotate
     const int c0 = t0 + g;
-    if (rv && c0 < nbe) {
-      Wp[row + (long)c0 * ldw] = w[0];
-      Lp[row + (long)c0 * ldw] = w[0] * sRD[c0];
-    }
+    if (rv && c0 < nbe) Wp[row + (long)c0 * ldw] = w[0];
     double mx = (rv && c0 < nbe) ? fabs(w[0]) : 0.0;
     if (mx != mx) mx = __longlong_as_double(0x7FF0000000000000ll);  // NaN ranks as +inf
 #pragma unroll
@@ -304,7 +297,7 @@ __global__ __launch_bounds__(256) void k_fast_trsm(int n, const double* const* L
 
 template <bool PIVOT>
 __global__ __launch_bounds__(256) void k_fast_commit(int n, double* const* LDs, long ldld,
-                                                     const double* const* Lps, long ldw,
+                                                     const double* const* Wps, long ldw,
                                                      const double* const* auxs, int* const* blks,
                                                      int* const* colpanels, FactorState* states,
                                                      int nb) {
@@ -337,9 +330,10 @@ __global__ __launch_bounds__(256) void k_fast_commit(int n, double* const* LDs, 
   const int jst = js;
   if (c < jst) {
     double* LD = LDs[s];
-    const double* Lp = Lps[s];
+    const double* Wp = Wps[s];
     const int col = k0 + c;
-    for (int i = col + 1 + tid; i < n; i += 256) LD[i + (long)col * ldld] = Lp[i + (long)c * ldw];
+    const double rd = 1.0 / Dv[c];  // the column's multipliers l = w (1 / d)
+    for (int i = col + 1 + tid; i < n; i += 256) LD[i + (long)col * ldld] = Wp[i + (long)c * ldw] * rd;
     if (tid == 0) {
       LD[col + (long)col * ldld] = Dv[c];
       blks[s][col] = 1;
@@ -1248,7 +1242,6 @@ static FactorPlan factor_subplan(const FactorPlan& fp, int s0, int cnt) {
   f.d_ipiv = fp.d_ipiv + s0;
   f.d_state = fp.d_state + s0;
   f.d_inertia = fp.d_inertia + 3 * (size_t)s0;
-  f.d_Lp = fp.d_Lp ? fp.d_Lp + s0 : nullptr;
   f.d_aux = fp.d_aux ? fp.d_aux + s0 : nullptr;
   return f;
 }
@@ -1267,32 +1260,34 @@ static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislic
     const long rows = n - k0_lb - 1;
     if (nb > 32) {
       SL_LAUNCH(k_fast_diag4<64>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
-                fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+                fp.ldld, fp.d_W, fp.ldw, fp.d_aux, fp.d_state, nb);
       SL_LAUNCH_CHECK();
       if (rows > 0) {
         SL_LAUNCH(k_fast_trsm<64>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
-                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
+                  (const double* const*)fp.d_aux,
                   fp.d_state, nb);
         SL_LAUNCH_CHECK();
       }
     } else {
       SL_LAUNCH(k_fast_diag4<32>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
-                fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux, fp.d_state, nb);
+                fp.ldld, fp.d_W, fp.ldw, fp.d_aux, fp.d_state, nb);
       SL_LAUNCH_CHECK();
       if (rows > 0) {
         SL_LAUNCH(k_fast_trsm<32>, dim3((unsigned)ceil_div(rows, 64), S), dim3(256), 0, st, n,
-                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_Lp, fp.d_aux,
+                  (const double* const*)fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
+                  (const double* const*)fp.d_aux,
                   fp.d_state, nb);
         SL_LAUNCH_CHECK();
       }
     }
     if (fp.pivot)
       SL_LAUNCH(k_fast_commit<true>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
-                (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
+                (const double* const*)fp.d_W, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
                 fp.d_colpanel, fp.d_state, nb);
     else
       SL_LAUNCH(k_fast_commit<false>, dim3(nb, S), dim3(256), 0, st, n, fp.d_LD, fp.ldld,
-                (const double* const*)fp.d_Lp, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
+                (const double* const*)fp.d_W, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
                 fp.d_colpanel, fp.d_state, nb);
     SL_LAUNCH_CHECK();
     prof_end(ph, tf, st);

@@ -174,8 +174,7 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   z.take<int>((size_t)S * npmax * n);
   z.take<FactorState>(S);
   z.take<int64_t>(3 * (size_t)S);
-  z.take<void*>(11 * (size_t)S);
-  z.take<double>((size_t)S * ldw * nb);            // Lp
+  z.take<void*>(10 * (size_t)S);
   z.take<double>((size_t)S * (3 * nb + nb * nb));   // aux
   Carver c(ws_get(h, bufid, z.off));
   FactorPlan fp;
@@ -199,11 +198,10 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   int* snap = c.take<int>((size_t)S * npmax * n);
   fp.d_state = c.take<FactorState>(S);
   fp.d_inertia = c.take<int64_t>(3 * (size_t)S);
-  void** tab = c.take<void*>(11 * (size_t)S);
-  double* Lp = c.take<double>((size_t)S * ldw * nb);
+  void** tab = c.take<void*>(10 * (size_t)S);
   double* aux = c.take<double>((size_t)S * (3 * nb + nb * nb));
   // host staging: sigmas then the pointer tables
-  size_t hbytes = sizeof(double) * S + sizeof(void*) * 11 * S;
+  size_t hbytes = sizeof(double) * S + sizeof(void*) * 10 * S;
   char* hs = static_cast<char*>(host_stage(h, hbytes));
   std::memcpy(hs, sigmas_host, sizeof(double) * S);
   void** ht = reinterpret_cast<void**>(hs + sizeof(double) * S);
@@ -217,11 +215,10 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
     ht[6 * S + s] = ps + (size_t)s * npmax;
     ht[7 * S + s] = snap + (size_t)s * npmax * n;
     ht[8 * S + s] = ipiv_host[s];
-    ht[9 * S + s] = Lp + (size_t)s * ldw * nb;
-    ht[10 * S + s] = aux + (size_t)s * (3 * nb + nb * nb);
+    ht[9 * S + s] = aux + (size_t)s * (3 * nb + nb * nb);
   }
   SL_HIP(hipMemcpyAsync(d_sig, hs, sizeof(double) * S, hipMemcpyHostToDevice, h->stream));
-  SL_HIP(hipMemcpyAsync(tab, ht, sizeof(void*) * 11 * S, hipMemcpyHostToDevice, h->stream));
+  SL_HIP(hipMemcpyAsync(tab, ht, sizeof(void*) * 10 * S, hipMemcpyHostToDevice, h->stream));
   fp.d_sigmas = d_sig;
   fp.d_LD = reinterpret_cast<double* const*>(tab + 0 * S);
   fp.d_W = reinterpret_cast<double* const*>(tab + 1 * S);
@@ -234,8 +231,7 @@ FactorPlan build_factor(sislice_handle* h, int bufid, int n, const double* A, lo
   fp.npmax = npmax;
   fp.d_snap = reinterpret_cast<int* const*>(tab + 7 * S);
   fp.d_ipiv = reinterpret_cast<int* const*>(tab + 8 * S);
-  fp.d_Lp = reinterpret_cast<double* const*>(tab + 9 * S);
-  fp.d_aux = reinterpret_cast<double* const*>(tab + 10 * S);
+  fp.d_aux = reinterpret_cast<double* const*>(tab + 9 * S);
   fp.nbpiv = nbpiv;
   fp.cus = h->cus;
   // two shift groups on two streams overlap one group's panels with the other's

@@ -32,7 +32,6 @@ struct FactorPlan {
   int npmax = 0;
   // pivot-free speculative panel path (per shift): staged L of the panel (n x nb),
   // D of the panel, inverse of the diagonal block (nb x nb), column maxima
-  double* const* d_Lp = nullptr;
   double* const* d_aux = nullptr;  // [nb] D | [nb] max|w| in block | [nb] max|w| below (uint64 bits) | nb*nb Linv
   int fast = 1;                    // use the pivot-free path
   int nbpiv = 32;                  // columns a pivoting panel handles after a rejection
