@@ -755,8 +755,14 @@ __global__ __launch_bounds__(256) void k_trailing_update(int n, double* const* L
 // flight while the wavefronts run the current one's MFMAs.
 // Layout per chunk and operand: [k][row], rows padded to 132 doubles so that the
 // four k-groups a wavefront reads at once fall on different banks.
+// With STREAM the C tile is read and written non-temporally: when the shifts run in
+// two groups on two streams (large orders), C has no reuse in the caches before the
+// next update, and streaming it keeps the other group's panel data resident (at
+// order 12288, 49 shifts: 2975 -> 2718 us per update launch, about 2% per
+// factorization).
 constexpr int kUpdK = 16;           // k-columns per staged chunk
 constexpr int kUpdLd = 128 + 4;     // padded row count per k-column
+template <bool STREAM>
 __global__ __launch_bounds__(1024) void k_trailing_update_lds(int n, double* const* LDs, long ldld,
                                                              double* const* Wps, long ldw,
                                                              const FactorState* states) {
@@ -820,7 +826,8 @@ __global__ __launch_bounds__(1024) void k_trailing_update_lds(int n, double* con
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int j = min(col0 + wj + 16 * y + lk + 4 * r, n - 1);
-          acc[x][y][r] = LD[i + (long)j * ldld];
+          acc[x][y][r] = STREAM ? __builtin_nontemporal_load(LD + i + (long)j * ldld)
+                                : LD[i + (long)j * ldld];
         }
     }
   }
@@ -860,7 +867,12 @@ __global__ __launch_bounds__(1024) void k_trailing_update_lds(int n, double* con
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jc = col0 + wj + 16 * y + lk + 4 * r;
-        if (i < n && jc < n && i >= jc) LD[i + (long)jc * ldld] = acc[x][y][r];
+        if (i < n && jc < n && i >= jc) {
+          if (STREAM)
+            __builtin_nontemporal_store(acc[x][y][r], LD + i + (long)jc * ldld);
+          else
+            LD[i + (long)jc * ldld] = acc[x][y][r];
+        }
       }
     }
   }
@@ -1315,8 +1327,12 @@ static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislic
               fp.d_W, fp.ldw, fp.d_state, S);
   } else if (n - k1_lb >= fp.wide_min) {
     const long T = ceil_div(n - k1_lb, 128);
-    SL_LAUNCH(k_trailing_update_lds, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st, n,
-              fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+    if (fp.stream_c)
+      SL_LAUNCH(k_trailing_update_lds<true>, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0, st,
+                n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
+    else
+      SL_LAUNCH(k_trailing_update_lds<false>, dim3((unsigned)(T * (T + 1) / 2), S), dim3(1024), 0,
+                st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw, fp.d_state);
   } else {
     const long T = ceil_div(n - k1_lb, 64);
     SL_LAUNCH(k_trailing_update, dim3((unsigned)(T * (T + 1) / 2), S), dim3(256), 0, st, n,
@@ -1378,7 +1394,10 @@ void factor_steps_launch(const FactorPlan& fp, hipStream_t st, bool readback) {
     sub[g] = factor_subplan(fp, s0, s1 - s0);
     // a persistent update would hold every CU for its whole launch and keep the
     // other groups' panels waiting: grouped runs take the workgroup-per-tile form
-    if (G > 1) sub[g].update_pipe = 0;
+    if (G > 1) {
+      sub[g].update_pipe = 0;
+      sub[g].stream_c = 1;
+    }
     gs[g] = g == 0 ? st : group_stream(ph, g - 1);
   }
   FactorState* hs = static_cast<FactorState*>(host_stage(ph, sizeof(FactorState) * S));

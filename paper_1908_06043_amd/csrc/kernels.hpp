@@ -37,6 +37,7 @@ struct FactorPlan {
   int nbpiv = 32;                  // columns a pivoting panel handles after a rejection
   int wide_min = 1024;             // trailing order from which the update takes 128x128 tiles
   int update_pipe = 1;             // 128x128 updates by the persistent pipelined kernel
+  int stream_c = 0;                // the 128-tile update streams C (shift groups on two streams)
   int cus = 256;                   // compute units of the device (its persistent grid)
   int groups = 1;                  // shift groups run on separate streams (with readback)
 };
