@@ -525,6 +525,19 @@ def main():
     roof["kernel_ms_per_step"] = {KCLASS[q]: round(float(tk_all[q]), 3) for q in range(6)}
     roof["launches_per_step"] = {KCLASS[q]: int(nk_all[q]) for q in range(6)}
     roof["timed_classes"] = [KCLASS[dom]] if brk is not None else list(KCLASS)
+    # the other rooflines, from the fully timed warm-up step (one step, every class)
+    by_class = {}
+    if brk is not None:
+        tb = np.asarray(brk["t_kern_ms"])
+        if tb[2] > 0:
+            a = float(brk["bytes_solve"]) / (tb[2] * 1e-3) / 1e9
+            by_class["triangular_solve"] = {"bound": "hbm", "achieved": a, "peak": PEAK_HBM,
+                                            "unit": "GB/s", "frac": a / PEAK_HBM}
+        if tb[1] > 0:
+            a = float(brk["flops_update"]) / (tb[1] * 1e-3) / 1e12
+            by_class["trailing_update_mfma"] = {"bound": "mfma", "achieved": a, "peak": PEAK_FP64,
+                                                "unit": "TFLOP/s", "frac": a / PEAK_FP64}
+    roof["by_class_warmup_step"] = by_class
     factor_tf = float(np.mean([r["flops_factor"] / (r["t_factor_ms"] * 1e-3) / 1e12 for r in reps]))
     line = {
         "metric": METRIC, "value": value, "unit": "eigenpairs/s", "n_gpus": 1,
