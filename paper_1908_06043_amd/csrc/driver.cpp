@@ -746,13 +746,12 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       zl.take<double>((size_t)QC * QC);  // S (eigvecs)
       zl.take<double>((size_t)QC * QC);  // S lock sel
       zl.take<double>((size_t)QC * QC);  // S keep sel
-      zl.take<double>(QC);               // theta
-      zl.take<double>(QC);               // est
       zl.take<double>((size_t)QC * b);   // CQ
       zl.take<double>((size_t)LC * b);   // CL
       zl.take<double>(4 * b * b);        // G, R1, R2, Rt
       zl.take<int>(2 * QC);              // idx lock / keep
     }
+    zl.take<double>((size_t)2 * QC * P);  // theta, est of every probe (one readback)
     zl.take<int>(P);  // flags
     const int ts_mmax = std::max(LC, QC);
     zl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));  // tall-skinny partials
@@ -778,8 +777,6 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       d.S = cl.take<double>((size_t)QC * QC);
       d.SL = cl.take<double>((size_t)QC * QC);
       d.SK = cl.take<double>((size_t)QC * QC);
-      d.th = cl.take<double>(QC);
-      d.est = cl.take<double>(QC);
       d.CQ = cl.take<double>((size_t)QC * b);
       d.CL = cl.take<double>((size_t)LC * b);
       double* g4 = cl.take<double>(4 * b * b);
@@ -790,6 +787,12 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       int* ii = cl.take<int>(2 * QC);
       d.il = ii;
       d.ik = ii + QC;
+    }
+    // the Ritz values and estimates of all probes side by side, read back in one copy
+    double* thest = cl.take<double>((size_t)2 * QC * P);
+    for (int j = 0; j < P; ++j) {
+      pd[j].th = thest + (size_t)2 * QC * j;
+      pd[j].est = pd[j].th + QC;
     }
     int* dflags = cl.take<int>(P);
     double* tspart = cl.take<double>(tsmt_partial_size(n, 2 * P, ts_mmax));
@@ -1021,14 +1024,17 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
       re.Rt = ring.cptrs(act_vec(act, [&](int j) { return pd[j].Rt; }));
       re.est = ring.ptrs(act_vec(act, [&](int j) { return pd[j].est; }));
       ritz_est_launch(re, na, st);
-      std::vector<std::vector<double>> th(na, std::vector<double>(QC)), es(na, std::vector<double>(QC));
-      for (int q = 0; q < na; ++q) {
-        SL_HIP(hipMemcpyAsync(th[q].data(), pd[act[q]].th, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
-        SL_HIP(hipMemcpyAsync(es[q].data(), pd[act[q]].est, sizeof(double) * QC, hipMemcpyDeviceToHost, st));
-      }
-      std::vector<int> hflags(P, 0);
-      SL_HIP(hipMemcpyAsync(hflags.data(), dflags, sizeof(int) * P, hipMemcpyDeviceToHost, st));
+      // one copy into pinned staging (every probe's theta and est) instead of two
+      // pageable copies per probe, each of which waits for the device
+      double* hte = static_cast<double*>(host_stage(h, sizeof(double) * 2 * QC * P));
+      SL_HIP(hipMemcpyAsync(hte, thest, sizeof(double) * 2 * QC * P, hipMemcpyDeviceToHost, st));
       SL_HIP(hipStreamSynchronize(st));
+      std::vector<std::vector<double>> th(na), es(na);
+      for (int q = 0; q < na; ++q) {
+        const double* src = hte + (size_t)2 * QC * act[q];
+        th[q].assign(src, src + QC);
+        es[q].assign(src + QC, src + 2 * QC);
+      }
       ring.synced();
       std::vector<std::vector<int>> lk(na), kp(na);
       std::vector<std::vector<double>> thk(na);
