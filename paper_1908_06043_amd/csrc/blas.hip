@@ -31,8 +31,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int K = g.k ? g.k[b] : g.k0;
   const int i0 = blockIdx.x * GT, j0 = blockIdx.y * GT;
   if (i0 >= m || j0 >= n) return;
-  const double* A = g.A[b];
-  const double* B = g.B[b];
+  const double* A = g.A ? g.A[b] : g.A1;
+  const double* B = g.B ? g.B[b] : g.B1;
   int kc = (K + g.splits - 1) / g.splits;
   kc = (kc + GK - 1) / GK * GK;
   const int kb = sp * kc, ke = min(K, kb + kc);
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         }
     return;
   }
-  double* C = g.C[b];
+  double* C = g.C ? g.C[b] : g.C1;
 #pragma unroll
   for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
   const int b = blockIdx.y;
   const int m = g.m ? g.m[b] : g.m0;
   const int n = g.n ? g.n[b] : g.n0;
-  double* C = g.C[b];
+  double* C = g.C ? g.C[b] : g.C1;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)m * n; e += (long)gridDim.x * 256) {
     const int i = (int)(e % m), j = (int)(e / m);
     double s = 0.0;
@@ -626,9 +626,9 @@ __global__ __launch_bounds__(256) void k_coldot_partial(ColDotArgs a) {
   const int b = blockIdx.z, c = blockIdx.y, chunk = blockIdx.x;
   const int nc = a.ncol ? a.ncol[b] : a.ncol0;
   if (c >= nc) return;
-  const double* X = a.X[b] + (long)c * a.ldx;
-  const double* Y = a.Y[b] + (long)c * a.ldy;
-  const double w = (a.mode == 1) ? a.w[b][c] : 0.0;
+  const double* X = (a.X ? a.X[b] : a.x1) + (long)c * a.ldx;
+  const double* Y = (a.Y ? a.Y[b] : a.y1) + (long)c * a.ldy;
+  const double w = (a.mode == 1) ? (a.w ? a.w[b] : a.w1)[c] : 0.0;
   const int r0 = chunk * kDotChunk, r1 = min(a.n, r0 + kDotChunk);
   double s = 0.0;
   for (int i = r0 + threadIdx.x; i < r1; i += 256) {
@@ -655,7 +655,7 @@ __global__ __launch_bounds__(256) void k_coldot_reduce(ColDotArgs a) {
   for (int c = threadIdx.x; c < nc; c += 256) {
     double s = 0.0;
     for (int q = 0; q < a.nchunk; ++q) s += a.partial[((long)b * a.maxcol + c) * a.nchunk + q];
-    a.out[b][c] = (a.mode == 1) ? sqrt(s) : s;
+    (a.out ? a.out[b] : a.out1)[c] = (a.mode == 1) ? sqrt(s) : s;
   }
 }
 

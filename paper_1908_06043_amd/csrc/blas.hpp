@@ -21,6 +21,10 @@ struct GemmArgs {
   long ldb = 0;
   double* const* C = nullptr;
   long ldc = 0;
+  // a batch of one may pass its operands directly (no device tables to upload)
+  const double* A1 = nullptr;
+  const double* B1 = nullptr;
+  double* C1 = nullptr;
   double alpha = 1.0, beta = 0.0;
   int splits = 1;
   double* partial = nullptr;
@@ -96,6 +100,11 @@ struct ColDotArgs {
   long ldy = 0;
   const double* const* w = nullptr;
   double* const* out = nullptr;
+  // a batch of one may pass its columns directly (no device tables to upload)
+  const double* x1 = nullptr;
+  const double* y1 = nullptr;
+  const double* w1 = nullptr;
+  double* out1 = nullptr;
   int mode = 0;
   double* partial = nullptr;  // batch * maxcol * ceil(n / kDotChunk)
   int maxcol = 0, nchunk = 0;

@@ -246,11 +246,11 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
     cr.partial = static_cast<double*>(ws_get(h, kBufEig, sizeof(double) * coldot_partial_size(n, 1, R)));
     auto dotR = [&](const double* x, const double* y, double* out) {
       ColDotArgs d = cr;
-      d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+      d.x1 = x;
       d.ldx = n;
-      d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+      d.y1 = y;
       d.ldy = n;
-      d.out = ring.ptrs(std::vector<double*>{out});
+      d.out1 = out;
       coldot_launch(d, 1, R, st);
     };
     dotR(Vd, Vd, d_s2 + (size_t)dk * R);
@@ -339,11 +339,11 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   cd.partial = static_cast<double*>(ws_get(h, kBufEig, sizeof(double) * coldot_partial_size(n, 1, nv)));
   auto dot1 = [&](const double* x, const double* y, double* out) {
     ColDotArgs d = cd;
-    d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+    d.x1 = x;
     d.ldx = n;
-    d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+    d.y1 = y;
     d.ldy = n;
-    d.out = ring.ptrs(std::vector<double*>{out});
+    d.out1 = out;
     coldot_launch(d, 1, 1, st);
   };
   double* d_alpha = small + 128;  // [m_b]
@@ -416,11 +416,11 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   cdv.ncol0 = nv;
   auto dotv = [&](const double* x, const double* y, double* out) {
     ColDotArgs d = cdv;
-    d.X = ring.cptrs(std::vector<double*>{const_cast<double*>(x)});
+    d.x1 = x;
     d.ldx = n;
-    d.Y = ring.cptrs(std::vector<double*>{const_cast<double*>(y)});
+    d.y1 = y;
     d.ldy = n;
-    d.out = ring.ptrs(std::vector<double*>{out});
+    d.out1 = out;
     coldot_launch(d, 1, nv, st);
   };
   // t_next = 2 H~ t_cur - t_prev = (2/d) H t_cur - (2c/d) t_cur - t_prev  (t_1 = H~ t_0)

@@ -169,8 +169,9 @@ struct DevBuf {
   ~DevBuf() { release(); }
 };
 
-// Batched GEMM helper: per-batch sizes, pointer tables through the ring,
-// split-K (ordered partials) when the reduction is long and the output small.
+// Batched GEMM helper: per-batch sizes, pointer tables through the ring (a batch of
+// one passes its sizes and operands in the arguments instead), split-K (ordered
+// partials) when the reduction is long and the output small.
 inline void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std::vector<int>& nn,
           const std::vector<int>& k, const std::vector<const double*>& A, long lda,
           const std::vector<const double*>& B, long ldb, const std::vector<double*>& C, long ldc,
@@ -185,14 +186,23 @@ inline void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std:
   }
   if (mmax == 0 || nmax == 0) return;
   GemmArgs g;
-  g.m = c.ring->vec(m);
-  g.n = c.ring->vec(nn);
-  g.k = c.ring->vec(k);
-  g.A = c.ring->cptrs(A);
+  if (batch == 1) {
+    g.m0 = m[0];
+    g.n0 = nn[0];
+    g.k0 = k[0];
+    g.A1 = A[0];
+    g.B1 = B[0];
+    g.C1 = C[0];
+  } else {
+    g.m = c.ring->vec(m);
+    g.n = c.ring->vec(nn);
+    g.k = c.ring->vec(k);
+    g.A = c.ring->cptrs(A);
+    g.B = c.ring->cptrs(B);
+    g.C = c.ring->ptrs(C);
+  }
   g.lda = lda;
-  g.B = c.ring->cptrs(B);
   g.ldb = ldb;
-  g.C = c.ring->ptrs(C);
   g.ldc = ldc;
   g.alpha = alpha;
   g.beta = beta;
