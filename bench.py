@@ -509,11 +509,13 @@ def main():
                 "frac": achieved / PEAK_HBM, "traffic": None,
                 "algorithmic_bytes_per_launch": by / max(nk[2], 1)}
     elif dom == 0:
-        # a panel of nb columns reads and writes the (n - k0) x nb panel block of every shift
-        per_launch = 2 * 8.0 * (n / 2.0) * 64 * (n_s + 1)
-        achieved = per_launch * nk[0] / (tk[0] * 1e-3) / 1e9
+        # a panel step (one timed ticket) reads and writes the (n - k0) x kb panel block
+        # of every shift (the library counts the blocks from the panel starts)
+        by = float(np.sum([r["bytes_panel"] for r in reps]))
+        achieved = by / (tk[0] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM, "traffic": None}
+                "frac": achieved / PEAK_HBM, "traffic": None,
+                "algorithmic_bytes_per_launch": by / max(nk[0], 1)}
     else:
         roof = {"bound": "mfma", "achieved": None, "peak": PEAK_FP64, "unit": "TFLOP/s",
                 "frac": None, "traffic": None}

@@ -117,6 +117,9 @@ typedef struct {
    * eigenvalues than validated candidates, and the rounds of insertion. */
   int32_t probes_inserted;
   int32_t recovery_rounds;
+  /* With opts->profile: algorithmic bytes of the Bunch-Kaufman panels, the panel
+   * block (n - k0) x kb of every shift read and written once per panel step. */
+  double bytes_panel;
 } sislice_report;
 
 /* Report of sislice_adjoint, host memory owned by the caller. */

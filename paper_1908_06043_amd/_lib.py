@@ -37,7 +37,8 @@ class Report(C.Structure):
                 ("slice_exact", c_int32_p), ("slice_cand", c_int32_p),
                 ("t_kern_ms", C.c_double * 6), ("n_kern", C.c_int64 * 6), ("flops_update", C.c_double),
                 ("bytes_solve", C.c_double), ("factor_id", C.c_uint64),
-                ("probes_inserted", C.c_int32), ("recovery_rounds", C.c_int32)]
+                ("probes_inserted", C.c_int32), ("recovery_rounds", C.c_int32),
+                ("bytes_panel", C.c_double)]
 
 
 class AdjointReport(C.Structure):

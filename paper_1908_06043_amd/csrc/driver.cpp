@@ -1327,9 +1327,10 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     }
     t_rr = ms_since(t_r0);
   }
-  double flops_update = 0.0;
+  double flops_update = 0.0, bytes_panel = 0.0;
   if (rep && o.profile) {
-    // algorithmic flops of the trailing updates from the panel starts of every shift
+    // algorithmic flops of the trailing updates and bytes of the panels, from the
+    // panel starts of every shift
     std::vector<int> ps((size_t)S1 * fp.npmax);
     std::vector<FactorState> fs(S1);
     SL_HIP(hipMemcpy(ps.data(), fp.pstart_base, sizeof(int) * ps.size(), hipMemcpyDeviceToHost));
@@ -1341,6 +1342,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
         const int k1 = q + 1 < np ? ps[(size_t)s * fp.npmax + q + 1] : n;
         const double m = (double)(n - k1);
         flops_update += m * (m + 1.0) * (double)(k1 - k0);
+        bytes_panel += 2.0 * 8.0 * (double)(n - k0) * (double)(k1 - k0);
       }
     }
   }
@@ -1673,6 +1675,7 @@ sislice_status solve_impl(sislice_handle* h, int64_t n64, const double* A, int64
     }
     prof_collect(h, rep->t_kern_ms, rep->n_kern);
     rep->flops_update = flops_update;
+    rep->bytes_panel = bytes_panel;
     rep->bytes_solve = bytes_solve;
   }
   prof_reset(h);

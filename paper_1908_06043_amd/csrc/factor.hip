@@ -1267,8 +1267,11 @@ static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislic
   const int n = fp.n, S = fp.nshift, nb = fp.nb;
   const int nbpiv = fp.fast ? fp.nbpiv : nb;
   const int min_kb = factor_min_panel(nb, fp.nbpiv, fp.fast != 0);
+  int tpan = -1;
   if (fp.fast) {
-    const int tf = prof_begin(ph, kProfPanel, st);
+    // one timed ticket per panel step: the speculative group and the pivoting
+    // panel are consecutive launches of the panel class
+    tpan = prof_begin(ph, kProfPanel, st);
     const long rows = n - k0_lb - 1;
     if (nb > 32) {
       SL_LAUNCH(k_fast_diag4<64>, dim3(S), dim3(256), 0, st, n, (const double* const*)fp.d_LD,
@@ -1302,9 +1305,8 @@ static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislic
                 (const double* const*)fp.d_W, fp.ldw, (const double* const*)fp.d_aux, fp.d_blk,
                 fp.d_colpanel, fp.d_state, nb);
     SL_LAUNCH_CHECK();
-    prof_end(ph, tf, st);
   }
-  const int tp = prof_begin(ph, kProfPanel, st);
+  if (tpan < 0) tpan = prof_begin(ph, kProfPanel, st);
   if (fp.pivot)
     SL_LAUNCH(k_bk_panel<true>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
               fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart, fp.d_state, nb, nbpiv);
@@ -1312,7 +1314,7 @@ static void factor_step(const FactorPlan& fp, hipStream_t st, long k0_lb, sislic
     SL_LAUNCH(k_bk_panel<false>, dim3(S), dim3(1024), 0, st, n, fp.d_LD, fp.ldld, fp.d_W, fp.ldw,
               fp.d_perm, fp.d_sw, fp.d_blk, fp.d_colpanel, fp.d_pstart, fp.d_state, nb, nbpiv);
   SL_LAUNCH_CHECK();
-  prof_end(ph, tp, st);
+  prof_end(ph, tpan, st);
   if (after_panel) SL_HIP(hipEventRecord(after_panel, st));
   const long k1_lb = std::min<long>(n, k0_lb + min_kb);
   if (k1_lb >= n) return;
