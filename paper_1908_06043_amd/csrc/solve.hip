@@ -9,7 +9,8 @@
 // the off-diagonal contributions of finished blocks as those blocks appear
 // (sentinel hand-off below), and finish their block with a precomputed inverse
 // of the 64x64 unit-lower diagonal block, so the critical path per block is one
-// hand-off plus a 64x64 GEMV.  L is read once per direction.
+// hand-off plus one 64x64 block product on FP64 MFMA.  L is read once per
+// direction.
 // The block-diagonal D^{-1} (1x1 and 2x2 pivots) is applied at the start of the
 // backward sweep.
 #include "common.hpp"
@@ -393,13 +394,19 @@ __global__ __launch_bounds__(256) void k_fwd(SolveArgs a) {
   load_frag<false>(Lbase + (long)b * SB * SB, inv);
   d4 acc[NT];  // -(P Y - contributions so far)
   {
-    const int pr = row < n ? perm[row] : 0;
+    // every load from a clamped index, then the selects: one round trip for Y
+    const int pr = perm[min(row, n - 1)];
+    double y[NT][4];
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) y[u][r] = Y[pr + (long)min(16 * u + g + 4 * r, nrhs - 1) * a.ldy];
 #pragma unroll
     for (int u = 0; u < NT; ++u)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int c = 16 * u + g + 4 * r;
-        acc[u][r] = (c < nrhs && row < n) ? -Y[pr + (long)c * a.ldy] : 0.0;
+        acc[u][r] = (c < nrhs && row < n) ? -y[u][r] : 0.0;
       }
   }
   // L(row, c0 + 4t + g) of block cb, the B operand of its contribution.  Rows past n
@@ -485,21 +492,40 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
   double inv[16];  // Linv_b^T
   load_frag<true>(Lbase + (long)b * SB * SB, inv);
   d4 acc[NT];  // -(D^{-1} Z_b - contributions so far)
-  // D^{-1} on this block's rows
+  // D^{-1} on this block's rows.  The pivot flag, both candidate 2x2 blocks (the row
+  // as first or as second row of its pivot) and the rows of Z around this row are
+  // loaded at once from clamped indices, and the values are selected afterwards, so
+  // the block starts after one round trip instead of a chain of dependent ones.
   {
+    const int rc = min(row, n - 1), rup = min(rc + 1, n - 1), rdn = max(rc - 1, 0);
+    const int bt_rc = blk[rc];
+    const int bt = row < n ? bt_rc : 1;
+    const double l_rr = LD[rc + (long)rc * a.ldld], l_ur = LD[rup + (long)rc * a.ldld];
+    const double l_uu = LD[rup + (long)rup * a.ldld], l_dd = LD[rdn + (long)rdn * a.ldld];
+    const double l_rd = LD[rc + (long)rdn * a.ldld];
+    double zs[NT][4], zu[NT][4], zd[NT][4];
+#pragma unroll
+    for (int u = 0; u < NT; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long cc = (long)min(16 * u + g + 4 * r, nrhs - 1) * a.ldz;
+        zs[u][r] = Z[rc + cc];
+        zu[u][r] = Z[rup + cc];
+        zd[u][r] = Z[rdn + cc];
+      }
+    // 1x1 pivot: d11; first row of a 2x2 pivot (k = row); second row (k = row - 1)
     double d11 = 1.0, d21 = 0.0, d22 = 1.0;
-    int bt = 1, partner = row;
     if (row < n) {
-      bt = blk[row];
-      if (bt == 2) partner = row + 1;
-      if (bt == 0) partner = row - 1;
       if (bt == 1) {
-        d11 = LD[row + (long)row * a.ldld];
+        d11 = l_rr;
+      } else if (bt == 2) {
+        d11 = l_rr;
+        d21 = l_ur;
+        d22 = l_uu;
       } else {
-        const int k = bt == 2 ? row : row - 1;
-        d11 = LD[k + (long)k * a.ldld];
-        d21 = LD[k + 1 + (long)k * a.ldld];
-        d22 = LD[k + 1 + (long)(k + 1) * a.ldld];
+        d11 = l_dd;
+        d21 = l_rd;
+        d22 = l_rr;
       }
     }
 #pragma unroll
@@ -509,13 +535,13 @@ __global__ __launch_bounds__(256) void k_bwd(SolveArgs a) {
         const int c = 16 * u + g + 4 * r;
         double v = 0.0;
         if (c < nrhs && row < n) {
-          const double z = Z[row + (long)c * a.ldz];
+          const double z = zs[u][r];
           if (!a.applyD) {
             v = z;
           } else if (bt == 1) {
             v = (d11 != 0.0) ? z / d11 : 0.0;
           } else {
-            const double zp = Z[partner + (long)c * a.ldz];
+            const double zp = bt == 2 ? zu[u][r] : zd[u][r];
             // [w1 w2] = D^{-1} [z1 z2], scaled by the off-diagonal as in the factorization
             const double z1 = bt == 2 ? z : zp, z2 = bt == 2 ? zp : z;
             const double aa = d11 / d21, gg = d22 / d21;
