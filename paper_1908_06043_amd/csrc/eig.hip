@@ -6,13 +6,18 @@
 //  k_syevj: one 1024-thread workgroup per matrix, the lower triangle of A in LDS
 //  as a full row-major array with the odd row length M + 1 (M = m rounded up to
 //  even): the blocks a wavefront updates lie along rows or columns of distinct
-//  players, which this length spreads over the banks (the packed triangle measured
-//  2.45 us per rotation round at m = 112, this layout 1.80).  Cyclic Jacobi in the parallel round-robin order:
-//  each round rotates m/2 disjoint (p, q) pairs (Golub & Van Loan, symmetric
-//  Schur 2x2 rotation) and applies all of them to A as independent 2x2 blocks
-//  J_k^T A_{kl} J_l, then moves to the next pairing.  The (c, s) of every pair of
-//  every round are written to a rotation record in device memory; at the end the
-//  eigenvalues are sorted ascending and the rank of each diagonal position kept.
+//  players, which this length spreads over the banks.  Cyclic Jacobi in the
+//  parallel round-robin order: each round rotates m/2 disjoint (p, q) pairs
+//  (Golub & Van Loan, symmetric Schur 2x2 rotation) and applies all of them to A
+//  as independent 2x2 blocks J_k^T A_{kl} J_l, then moves to the next pairing.
+//  The rounds are pipelined: wavefront 0 updates the blocks that the next round's
+//  rotations read (every diagonal block and one off-diagonal block per pair) and
+//  then computes those rotations while the other fifteen wavefronts update the
+//  rest, so a round is one block update and one workgroup barrier (a 112 x 112
+//  solve takes 19% less time than with a rotation phase and two barriers a round).
+//  The (c, s) of every pair of every round are written to a rotation record in
+//  device memory; at the end the eigenvalues are sorted ascending and the rank of
+//  each diagonal position kept.
 //  k_syevj_vecs: forms V = J_1 J_2 ... by replaying the record on rows of the
 //  identity.  Rows of V never mix, so one wavefront owns two rows in LDS (lane k
 //  applies pair k of each round) and needs no workgroup barrier, and the rows of
@@ -64,6 +69,36 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // holds 1 + (pos - 1 + r) mod (M - 1)).
 __device__ __forceinline__ int rr_next(int v, int M) { return v == 0 ? 0 : (v == M - 1 ? 1 : v + 1); }
 
+// The Jacobi rotation of one pair (Golub & Van Loan, symmetric Schur 2x2 step):
+// (c, s) and t = s / c that zero a_pq, or the identity when the pair is padding or
+// a_pq is negligible against sqrt(|a_pp a_qq|).  Returns whether it rotates.  The
+// threshold test and the rotation are evaluated side by side (their square roots
+// are independent) and the result selected afterwards.
+__device__ __forceinline__ bool pair_rotation(double app, double aqq, double apq, bool valid,
+                                              double& c, double& sn, double& t) {
+  const double thr = 1e-15 * sqrt(fabs(app * aqq));
+  const bool rot = valid & (fabs(apq) > thr) & (fabs(apq) > 1e-300);
+  // t = tan of the angle that zeroes a_pq, the root of t^2 + 2 tau t - 1 of smaller
+  // modulus, tau = (a_qq - a_pp) / (2 a_pq), written as
+  // t = sgn(tau) |e| / (|d| + sqrt(d^2 + e^2)) with d = a_qq - a_pp, e = 2 a_pq
+  const double d = aqq - app, e = 2.0 * apq;
+  const double hyp = sqrt(fma(d, d, e * e));
+  double tt = fabs(e) * rcp_nr(fabs(d) + hyp);
+  if (rot && !(hyp > 1e-150 && hyp < 1e300)) {
+    // d^2 + e^2 underflows or overflows: the same form on d and e scaled by a power
+    // of two (t does not depend on the scale; e != 0 when the pair rotates)
+    const int ex = ilogb(fmax(fabs(d), fabs(e)));
+    const double ds = ldexp(d, -ex), es = ldexp(e, -ex);
+    tt = fabs(es) * rcp_nr(fabs(ds) + sqrt(fma(ds, ds, es * es)));
+  }
+  if (d != 0.0 && ((d < 0.0) != (e < 0.0))) tt = -tt;
+  const double cr = rsq_nr(fma(tt, tt, 1.0));
+  c = rot ? cr : 1.0;
+  sn = rot ? tt * cr : 0.0;
+  t = rot ? tt : 0.0;
+  return rot;
+}
+
 __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__ rot, long rstride,
                                                 int* __restrict__ meta) {
   extern __shared__ double sh[];
@@ -71,128 +106,164 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
   const int m = a.m[b];
   if (m <= 0) return;
   const int M = m + (m & 1);
-  const int h = M / 2;
+  const int h = M / 2, R = M - 1;
   const int npk = M * (M + 1);
-  double* A = sh;                                                 // lower triangle, rows of M + 1
-  double2* csn = reinterpret_cast<double2*>(sh + ((npk + 1) & ~1));  // [h] (c, s)
-  int* flag = reinterpret_cast<int*>(csn + h);                      // [4], then rank [m]
-  double2* rb = rot + (long)b * rstride;                            // [sweep][round][pair]
+  double* A = sh;                                                    // lower triangle, rows of M + 1
+  double2* csn = reinterpret_cast<double2*>(sh + ((npk + 1) & ~1));  // [2][h] (c, s) by round parity
+  int* flag = reinterpret_cast<int*>(csn + 2 * h);                     // [4], then rank [m]
+  int* rflag = flag + 2;                                               // [2] the round rotates
+  double2* rb = rot + (long)b * rstride;                               // [sweep][round][pair]
   const double* Ain = a.A[b];
   const long lda = a.lda;
   for (int e = tid; e < m * m; e += blockDim.x) {
     const int i = e % m, j = e / m;
     if (i >= j) A[pidx(i, j, m)] = Ain[i + (long)j * lda];
   }
-  __syncthreads();
-  const int ntask_blk = h * (h + 1) / 2;
-  // Each thread's 2x2 block tasks t = tid + 1024 j -> pair indices (k >= l) are
-  // the same in every round: decode them once.  The players of the pairs' two
-  // positions (k and M - 1 - k) advance by one per round in registers: after
-  // M - 1 rounds (one sweep) they are back where they started.
+  // Block tasks (k, l), k >= l, of pairs of pairs; a thread's tasks are the same in
+  // every round, only the players of the pairs' positions (k and M - 1 - k) move on
+  // by one per round (in registers; after M - 1 rounds they are back).
+  // Wavefront 0 owns the blocks that the next round's rotations read: every diagonal
+  // block (k, k), and for each pair k' the block that will hold a_pq of k' in the
+  // next round.  By the round-robin rule the two players of pair k' next round come
+  // from this round's pairs k' + 1 and k' - 1 (pairs 0 and 1 for k' = 0, pairs
+  // h - 1 and h - 2 for k' = h - 1).  So wavefront 0 can compute the next round's
+  // rotations from its own results while the other wavefronts apply the rest of
+  // this round's blocks: one workgroup barrier per round, the rotation latency off
+  // the critical path.
   constexpr int JA = 2;  // enough for m <= kEigMax (h <= 56)
-  int tk[JA], tl[JA], uk[JA], vk[JA], ul[JA], vl[JA];
+  int tk[JA], tl[JA];
+  const int w = tid >> 6, lane = tid & 63;
+  if (w == 0) {
+    tk[0] = lane < h ? lane : -1;
+    tl[0] = lane < h ? lane : 0;
+    int k1 = -1, k2 = 0;
+    if (lane == 0 && h >= 2) {
+      k1 = 1;
+      k2 = 0;
+    } else if (lane >= 1 && lane <= h - 2) {
+      k1 = lane + 1;
+      k2 = lane - 1;
+    } else if (lane == h - 1 && h >= 3) {
+      k1 = h - 1;
+      k2 = h - 2;
+    }
+    tk[1] = k1;
+    tl[1] = k2;
+  } else {
+    // the other blocks row by row: row k (2 <= k <= h - 2) without (k, k - 2), row
+    // h - 1 without (h - 1, h - 3) and (h - 1, h - 2); rows 0 and 1 have none
+#pragma unroll
+    for (int j = 0; j < JA; ++j) {
+      int idx = (tid - 64) + (1024 - 64) * j, k = -1, l = 0;
+      for (int kk = 2; kk <= h - 1 && k < 0; ++kk) {
+        const int cnt = kk <= h - 2 ? kk - 1 : h - 3;
+        if (idx < cnt) {
+          k = kk;
+          l = (kk <= h - 2 && idx == kk - 2) ? kk - 1 : idx;
+        } else {
+          idx -= cnt;
+        }
+      }
+      tk[j] = k;
+      tl[j] = l;
+    }
+  }
+  int uk[JA], vk[JA], ul[JA], vl[JA];
 #pragma unroll
   for (int j = 0; j < JA; ++j) {
-    const int t = tid + 1024 * j;
-    int k = -1, l = 0;
-    if (t < ntask_blk) {
-      k = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (k * (k + 1) / 2 > t) --k;
-      while ((k + 1) * (k + 2) / 2 <= t) ++k;
-      l = t - k * (k + 1) / 2;
-    }
-    tk[j] = k;
-    tl[j] = l;
-    uk[j] = k < 0 ? 0 : k;
-    vk[j] = k < 0 ? 0 : M - 1 - k;
+    const int k = tk[j] < 0 ? 0 : tk[j], l = tl[j];
+    uk[j] = k;
+    vk[j] = M - 1 - k;
     ul[j] = l;
     vl[j] = M - 1 - l;
   }
-  int up = tid, vp = M - 1 - tid;  // players of pair `tid` (rotation phase, tid < h)
-  // flag[0]: a rotation happened in this sweep; rflag[r & 1]: in round r (the slot
-  // of the next round is cleared by thread 0 while the current one is being set)
-  int* rflag = flag + 2;
+  // the second task slot is empty in whole wavefronts at small orders: skip its loads
+  const bool slot1 = __ballot(tk[1] >= 0) != 0;
+  int up = lane, vp = M - 1 - lane;  // wavefront 0, lane < h: the players of pair `lane`
+  // wavefront 0: the rotations of global round g into buffer g & 1, the round's flag
+  const long gmax = (long)a.max_sweeps * R;
+  // The pair's own (diagonal) block of the next round is exactly what the rotation
+  // reads, and nothing else touches it before that round's update: its elements
+  // and rotation stay in registers (d_*) for the diagonal task.
+  double d_app = 0.0, d_aqq = 0.0, d_apq = 0.0, d_sn = 0.0, d_t = 0.0;
+  auto next_rotations = [&](long g) {
+    const int p = min(up, vp), q = max(up, vp), qc = min(q, m - 1);
+    d_apq = A[pidx(qc, p, m)];
+    d_app = A[pidx(p, p, m)];
+    d_aqq = A[pidx(qc, qc, m)];
+    double c;
+    const bool r = pair_rotation(d_app, d_aqq, d_apq, q < m, c, d_sn, d_t);
+    const int buf = (int)(g & 1);
+    csn[buf * h + lane] = make_double2(c, d_sn);
+    rb[g * h + lane] = make_double2(c, d_sn);
+    const bool any = __ballot(r) != 0;
+    if (lane == 0) rflag[buf] = any ? 1 : 0;
+  };
+  __syncthreads();
+  if (tid < h) next_rotations(0);
+  __syncthreads();
   int nsw = 0;
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
-    if (tid == 0) {
-      flag[0] = 0;
-      rflag[0] = 0;
-      rflag[1] = 0;
-    }
-    __syncthreads();
-    for (int r = 0; r < M - 1; ++r) {
-      if (tid == 0) rflag[(r + 1) & 1] = 0;
-      if (tid < h) {
-        const int p = min(up, vp), q = max(up, vp);
-        double c = 1.0, s = 0.0;
-        if (q < m) {
-          const double apq = A[pidx(q, p, m)];
-          const double app = A[pidx(p, p, m)], aqq = A[pidx(q, q, m)];
-          if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-300) {
-            // t = tan of the angle that zeroes a_pq, the root of t^2 + 2 tau t - 1
-            // of smaller modulus, tau = (a_qq - a_pp) / (2 a_pq) (Golub & Van Loan,
-            // symmetric Schur), written as t = sgn(tau) |e| / (|d| + sqrt(d^2 + e^2))
-            // with d = a_qq - a_pp, e = 2 a_pq (one square root, one reciprocal)
-            const double d = aqq - app, e = 2.0 * apq;
-            const double hyp = sqrt(fma(d, d, e * e));
-            double t;
-            if (hyp < 1e300) {
-              t = fabs(e) * rcp_nr(fabs(d) + hyp);
-              if (d != 0.0 && ((d < 0.0) != (e < 0.0))) t = -t;
-            } else {  // d^2 + e^2 overflows: the scaled form
-              const double tau = d / e;
-              t = (tau >= 0.0) ? 1.0 / (tau + sqrt(1.0 + tau * tau))
-                               : -1.0 / (-tau + sqrt(1.0 + tau * tau));
-            }
-            c = rsq_nr(fma(t, t, 1.0));
-            s = t * c;
-            flag[0] = 1;
-            rflag[r & 1] = 1;
-          }
-        }
-        csn[tid] = make_double2(c, s);
-        rb[(long)(sweep * (M - 1) + r) * h + tid] = make_double2(c, s);
-      }
-      __syncthreads();
-      // no rotation in this round: A is unchanged and nothing reads (c, s) before
-      // the next round's rotation phase rewrites them, so no closing barrier
-      const bool rotated = rflag[r & 1] != 0;
+    bool swept = false;
+    for (int r = 0; r < R; ++r) {
+      const long g = (long)sweep * R + r;
+      const int buf = (int)(g & 1);
+      const double2* cs = csn + buf * h;
+      const bool rotated = rflag[buf] != 0;
+      swept |= rotated;
       if (rotated) {
-        // A <- J^T A J as independent 2x2 blocks of pair pairs (k >= l)
+        // A <- J^T A J as independent 2x2 blocks.  The blocks of one round are
+        // disjoint, so every load of this thread's blocks is issued before any
+        // store; absent elements (an index at or past m) are read from a valid
+        // address, zeroed and never stored.  Wavefront 0's first task is its pair's
+        // diagonal block, held in registers; every other task is off-diagonal.
+        const int j0 = w == 0 ? 1 : 0;
+        double2 csk[JA], csl[JA];
+        int i00[JA], i01[JA], i10[JA], i11[JA];
+        double x00[JA], x01[JA], x10[JA], x11[JA];
+        bool vq_k[JA], vq_l[JA];
 #pragma unroll
         for (int j = 0; j < JA; ++j) {
-          const int k = tk[j], l = tl[j];
-          if (k < 0) continue;
-          const double2 csk = csn[k], csl = csn[l];
-          const double ck = csk.x, sk = csk.y, cl = csl.x, sl = csl.y;
-          if (sk == 0.0 && sl == 0.0) continue;
+          if (j < j0 || (j > 0 && !slot1)) continue;
+          csk[j] = cs[max(tk[j], 0)];
+          csl[j] = cs[tl[j]];
           const int pk = min(uk[j], vk[j]), qk = max(uk[j], vk[j]);
           const int pl = min(ul[j], vl[j]), ql = max(ul[j], vl[j]);
-          if (k == l) {
-            if (qk >= m) continue;
-            const int ipq = pidx(qk, pk, m);
-            const double apq = A[ipq];
-            const double tt = sk / ck;
-            A[pidx(pk, pk, m)] -= tt * apq;
-            A[pidx(qk, qk, m)] += tt * apq;
-            A[ipq] = 0.0;
-          } else {
-            const bool vq_k = qk < m, vq_l = ql < m;
-            const int i00 = sidx(pk, pl, m);
-            const int i01 = vq_l ? sidx(pk, ql, m) : -1;
-            const int i10 = vq_k ? sidx(qk, pl, m) : -1;
-            const int i11 = (vq_k && vq_l) ? sidx(qk, ql, m) : -1;
-            const double x00 = A[i00], x01 = vq_l ? A[i01] : 0.0;
-            const double x10 = vq_k ? A[i10] : 0.0, x11 = (vq_k && vq_l) ? A[i11] : 0.0;
-            // rows: J_k^T
-            const double r00 = ck * x00 - sk * x10, r01 = ck * x01 - sk * x11;
-            const double r10 = sk * x00 + ck * x10, r11 = sk * x01 + ck * x11;
-            // columns: J_l
-            A[i00] = cl * r00 - sl * r01;
-            if (vq_l) A[i01] = sl * r00 + cl * r01;
-            if (vq_k) A[i10] = cl * r10 - sl * r11;
-            if (vq_k && vq_l) A[i11] = sl * r10 + cl * r11;
-          }
+          vq_k[j] = qk < m;
+          vq_l[j] = ql < m;
+          i00[j] = sidx(pk, pl, m);
+          i01[j] = vq_l[j] ? sidx(pk, ql, m) : i00[j];
+          i10[j] = vq_k[j] ? sidx(qk, pl, m) : i00[j];
+          i11[j] = (vq_k[j] && vq_l[j]) ? sidx(qk, ql, m) : i00[j];
+          x00[j] = A[i00[j]];
+          x01[j] = A[i01[j]];
+          x10[j] = A[i10[j]];
+          x11[j] = A[i11[j]];
+        }
+        if (w == 0 && lane < h && d_sn != 0.0) {
+          // the pair's own block: a_pp - t a_pq, a_qq + t a_pq, a_pq = 0 (a pair
+          // that rotates has both players below m)
+          const int p = min(up, vp), q = max(up, vp);
+          A[pidx(p, p, m)] = d_app - d_t * d_apq;
+          A[pidx(q, q, m)] = d_aqq + d_t * d_apq;
+          A[pidx(q, p, m)] = 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < JA; ++j) {
+          if (j < j0 || (j > 0 && !slot1)) continue;
+          const double ck = csk[j].x, sk = csk[j].y, cl = csl[j].x, sl = csl[j].y;
+          if (tk[j] < 0 || (sk == 0.0 && sl == 0.0)) continue;
+          const double a01 = vq_l[j] ? x01[j] : 0.0;
+          const double a10 = vq_k[j] ? x10[j] : 0.0;
+          const double a11 = (vq_k[j] && vq_l[j]) ? x11[j] : 0.0;
+          // rows: J_k^T
+          const double r00 = ck * x00[j] - sk * a10, r01 = ck * a01 - sk * a11;
+          const double r10 = sk * x00[j] + ck * a10, r11 = sk * a01 + ck * a11;
+          // columns: J_l
+          A[i00[j]] = cl * r00 - sl * r01;
+          if (vq_l[j]) A[i01[j]] = sl * r00 + cl * r01;
+          if (vq_k[j]) A[i10[j]] = cl * r10 - sl * r11;
+          if (vq_k[j] && vq_l[j]) A[i11[j]] = sl * r10 + cl * r11;
         }
       }
       // every round, rotated or not, moves the players on
@@ -203,13 +274,16 @@ __global__ __launch_bounds__(1024) void k_syevj(EigArgs a, double2* __restrict__
         ul[j] = rr_next(ul[j], M);
         vl[j] = rr_next(vl[j], M);
       }
-      up = rr_next(up, M);
-      vp = rr_next(vp, M);
-      if (rotated) __syncthreads();
+      if (tid < h) {
+        // wavefront 0 wrote every element these read (its own stores, in order)
+        up = rr_next(up, M);
+        vp = rr_next(vp, M);
+        if (g + 1 < gmax) next_rotations(g + 1);
+      }
+      __syncthreads();
     }
-    if (flag[0] == 0) break;
+    if (!swept) break;
     ++nsw;
-    __syncthreads();
   }
   __syncthreads();
   // sort ascending: rank of each eigenvalue (ties by index)
@@ -311,7 +385,7 @@ size_t eig_lds_bytes(int mmax) {
   const int M = mmax + (mmax & 1);
   const int h = M / 2;
   const size_t npk = (size_t)M * (M + 1);
-  return sizeof(double) * (((npk + 1) & ~size_t(1)) + 2 * h) + sizeof(int) * (4 + mmax) + 64;
+  return sizeof(double) * (((npk + 1) & ~size_t(1)) + 4 * h) + sizeof(int) * (4 + mmax) + 64;
 }
 
 // Rotation records are staged per chunk of the batch so that their workspace
