@@ -19,10 +19,11 @@
 //  device memory; at the end the eigenvalues are sorted ascending and the rank of
 //  each diagonal position kept.
 //  k_syevj_vecs: forms V = J_1 J_2 ... by replaying the record on rows of the
-//  identity.  Rows of V never mix, so one wavefront owns two rows in LDS (lane k
-//  applies pair k of each round) and needs no workgroup barrier, and the rows of
-//  one matrix spread over many CUs instead of sharing the LDS bandwidth of the one
-//  CU that runs the rotations.
+//  identity.  Rows of V never mix and a round moves every player one position
+//  along a fixed conveyor, so each lane keeps the two entries of its pair's
+//  players in registers and passes them to the neighbouring lanes after each
+//  round (cross-lane moves, no LDS, no barrier); the rows of one matrix spread over
+//  many CUs instead of sharing the CU that runs the rotations.
 // A rotation is skipped when |a_pq| <= 1e-15 sqrt(|a_pp a_qq|) (relative
 // threshold, so tiny and large eigenvalues both converge to full relative
 // accuracy); the iteration stops after a sweep without rotations.
@@ -310,11 +311,32 @@ constexpr int kVecWaves = 4;
 constexpr int kVecRows = kVecRowsPerWave * kVecWaves;  // rows of V per workgroup
 constexpr int kVecPf = 16;                              // rounds of (c, s) loaded ahead
 
+// Whole-wavefront lane shifts by one (DPP wave_shl:1 and wave_shr:1): lane k receives
+// the value of lane k + 1, respectively k - 1 (0 past the ends).
+__device__ __forceinline__ double from_next_lane(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0x130, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_prev_lane(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), 0x138, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Rows of V never mix, and in the round-robin order a round moves every player one
+// position along a fixed conveyor: so lane k of a wavefront keeps, for each of its
+// rows, the entries of the two players at positions k and M - 1 - k (pair k) in
+// registers, applies pair k's rotation of the round to them, then passes them on to
+// the neighbouring lanes (the entry at position k + 1 comes from lane k + 1, the one
+// at M - k from lane k - 1, with the turn-arounds at lanes 0 and h - 1).  No LDS, no
+// barrier; after whole sweeps every player is back at its starting position.
 __global__ __launch_bounds__(64 * kVecWaves) void k_syevj_vecs(EigArgs a,
                                                                const double2* __restrict__ rot,
                                                                long rstride,
                                                                const int* __restrict__ meta) {
-  __shared__ double Vs[kVecRows][kEigMax];
   const int b = blockIdx.x;
   const int m = a.m[b];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -323,61 +345,70 @@ __global__ __launch_bounds__(64 * kVecWaves) void k_syevj_vecs(EigArgs a,
   const int M = m + (m & 1), h = M / 2, R = M - 1;
   const int* mb = meta + (long)b * kMetaStride;
   const long total = (long)mb[0] * R;  // rounds to replay
-  const bool has1 = i0 + 1 < m;
-  double* v0 = Vs[w * kVecRowsPerWave];
-  double* v1 = Vs[w * kVecRowsPerWave + 1];
-  for (int j = lane; j < m; j += 64) {
-    v0[j] = (j == i0) ? 1.0 : 0.0;
-    v1[j] = (j == i0 + 1) ? 1.0 : 0.0;
-  }
   const bool act = lane < h;
-  // players of pair `lane` in round r (the round-robin of k_syevj), advanced by one
-  // position per round: 1..R cyclically, player 0 fixed
+  // players at this lane's two positions, advanced by one position per round
   int pa = lane, pb = M - 1 - lane;
-  const double2* rb = rot + (long)b * rstride + lane;
-  double2 cur[kVecPf], nxt[kVecPf];
+  double lo[kVecRowsPerWave], hi[kVecRowsPerWave];
 #pragma unroll
-  for (int j = 0; j < kVecPf; ++j)
-    cur[j] = (act && j < total) ? rb[(long)j * h] : make_double2(1.0, 0.0);
-  for (long g0 = 0; g0 < total; g0 += kVecPf) {
+  for (int r = 0; r < kVecRowsPerWave; ++r) {
+    lo[r] = (act && pa == i0 + r) ? 1.0 : 0.0;
+    hi[r] = (act && pb == i0 + r) ? 1.0 : 0.0;
+  }
+  // (c, s) of this lane's pair, kVecPf rounds per buffer, two buffers in turn: one
+  // is replayed while the next is loaded.  Rounds past the end are loaded from the
+  // last one (clamped, so every load is unconditional) and never replayed.  Lanes
+  // past the pairs read pair 0's record; their entries never reach an active lane.
+  const double2* rb = rot + (long)b * rstride + (act ? lane : 0);
+  auto fetch = [&](double2* buf, long g0) {
+#pragma unroll
+    for (int j = 0; j < kVecPf; ++j) buf[j] = rb[min(g0 + j, total - 1) * h];
+  };
+  auto replay = [&](const double2* buf, long g0) {
 #pragma unroll
     for (int j = 0; j < kVecPf; ++j) {
-      const long g = g0 + kVecPf + j;
-      nxt[j] = (act && g < total) ? rb[g * h] : make_double2(1.0, 0.0);
-    }
+      if (g0 + j >= total) break;  // uniform per wavefront
+      // the rotation of pair (p, q) acts on (v_p, v_q); with p at position
+      // M - 1 - k instead of k the same formula holds with s negated
+      const double c = buf[j].x, s = pa < pb ? buf[j].y : -buf[j].y;
 #pragma unroll
-    for (int j = 0; j < kVecPf; ++j) {
-      // guard rather than break: the loop unrolls fully and cur[] stays in registers
-      const bool live = g0 + j < total;  // uniform per wavefront
-      // the writes of the previous round (other lanes' columns) are read below
-      asm volatile("" ::: "memory");
-      __builtin_amdgcn_wave_barrier();
-      const double c = cur[j].x, s = cur[j].y;
-      const int p = min(pa, pb), q = max(pa, pb);
-      if (live && act && s != 0.0 && q < m) {
-        const double x0 = v0[p], y0 = v0[q];
-        v0[p] = c * x0 - s * y0;
-        v0[q] = s * x0 + c * y0;
-        if (has1) {
-          const double x1 = v1[p], y1 = v1[q];
-          v1[p] = c * x1 - s * y1;
-          v1[q] = s * x1 + c * y1;
+      for (int r = 0; r < kVecRowsPerWave; ++r) {
+        const double x = lo[r], y = hi[r];
+        lo[r] = c * x - s * y;
+        hi[r] = s * x + c * y;
+      }
+      if (h > 1) {  // uniform; with one pair nothing moves
+#pragma unroll
+        for (int r = 0; r < kVecRowsPerWave; ++r) {
+          const double up = from_next_lane(lo[r]), dn = from_prev_lane(hi[r]);
+          const double nlo = lane == 0 ? lo[r] : (lane == h - 1 ? hi[r] : up);
+          hi[r] = lane == 0 ? up : dn;
+          lo[r] = nlo;
         }
       }
       if (lane != 0) pa = (pa == R) ? 1 : pa + 1;
       pb = (pb == R) ? 1 : pb + 1;
     }
-#pragma unroll
-    for (int j = 0; j < kVecPf; ++j) cur[j] = nxt[j];
+  };
+  if (total > 0) {
+    double2 bufa[kVecPf], bufb[kVecPf];
+    fetch(bufa, 0);
+    for (long g0 = 0; g0 < total; g0 += 2 * kVecPf) {
+      fetch(bufb, g0 + kVecPf);
+      replay(bufa, g0);
+      if (g0 + kVecPf >= total) break;
+      fetch(bufa, g0 + 2 * kVecPf);
+      replay(bufb, g0 + kVecPf);
+    }
   }
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
+  if (!act) return;
   double* Vout = a.V[b];
   const long ldv = a.ldv;
-  for (int j = lane; j < m; j += 64) {
-    const long col = (long)mb[1 + j] * ldv;
-    Vout[i0 + col] = v0[j];
-    if (has1) Vout[i0 + 1 + col] = v1[j];
+#pragma unroll
+  for (int r = 0; r < kVecRowsPerWave; ++r) {
+    const int i = i0 + r;
+    if (i >= m) break;
+    Vout[i + (long)mb[1 + pa] * ldv] = lo[r];
+    if (pb < m) Vout[i + (long)mb[1 + pb] * ldv] = hi[r];
   }
 }
 
