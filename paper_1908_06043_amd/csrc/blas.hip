@@ -5,8 +5,8 @@
 //
 // GEMM design (gfx950): 64x64 output tile per 256-thread workgroup, four
 // wavefronts each owning 32x32 as 2x2 v_mfma_f64_16x16x4 blocks; K staged
-// through double-buffered LDS in chunks of 16 (sA[k][i], sB[k][j]), the next
-// chunk's loads in flight during the current chunk's MFMAs.  The MFMA A operand carries
+// through double-buffered LDS in chunks of 16 (sA[k][i], sB[k][j]), the next two
+// chunks' loads in flight during the current chunk's MFMAs.  The MFMA A operand carries
 // op(B)^T and the B operand op(A)^T so that accumulator register r of lane l
 // holds C(i0 + l%16, j0 + l/16 + 4r): sixteen consecutive rows of one column,
 // i.e. coalesced column-major stores.  Transposed operands only change the
@@ -21,7 +21,7 @@ constexpr int GT = 64;   // tile rows/cols
 constexpr int GK = 16;   // K chunk
 
 template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+__global__ __launch_bounds__(256, 4) void k_gemm(GemmArgs g) {
   __shared__ double sA[2][GK][GT + 2];
   __shared__ double sB[2][GK][GT + 2];
   const int zb = blockIdx.z;
@@ -45,61 +45,54 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int y = 0; y < 2; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
   // Staging: element e = tid + 256 q of a chunk, read along the contiguous
-  // dimension of each operand; the next chunk is in registers while the current
-  // one feeds the MFMAs, so one barrier per chunk suffices.
+  // dimension of each operand.  Two register sets hold the chunks after the one in
+  // LDS: chunk c + 2 is loaded while chunk c feeds the MFMAs and chunk c + 1 is
+  // written to the other LDS buffer, one barrier per chunk; two chunks in flight per
+  // workgroup are what hides the memory latency at four workgroups per CU.
+  // The loads are buffer loads from a descriptor based at the tile's corner of the
+  // chunk: a lane's offset is small and fixed, and an element outside the operand
+  // gets an offset past the descriptor's range, which the hardware reads as zero.
   constexpr int NQ = GK * GT / 256;
-  double ra[NQ], rb[NQ];
-  auto a_pos = [&](int q, int& ii, int& kk) {
-    const int e = tid + 256 * q;
-    if (!TA) {
-      ii = e & 63;
-      kk = e >> 6;
-    } else {
-      kk = e & 15;
-      ii = e >> 4;
-    }
-  };
-  auto b_pos = [&](int q, int& jj, int& kk) {
-    const int e = tid + 256 * q;
-    if (!TB) {
-      kk = e & 15;
-      jj = e >> 4;
-    } else {
-      jj = e & 63;
-      kk = e >> 6;
-    }
-  };
-  auto fetch = [&](int k0) {
+  constexpr unsigned kOut = 0x80000000u;  // past kRange: reads as 0
+  constexpr int kRange = 0x7fffffff;
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  double ra[2][NQ], rb[2][NQ];
+  // Load q of a thread: A element (row ia0 + q da_i, k ka0 + q da_k) of the chunk,
+  // B element (k kb0 + q db_k, column ib0 + q db_j): along the contiguous dimension
+  // the 256 threads cover the tile's 64 entries or the chunk's 16 once per q.
+  const int ia0 = TA ? tid >> 4 : tid & 63, ka0 = TA ? tid & 15 : tid >> 6;
+  constexpr int da_i = TA ? 16 : 0, da_k = TA ? 0 : 4;
+  const int ib0 = TB ? tid & 63 : tid >> 4, kb0 = TB ? tid >> 6 : tid & 15;
+  constexpr int db_j = TB ? 0 : 16, db_k = TB ? 4 : 0;
+  // byte offsets from the chunk's corner and their per-q strides
+  const unsigned oa0 = 8u * (unsigned)(TA ? ka0 + ia0 * g.lda : ia0 + ka0 * g.lda);
+  const unsigned sa = 8u * (unsigned)(TA ? da_i * g.lda : da_k * g.lda);
+  const unsigned ob0 = 8u * (unsigned)(TB ? ib0 + kb0 * g.ldb : kb0 + ib0 * g.ldb);
+  const unsigned sbq = 8u * (unsigned)(TB ? db_k * g.ldb : db_j * g.ldb);
+  auto fetch = [&](int s, int k0) {
+    // corners of the chunk in A (rows i0.., k k0..) and in B (k k0.., columns j0..)
+    const double* ca = TA ? A + k0 + (long)i0 * g.lda : A + i0 + (long)k0 * g.lda;
+    const double* cb = TB ? B + j0 + (long)k0 * g.ldb : B + k0 + (long)j0 * g.ldb;
+    const __amdgpu_buffer_rsrc_t da = __builtin_amdgcn_make_buffer_rsrc((void*)ca, (short)0, kRange, 0x00020000);
+    const __amdgpu_buffer_rsrc_t db = __builtin_amdgcn_make_buffer_rsrc((void*)cb, (short)0, kRange, 0x00020000);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      int ii, kk, jj, kk2;
-      a_pos(q, ii, kk);
-      b_pos(q, jj, kk2);
-      const int gi = i0 + ii, gk = k0 + kk;
-      ra[q] = (gi < m && gk < ke) ? (TA ? A[gk + (long)gi * g.lda] : A[gi + (long)gk * g.lda]) : 0.0;
-      const int gj = j0 + jj, gk2 = k0 + kk2;
-      rb[q] = (gj < n && gk2 < ke) ? (TB ? B[gj + (long)gk2 * g.ldb] : B[gk2 + (long)gj * g.ldb]) : 0.0;
+      const bool va = (i0 + ia0 + q * da_i < m) & (k0 + ka0 + q * da_k < ke);
+      const bool vb = (j0 + ib0 + q * db_j < n) & (k0 + kb0 + q * db_k < ke);
+      const u2 xa = __builtin_amdgcn_raw_buffer_load_b64(da, (int)(va ? oa0 + q * sa : kOut), 0, 0);
+      const u2 xb = __builtin_amdgcn_raw_buffer_load_b64(db, (int)(vb ? ob0 + q * sbq : kOut), 0, 0);
+      ra[s][q] = __builtin_bit_cast(double, xa);
+      rb[s][q] = __builtin_bit_cast(double, xb);
     }
   };
-  auto stage = [&](int buf) {
+  auto stage = [&](int buf, int s) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      int ii, kk, jj, kk2;
-      a_pos(q, ii, kk);
-      b_pos(q, jj, kk2);
-      sA[buf][kk][ii] = ra[q];
-      sB[buf][kk2][jj] = rb[q];
+      sA[buf][ka0 + q * da_k][ia0 + q * da_i] = ra[s][q];
+      sB[buf][kb0 + q * db_k][ib0 + q * db_j] = rb[s][q];
     }
   };
-  if (kb < ke) {
-    fetch(kb);
-    stage(0);
-  }
-  __syncthreads();
-  int buf = 0;
-  for (int k0 = kb; k0 < ke; k0 += GK) {
-    const bool more = k0 + GK < ke;
-    if (more) fetch(k0 + GK);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       const double bA0 = sA[buf][kk + lk][wi + lr], bA1 = sA[buf][kk + lk][wi + 16 + lr];
@@ -109,9 +102,27 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       acc[1][0] = mfma16x16x4(aB0, bA1, acc[1][0]);
       acc[1][1] = mfma16x16x4(aB1, bA1, acc[1][1]);
     }
-    if (more) stage(buf ^ 1);
+  };
+  // Chunk c sits in LDS buffer c & 1 and came through register set c & 1.  The
+  // fetches are unconditional (past the end every element reads as zero and is never
+  // staged), so the wait before each stage always leaves the newest set in flight.
+  const int nch = kb < ke ? (ke - kb + GK - 1) / GK : 0;
+  if (nch > 0) {
+    fetch(0, kb);
+    fetch(1, kb + GK);
+    stage(0, 0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nch; c += 2) {
+    fetch(0, kb + (c + 2) * GK);
+    compute(0);
+    if (c + 1 < nch) stage(1, 1);
     __syncthreads();
-    buf ^= 1;
+    if (c + 1 >= nch) break;
+    fetch(1, kb + (c + 3) * GK);
+    compute(1);
+    if (c + 2 < nch) stage(0, 0);
+    __syncthreads();
   }
   if (g.splits > 1) {
     double* P = g.partial + ((long)b * g.splits + sp) * g.pstride;
@@ -150,9 +161,18 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
   double* C = g.C ? g.C[b] : g.C1;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)m * n; e += (long)gridDim.x * 256) {
     const int i = (int)(e % m), j = (int)(e / m);
+    const double* P = g.partial + (long)b * g.splits * g.pstride + i + (long)j * g.pld;
+    // summed in split order; eight loads issued at a time
     double s = 0.0;
-    for (int sp = 0; sp < g.splits; ++sp)
-      s += g.partial[((long)b * g.splits + sp) * g.pstride + i + (long)j * g.pld];
+    int sp = 0;
+    for (; sp + 8 <= g.splits; sp += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = P[(long)(sp + t) * g.pstride];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s += v[t];
+    }
+    for (; sp < g.splits; ++sp) s += P[(long)sp * g.pstride];
     double* c = C + i + (long)j * g.ldc;
     const double v = g.alpha * s;
     *c = (g.beta == 0.0) ? v : v + g.beta * *c;

@@ -209,7 +209,9 @@ inline void gemm(Ctx& c, bool ta, bool tb, const std::vector<int>& m, const std:
   int splits = 1;
   const long tiles = ceil_div(mmax, 64) * ceil_div(nmax, 64) * (long)batch;
   if (kmax >= 1024 && tiles < 512) {
-    splits = (int)std::min<long>(std::max<long>(1, 1024 / tiles), kmax / 256);
+    // splits at least 256 deep; 64 deep (four K chunks) for outputs of a few tiles,
+    // the Gram-type products V^T w of the reorthogonalisations
+    splits = (int)std::min<long>(std::max<long>(1, 1024 / tiles), kmax / (tiles < 16 ? 64 : 256));
     splits = std::max(1, std::min(splits, 64));
   }
   g.splits = splits;
