@@ -283,6 +283,68 @@ __global__ __launch_bounds__(256) void k_skinny_mm(int n, const double* __restri
   }
 }
 
+// MFMA form for 8..32 columns.  With the columns broadcast from LDS, the VALU form
+// spends ten 16-byte LDS reads per row of M for its 20 FMAs a lane: bound by LDS.  Here
+// wavefront w owns rows i0 + 16 w .. + 15 and one or two 16-column blocks of the
+// output; per k-step of 4 it streams one entry of M per lane (the MFMA's A operand,
+// 16 rows x 4 k) and reads one X entry per lane and block from LDS (the B operand),
+// with 16 loads of M in flight.  Columns past NC read a valid column and are zeroed.
+// Partial layout and chunk skipping as in k_skinny_mm.
+template <int NC>
+__global__ __launch_bounds__(256) void k_skinny_mfma(int n, const double* __restrict__ M, long ldm,
+                                                     int tri, const double* __restrict__ X,
+                                                     long ldx, double* __restrict__ P, int pcols,
+                                                     int c_off) {
+  constexpr int NB = (NC + 15) / 16;  // 16-column blocks
+  constexpr int SP = NC + 2;          // LDS row stride (doubles)
+  constexpr int NS = kSkinnyKc / 4;   // k-steps per chunk
+  constexpr int PF = 16;              // loads of M in flight per lane
+  __shared__ double sh[kSkinnyKc * SP];
+  const int t = blockIdx.x, q = blockIdx.y;
+  const int i0 = t * 64, kc = q * kSkinnyKc;
+  if (!skinny_chunk_live(tri, i0, kc)) return;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  // X chunk, k-major: sh[k * SP + c] = X(kc + k, c), zero past n
+  for (int e = tid; e < kSkinnyKc * NC; e += 256) {
+    const int k = e % kSkinnyKc, c = e / kSkinnyKc;
+    sh[k * SP + c] = (kc + k < n) ? X[kc + k + (long)c * ldx] : 0.0;
+  }
+  __syncthreads();
+  const int row = i0 + 16 * w + lr;
+  const double* Mr = M + min(row, n - 1);
+  // k past n reads a valid entry: its X row is zero
+  auto ldm_at = [&](int s) { return Mr[(long)min(kc + 4 * s + lk, n - 1) * ldm]; };
+  d4 acc[NB];
+#pragma unroll
+  for (int bb = 0; bb < NB; ++bb) acc[bb] = d4{0.0, 0.0, 0.0, 0.0};
+  double mv[PF];
+#pragma unroll
+  for (int j = 0; j < PF; ++j) mv[j] = ldm_at(j);
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const double a = mv[s % PF];
+    if (s + PF < NS) mv[s % PF] = ldm_at(s + PF);
+    const double* xs = sh + (4 * s + lk) * SP;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb) {
+      const int c = 16 * bb + lr;
+      const double xv = xs[c < NC ? c : 0];
+      acc[bb] = mfma16x16x4(c < NC ? xv : 0.0, a, acc[bb]);
+    }
+  }
+  // acc[bb] register r of lane l: output row i0 + 16 w + lr, column 16 bb + lk + 4 r
+  if (row < n) {
+    double* Pq = P + (long)q * n * pcols + (long)c_off * n;
+#pragma unroll
+    for (int bb = 0; bb < NB; ++bb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * bb + lk + 4 * r;
+        if (c < NC) Pq[row + (long)c * n] = acc[bb][r];
+      }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_skinny_reduce(int n, int ncol, int nchunk, int tri,
                                                        const double* __restrict__ P, double alpha,
                                                        double beta, double* __restrict__ C,
@@ -304,8 +366,12 @@ template <int NC>
 static void skinny_part(int n, const double* M, long ldm, int tri, const double* X, long ldx,
                         double* partial, int pcols, int c_off, hipStream_t st) {
   const int nchunk = (int)ceil_div(n, kSkinnyKc);
-  SL_LAUNCH((k_skinny_mm<NC>), dim3((unsigned)ceil_div(n, 64), nchunk), dim3(256), 0, st, n, M,
-            ldm, tri, X + (long)c_off * ldx, ldx, partial, pcols, c_off);
+  if constexpr (NC >= 8)
+    SL_LAUNCH((k_skinny_mfma<NC>), dim3((unsigned)ceil_div(n, 64), nchunk), dim3(256), 0, st, n,
+              M, ldm, tri, X + (long)c_off * ldx, ldx, partial, pcols, c_off);
+  else
+    SL_LAUNCH((k_skinny_mm<NC>), dim3((unsigned)ceil_div(n, 64), nchunk), dim3(256), 0, st, n, M,
+              ldm, tri, X + (long)c_off * ldx, ldx, partial, pcols, c_off);
   SL_LAUNCH_CHECK();
 }
 
