@@ -631,6 +631,116 @@ void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, d
   SL_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------ single-vector Lanczos step tail
+//
+// After w = H v_j, one step of the single-vector Lanczos run that bounds the spectrum
+// ends with alpha_j = v_j^T w, two classical Gram-Schmidt passes of w against
+// V[:, 0..j], beta_j = ||w|| and v_{j+1} = w / beta_j.  V has at most 61 columns and
+// stays in L2, so one 1024-thread workgroup does all of it in one launch: eleven short
+// launches before, whose gaps cost more than their work.  Every sum is taken in a
+// fixed order (a lane's rows in order, the wavefront's butterfly, the sixteen
+// wavefronts in order), so the result is deterministic.
+__device__ __forceinline__ double lt_wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__global__ __launch_bounds__(1024) void k_lanczos_tail(int n, int j, double* __restrict__ V,
+                                                       double* __restrict__ wv,
+                                                       double* __restrict__ alpha,
+                                                       double* __restrict__ s2,
+                                                       double* __restrict__ beta) {
+  extern __shared__ double sw[];  // w of the pass, n doubles
+  __shared__ double coef[kLanczosTailMaxCols];
+  __shared__ double red[16];
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int nc = j + 1;
+  auto block_sum = [&](double v) -> double {  // every thread gets the sum
+    v = lt_wave_sum(v);
+    __syncthreads();
+    if (l == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) t += red[q];
+    return t;
+  };
+  {
+    const double* vj = V + (long)j * n;
+    double s = 0.0;
+    for (int r = tid; r < n; r += 1024) s += vj[r] * wv[r];
+    const double a = block_sum(s);
+    if (tid == 0) alpha[j] = a;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int r = tid; r < n; r += 1024) sw[r] = wv[r];
+    __syncthreads();
+    // coef_i = V[:, i]^T w: wavefront i mod 16 takes column i; eight loads of the
+    // column in flight per lane, into eight partial sums added in order
+    for (int i = wave; i < nc; i += 16) {
+      const double* vi = V + (long)i * n;
+      double p8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int r = l;
+      for (; r + 7 * 64 < n; r += 8 * 64) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = vi[r + 64 * u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) p8[u] += x[u] * sw[r + 64 * u];
+      }
+      for (int u = 0; r < n; r += 64, ++u) p8[u] += vi[r] * sw[r];
+      double s = 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p8[u];
+      s = lt_wave_sum(s);
+      if (l == 0) coef[i] = s;
+    }
+    __syncthreads();
+    // w -= V coef (a thread's rows only), eight columns' loads in flight
+    for (int r = tid; r < n; r += 1024) {
+      double acc = 0.0;
+      int i = 0;
+      for (; i + 8 <= nc; i += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = V[r + (long)(i + u) * n];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += x[u] * coef[i + u];
+      }
+      for (; i < nc; ++i) acc += V[r + (long)i * n] * coef[i];
+      wv[r] = sw[r] - acc;
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int r = tid; r < n; r += 1024) s += wv[r] * wv[r];
+  const double t = block_sum(s);
+  const double nr = sqrt(fmax(t, 0.0));
+  const double f = nr > 0.0 ? 1.0 / nr : 0.0;
+  double* vn = V + (long)(j + 1) * n;
+  for (int r = tid; r < n; r += 1024) vn[r] = wv[r] * f;
+  if (tid == 0) {
+    s2[j] = t;
+    beta[j] = nr;
+  }
+}
+
+void lanczos_tail_launch(int n, int j, double* V, double* w, double* alpha, double* s2,
+                         double* beta, hipStream_t st) {
+  static std::once_flag attr;
+  std::call_once(attr, [] {
+    SL_HIP(hipFuncSetAttribute((const void*)k_lanczos_tail,
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)(kLanczosTailMaxN * sizeof(double))));
+  });
+  SL_CHECK_ARG(n >= 1 && n <= kLanczosTailMaxN, "Lanczos step tail: order out of range");
+  SL_CHECK_ARG(j >= 0 && j + 1 <= kLanczosTailMaxCols, "Lanczos step tail: too many columns");
+  SL_LAUNCH(k_lanczos_tail, dim3(1), dim3(1024), (size_t)n * sizeof(double), st, n, j, V, w,
+            alpha, s2, beta);
+  SL_LAUNCH_CHECK();
+}
+
 // Y[:, c] = X[:, c] / sqrt(s2[c]) for ncol columns (zero when s2 <= 0), rec[c] = sqrt(s2[c]).
 __global__ __launch_bounds__(256) void k_scale_cols(int n, const double* __restrict__ s2,
                                                     const double* __restrict__ X, long ldx,

@@ -48,6 +48,14 @@ void lincomb3_launch(long tot, double f1, const double* X, double f2, const doub
                      const double* Z, double* out, hipStream_t st);
 void scale_by_norm_launch(int n, const double* s2, const double* x, double* y, double* rec,
                           hipStream_t st);
+// One step tail of the single-vector Lanczos on H after w = H v_j (V: n x (j + 2), columns
+// contiguous): alpha[j] = v_j^T w; w orthogonalised twice against V[:, 0..j] (classical
+// Gram-Schmidt); s2[j] = ||w||^2, beta[j] = ||w||, V[:, j + 1] = w / beta[j] (zero when
+// beta[j] == 0).  One workgroup; n <= kLanczosTailMaxN, j + 1 <= kLanczosTailMaxCols.
+constexpr int kLanczosTailMaxN = 16384;
+constexpr int kLanczosTailMaxCols = 64;
+void lanczos_tail_launch(int n, int j, double* V, double* w, double* alpha, double* s2,
+                         double* beta, hipStream_t st);
 void transpose_launch(int n, const double* S, long lds, double* T, long ldt, hipStream_t st);
 // Y[:, c] = X[:, c] / sqrt(s2[c]) (ncol columns), rec[c] = sqrt(s2[c]) (may be null).
 void scale_cols_launch(int n, int ncol, const double* s2, const double* X, long ldx, double* Y,

@@ -355,6 +355,11 @@ sislice_status plan_impl(sislice_handle* h, int64_t n64, const double* A, int64_
   for (int j = 0; j < m_b; ++j) {
     double* vj = Vb + (size_t)j * n;
     apply_H(vj, wv, 1);
+    if (n <= kLanczosTailMaxN) {
+      // alpha, the two Gram-Schmidt passes, beta and the next vector in one workgroup
+      lanczos_tail_launch(n, j, Vb, wv, d_alpha, d_s2, d_beta, st);
+      continue;
+    }
     dot1(vj, wv, d_alpha + j);
     for (int pass = 0; pass < 2; ++pass) {
       // coef = V^T w ; w -= V coef
