@@ -35,25 +35,48 @@ void jackson(int M, double* g) {
 
 // Phi(omega) = N [g0 mu0 (1 - th/pi) - (2/pi) sum_{k>=1} g_k mu_k sin(k th)/k],
 // th = arccos((omega - c)/d): the integral of the Jackson-damped Chebyshev
-// density from the bottom of [a, b] up to omega.
-double kpm_cdos(const double* mu, const double* g, int M, double a, double b, int64_t n,
-                double omega) {
+// density from the bottom of [a, b] up to omega.  With the coefficients
+// e_0 = g0 mu0 and e_k = (2/pi) g_k mu_k / k (k >= 1) formed once,
+// Phi = N [e_0 (1 - th/pi) - sum_k e_k sin(k th)].
+static void cdos_coefs(const double* mu, const double* g, int M, double* e) {
+  e[0] = g[0] * mu[0];
+  for (int k = 1; k < M; ++k) e[k] = (2.0 / M_PI) * g[k] * mu[k] / k;
+}
+
+static double cdos_eval(const double* e, int M, double a, double b, int64_t n, double omega) {
   const double c = 0.5 * (a + b), d = 0.5 * (b - a);
   double t = (omega - c) / d;
   t = std::min(1.0, std::max(-1.0, t));
   const double th = std::acos(t);
-  double acc = g[0] * mu[0] * (1.0 - th / M_PI);
-  for (int k = 1; k < M; ++k) acc -= (2.0 / M_PI) * g[k] * mu[k] * std::sin(k * th) / k;
+  double acc = e[0] * (1.0 - th / M_PI);
+  // sin(k th) from the rotation (cos kth, sin kth) <- (cos th, sin th) (cos (k-1)th, sin (k-1)th):
+  // one sine and one cosine per evaluation instead of one sine per term (the bisections of
+  // the placement evaluate this a few hundred times); the rotation's error grows linearly in k
+  const double c1 = std::cos(th), s1 = std::sin(th);
+  double ck = c1, sk = s1;
+  for (int k = 1; k < M; ++k) {
+    acc -= e[k] * sk;
+    const double cn = ck * c1 - sk * s1;
+    sk = sk * c1 + ck * s1;
+    ck = cn;
+  }
   return (double)n * acc;
 }
 
-double kpm_root(double target, const double* mu, const double* g, int M, double a, double b,
-                int64_t n) {
+double kpm_cdos(const double* mu, const double* g, int M, double a, double b, int64_t n,
+                double omega) {
+  std::vector<double> e(M);
+  cdos_coefs(mu, g, M, e.data());
+  return cdos_eval(e.data(), M, a, b, n, omega);
+}
+
+// bisection to 1e-12 (b - a) on the coefficients of cdos_coefs
+static double kpm_root(double target, const double* e, int M, double a, double b, int64_t n) {
   double lo = a, hi = b;
   const double tol = 1e-12 * (b - a);
   while (hi - lo > tol) {
     const double mid = 0.5 * (lo + hi);
-    if (kpm_cdos(mu, g, M, a, b, n, mid) < target)
+    if (cdos_eval(e, M, a, b, n, mid) < target)
       lo = mid;
     else
       hi = mid;
@@ -63,15 +86,16 @@ double kpm_root(double target, const double* mu, const double* g, int M, double 
 
 void kpm_place(const double* mu, int M, double a, double b, int64_t n, int64_t n_e, int64_t n_s,
                double top_margin, double* sigmas, double* omega_top) {
-  std::vector<double> g(M);
+  std::vector<double> g(M), e(M);
   jackson(M, g.data());
+  cdos_coefs(mu, g.data(), M, e.data());
   const double K = (double)n_e / (double)n_s;
   const double top_count = (double)n_e + top_margin * K;
-  *omega_top = kpm_root(top_count, mu, g.data(), M, a, b, n);
+  *omega_top = kpm_root(top_count, e.data(), M, a, b, n);
   const double Kp = top_count / (double)n_s;
   double prev = a;
   for (int64_t j = 1; j <= n_s; ++j) {
-    const double w = kpm_root(j * Kp, mu, g.data(), M, a, b, n);
+    const double w = kpm_root(j * Kp, e.data(), M, a, b, n);
     sigmas[j - 1] = 0.5 * (prev + w);
     prev = w;
   }
