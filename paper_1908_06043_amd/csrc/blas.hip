@@ -353,9 +353,21 @@ __global__ __launch_bounds__(256) void k_skinny_reduce(int n, int ncol, int nchu
   for (long e = blockIdx.x * 256L + threadIdx.x; e < tot; e += (long)gridDim.x * 256) {
     const int i = (int)(e % n), c = (int)(e / n);
     const int i0 = (i / 64) * 64;
+    const double* Pe = P + i + (long)c * n;
+    // summed in chunk order over the live chunks; eight loads issued at a time (a dead
+    // chunk's partial is read but not added)
     double s = 0.0;
-    for (int q = 0; q < nchunk; ++q)
-      if (skinny_chunk_live(tri, i0, q * kSkinnyKc)) s += P[(long)q * tot + i + (long)c * n];
+    int q = 0;
+    for (; q + 8 <= nchunk; q += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Pe[(long)(q + u) * tot];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (skinny_chunk_live(tri, i0, (q + u) * kSkinnyKc)) s += v[u];
+    }
+    for (; q < nchunk; ++q)
+      if (skinny_chunk_live(tri, i0, q * kSkinnyKc)) s += Pe[(long)q * tot];
     double* cp = C + i + (long)c * ldc;
     const double v = alpha * s;
     *cp = (beta == 0.0) ? v : v + beta * *cp;
