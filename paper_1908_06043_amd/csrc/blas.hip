@@ -17,6 +17,22 @@
 
 namespace sislice {
 
+// p[0] + p[stride] + ... + p[(cnt - 1) stride], added in that order, with eight loads in
+// flight (a plain loop issues one load per round trip): the split-K reductions.
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ p, long stride, int cnt) {
+  double s = 0.0;
+  int q = 0;
+  for (; q + 8 <= cnt; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(long)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < cnt; ++q) s += p[(long)q * stride];
+  return s;
+}
+
 constexpr int GT = 64;   // tile rows/cols
 constexpr int GK = 16;   // K chunk
 
@@ -161,18 +177,9 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
   double* C = g.C ? g.C[b] : g.C1;
   for (long e = blockIdx.x * 256L + threadIdx.x; e < (long)m * n; e += (long)gridDim.x * 256) {
     const int i = (int)(e % m), j = (int)(e / m);
-    const double* P = g.partial + (long)b * g.splits * g.pstride + i + (long)j * g.pld;
-    // summed in split order; eight loads issued at a time
-    double s = 0.0;
-    int sp = 0;
-    for (; sp + 8 <= g.splits; sp += 8) {
-      double v[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) v[t] = P[(long)(sp + t) * g.pstride];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) s += v[t];
-    }
-    for (; sp < g.splits; ++sp) s += P[(long)sp * g.pstride];
+    // summed in split order
+    const double s =
+        ordered_sum(g.partial + (long)b * g.splits * g.pstride + i + (long)j * g.pld, g.pstride, g.splits);
     double* c = C + i + (long)j * g.ldc;
     const double v = g.alpha * s;
     *c = (g.beta == 0.0) ? v : v + g.beta * *c;
@@ -496,8 +503,7 @@ __global__ __launch_bounds__(256) void k_tsmt_reduce(TsArgs a) {
   double* C = a.C[b];
   for (int e = blockIdx.x * 256 + threadIdx.x; e < m * 8; e += gridDim.x * 256) {
     const int i = e >> 3, c = e & 7;
-    double s = 0.0;
-    for (int q = 0; q < a.nchunk; ++q) s += a.partial[(((long)b * a.nchunk + q) * a.mmax + i) * 8 + c];
+    const double s = ordered_sum(a.partial + ((long)b * a.nchunk * a.mmax + i) * 8 + c, (long)a.mmax * 8, a.nchunk);
     const long ldc = a.ldcb ? a.ldcb[b] : a.ldc;
     C[i + (long)c * ldc] = a.alpha * s;
   }
@@ -861,8 +867,7 @@ __global__ __launch_bounds__(256) void k_coldot_reduce(ColDotArgs a) {
   const int b = blockIdx.x;
   const int nc = a.ncol ? a.ncol[b] : a.ncol0;
   for (int c = threadIdx.x; c < nc; c += 256) {
-    double s = 0.0;
-    for (int q = 0; q < a.nchunk; ++q) s += a.partial[((long)b * a.maxcol + c) * a.nchunk + q];
+    const double s = ordered_sum(a.partial + ((long)b * a.maxcol + c) * a.nchunk, 1, a.nchunk);
     (a.out ? a.out[b] : a.out1)[c] = (a.mode == 1) ? sqrt(s) : s;
   }
 }
