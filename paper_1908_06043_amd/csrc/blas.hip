@@ -446,9 +446,15 @@ __global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
   const double* V = a.V[b];
   const double* X = a.X[b];
   const int tid = threadIdx.x;
+  // loads from clamped indices, issued unconditionally through the global address space
+  // (flat loads would also wait on the LDS counter), zeroed where they lie outside
+  typedef __attribute__((address_space(1))) const double gcd;
+  const gcd* Xg = (const gcd*)X;
+  const gcd* Vg = (const gcd*)V;
   for (int e = tid; e < kTsRows * 8; e += 256) {
     const int r = e % kTsRows, c = e / kTsRows;
-    sX[r][c] = (r0 + r < n) ? X[r0 + r + (long)c * a.ldx] : 0.0;
+    const double x = Xg[min(r0 + r, n - 1) + (long)c * a.ldx];
+    sX[r][c] = (r0 + r < n) ? x : 0.0;
   }
   const int i = tid & 63, rg = tid >> 6;
   double acc[8];
@@ -462,16 +468,17 @@ __global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int e = tid + 256 * j, r = e & 63, ii = e >> 6;
-      vn[j] = (rs + r < n && i0 + ii < m) ? V[rs + r + (long)(i0 + ii) * a.ldv] : 0.0;
+      vn[j] = Vg[min(rs + r, n - 1) + (long)min(i0 + ii, m - 1) * a.ldv];
     }
   };
   load_v(0);
   for (int st = 0; st < kTsRows / 64; ++st) {
     __syncthreads();
+    const int rs = r0 + 64 * st;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int e = tid + 256 * j;
-      sV[e & 63][e >> 6] = vn[j];
+      const int e = tid + 256 * j, r = e & 63, ii = e >> 6;
+      sV[r][ii] = ((rs + r < n) & (i0 + ii < m)) ? vn[j] : 0.0;
     }
     if (st + 1 < kTsRows / 64) load_v(st + 1);
     __syncthreads();
