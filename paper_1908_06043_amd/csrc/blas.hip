@@ -38,8 +38,10 @@ constexpr int GK = 16;   // K chunk
 
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256, 4) void k_gemm(GemmArgs g) {
-  __shared__ double sA[2][GK][GT + 2];
-  __shared__ double sB[2][GK][GT + 2];
+  // row stride GT + 1 (odd): the staging stores along k (16 lanes a quarter-wave) hit
+  // 16 different banks
+  __shared__ double sA[2][GK][GT + 1];
+  __shared__ double sB[2][GK][GT + 1];
   const int zb = blockIdx.z;
   const int b = zb / g.splits, sp = zb % g.splits;
   const int m = g.m ? g.m[b] : g.m0;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256) void k_skinny_mfma(int n, const double* __rest
                                                      long ldx, double* __restrict__ P, int pcols,
                                                      int c_off) {
   constexpr int NB = (NC + 15) / 16;  // 16-column blocks
-  constexpr int SP = NC + 2;          // LDS row stride (doubles)
+  constexpr int SP = NC | 1;          // LDS row stride (doubles), odd: conflict-free staging
   constexpr int NS = kSkinnyKc / 4;   // k-steps per chunk
   constexpr int PF = 16;              // loads of M in flight per lane
   __shared__ double sh[kSkinnyKc * SP];
@@ -534,20 +536,23 @@ void tsmt_launch(TsArgs a, int batch, int mmax, hipStream_t st) {
 // (lane g takes k = g mod 4, for all eight outputs), so a wavefront reads 16 rows
 // of four different columns per load (four 128-byte segments, none repeated) and
 // the four partial sums of a row meet through lane shuffles.
+// Coefficient rows sit kTsmmLd = 9 doubles apart: the four rows a quarter-wave reads
+// at once (k = g mod 4) then fall in different banks, as do the staging stores.
+constexpr int kTsmmLd = 9;
 __global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
-  extern __shared__ double sC[];  // [m1 + m2][8]
+  extern __shared__ double sC[];  // [m1 + m2][kTsmmLd]
   const int b = blockIdx.y, tid = threadIdx.x;
   const int m1 = a.m[b], m2 = a.m2 ? a.m2[b] : 0;
   const double* C1 = a.C[b];
   for (int e = tid; e < m1 * 8; e += 256) {
     const int k = e % m1, c = e / m1;
-    sC[k * 8 + c] = C1[k + (long)c * a.ldc];
+    sC[k * kTsmmLd + c] = C1[k + (long)c * a.ldc];
   }
   if (m2 > 0) {
     const double* C2 = a.C2[b];
     for (int e = tid; e < m2 * 8; e += 256) {
       const int k = e % m2, c = e / m2;
-      sC[(m1 + k) * 8 + c] = C2[k + (long)c * a.ldc2];
+      sC[(m1 + k) * kTsmmLd + c] = C2[k + (long)c * a.ldc2];
     }
   }
   __syncthreads();
@@ -566,20 +571,20 @@ __global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
       for (int u = 0; u < 4; ++u) v[u] = Vb[(long)(k + 4 * u) * ldv];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const double* cr = sCb + (k + 4 * u) * 8;
+        const double* cr = sCb + (k + 4 * u) * kTsmmLd;
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc[c] += v[u] * cr[c];
       }
     }
     for (; k < mb; k += 4) {
       const double v = Vb[(long)k * ldv];
-      const double* cr = sCb + k * 8;
+      const double* cr = sCb + k * kTsmmLd;
 #pragma unroll
       for (int c = 0; c < 8; ++c) acc[c] += v * cr[c];
     }
   };
   run(a.V[b] + rc, a.ldv, sC, m1);
-  if (m2 > 0) run(a.V2[b] + rc, a.ldv2, sC + m1 * 8, m2);
+  if (m2 > 0) run(a.V2[b] + rc, a.ldv2, sC + m1 * kTsmmLd, m2);
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     acc[c] += __shfl_xor(acc[c], 1);
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(256) void k_tsmm(TsArgs a) {
 
 void tsmm_launch(TsArgs a, int batch, int mtot_max, hipStream_t st) {
   if (batch <= 0) return;
-  const size_t lds = (size_t)std::max(mtot_max, 1) * 8 * sizeof(double);
+  const size_t lds = (size_t)std::max(mtot_max, 1) * kTsmmLd * sizeof(double);
   SL_CHECK_ARG(lds <= kTsmmMaxLds, "tall-skinny product: too many basis columns");
   static std::once_flag attr;
   std::call_once(attr, [] {

@@ -189,7 +189,9 @@ __device__ __forceinline__ bool wait_expired(const WaitBound& wb, unsigned& poll
 // one of the block), so the waiting workgroups do not stream the whole block from
 // the coherence point on every poll; the block is then loaded and checked in full
 // (other lanes' stores may still be on their way).
-constexpr int kLdx = SB + 4;  // LDS column stride of a vector block (bank spread)
+// LDS column stride of a vector block: odd, so the 16 rows of one column that a
+// quarter-wave reads as an MFMA operand fall in 16 different banks
+constexpr int kLdx = SB + 1;
 
 __device__ __forceinline__ void poll_block(double* sx, const double* B, long ldb, int nrhs,
                                            int rows, const WaitBound& wb) {
