@@ -453,10 +453,14 @@ __global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
   typedef __attribute__((address_space(1))) const double gcd;
   const gcd* Xg = (const gcd*)X;
   const gcd* Vg = (const gcd*)V;
-  for (int e = tid; e < kTsRows * 8; e += 256) {
-    const int r = e % kTsRows, c = e / kTsRows;
-    const double x = Xg[min(r0 + r, n - 1) + (long)c * a.ldx];
-    sX[r][c] = (r0 + r < n) ? x : 0.0;
+  // the X slice: every load issued before any store (a rolled load / wait / store loop
+  // made one memory round trip per element a thread stages)
+  constexpr int XE = kTsRows * 8 / 256;
+  double xv[XE];
+#pragma unroll
+  for (int u = 0; u < XE; ++u) {
+    const int e = tid + 256 * u, r = e % kTsRows, c = e / kTsRows;
+    xv[u] = Xg[min(r0 + r, n - 1) + (long)c * a.ldx];
   }
   const int i = tid & 63, rg = tid >> 6;
   double acc[8];
@@ -474,6 +478,11 @@ __global__ __launch_bounds__(256) void k_tsmt(TsArgs a) {
     }
   };
   load_v(0);
+#pragma unroll
+  for (int u = 0; u < XE; ++u) {
+    const int e = tid + 256 * u, r = e % kTsRows, c = e / kTsRows;
+    sX[r][c] = (r0 + r < n) ? xv[u] : 0.0;
+  }
   for (int st = 0; st < kTsRows / 64; ++st) {
     __syncthreads();
     const int rs = r0 + 64 * st;
